@@ -1,0 +1,691 @@
+/*
+ * FP64 oracle for one DPD time step of fluid particles and frozen wall
+ * particles with phase-field bounce-back at the phi = 0 level set
+ * (Xu & Meakin, "A phase field approach to no slip boundary conditions in
+ * dissipative particle dynamics ...").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  It shares no
+ * code, header, table or helper with the GPU library.
+ *
+ * Plain and slow on purpose: per-particle loops over all candidates, FP64
+ * physics, no blocking, no fusion.  Where a floating-point comparison decides
+ * an integer (the cell of a particle, whether a pair is within the cutoff,
+ * whether a particle crossed phi = 0) the decision is taken in the precision
+ * the GPU kernels use, FP32 (or FP64 for an FP64 phi grid), with the op
+ * order written out below and no contraction (-ffp-contract=off), so that
+ * both sides take the same discrete decisions from the same FP32 inputs.
+ *
+ * Readings of the paper taken here (each is listed with its reason in the
+ * design notes):
+ *   - random force sigma*w*xi/sqrt(dt) (Groot-Warren discretisation of Eq. 7)
+ *   - modified velocity-Verlet of Groot & Warren with parameter lambda
+ *   - d = sqrt(2)eps*atanh(phi) (Eq. 16 prints tanh; Sec. II.C uses atanh)
+ *   - Eq. 17 with the start-of-step velocity v^t as printed; if the mirrored
+ *     point is still in the solid the particle returns to r^t
+ *   - after a bounce v = -v^t and the predicted velocity is -v^t as well
+ *   - atanh arguments clamped to [0, 1 - 2^-20]
+ *   - mass 1, box periodic in all three axes, phi grid periodic and
+ *     node-centred, trilinear interpolation ("linear interpolation", Sec. II.C)
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_PI 3.14159265358979323846
+
+/* ------------------------------------------------------------------------
+ * Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
+ * easy as 1, 2, 3", SC'11): ten rounds of two 32x32->64 multiplies by
+ * 0xD2511F53 and 0xCD9E8D57 with a Weyl key schedule 0x9E3779B9, 0xBB67AE85.
+ * ---------------------------------------------------------------------- */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t y0 = hi1 ^ x1 ^ k0;
+        uint32_t y2 = hi0 ^ x3 ^ k1;
+        x0 = y0;
+        x1 = lo1;
+        x2 = y2;
+        x3 = lo0;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Pair-symmetric Gaussian xi_ij of Eq. 7 for force evaluation k: the Philox
+ * counter is (min gid, max gid, k low word, k bits 32..47 | replica << 16),
+ * the key the 64-bit seed.  Box-Muller (1958) on u1 = (x0>>9 + 1/2) 2^-23 in
+ * (0,1) and u2 = (x1>>9) 2^-23 in [0,1): xi = sqrt(-2 ln u1) cos(2 pi u2).
+ * Swapping i and j gives the same counter, hence xi_ij = xi_ji. */
+void orc_uniform_pair(uint64_t seed, uint32_t gi, uint32_t gj, uint64_t k,
+                      uint32_t replica, uint32_t out[4])
+{
+    uint32_t lo = gi < gj ? gi : gj;
+    uint32_t hi = gi < gj ? gj : gi;
+    uint32_t ctr[4] = {lo, hi, (uint32_t)k,
+                       ((uint32_t)(k >> 32) & 0xFFFFu) | (replica << 16)};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    orc_philox4x32_10(ctr, key, out);
+}
+
+double orc_xi(uint64_t seed, uint32_t gi, uint32_t gj, uint64_t k, uint32_t replica)
+{
+    uint32_t o[4];
+    orc_uniform_pair(seed, gi, gj, k, replica, o);
+    double u1 = ((double)(o[0] >> 9) + 0.5) * 0x1p-23;
+    double u2 = (double)(o[1] >> 9) * 0x1p-23;
+    return sqrt(-2.0 * log(u1)) * cos(2.0 * ORC_PI * u2);
+}
+
+/* xi for the pairs (gi, gj0 + m), m = 0..count-1, at evaluation k. */
+void orc_xi_fill(uint64_t seed, uint32_t gi, uint32_t gj0, int64_t count,
+                 uint64_t k, uint32_t replica, double *out)
+{
+    for (int64_t m = 0; m < count; ++m)
+        out[m] = orc_xi(seed, gi, gj0 + (uint32_t)m, k, replica);
+}
+
+/* ------------------------------------------------------------------------
+ * Geometry shared by every routine below.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    double L[3];        /* periodic box edges */
+    int32_t nc[3];      /* cells per axis, floor(L/rc) (>= 3) */
+    float L32[3];       /* (float)L */
+    float invw32[3];    /* (float)(nc/L): cell decision scale */
+    int32_t ng[3];      /* phi grid nodes per axis (x, y, z) */
+    double h[3];        /* phi grid spacing */
+    float inv_h32[3];   /* (float)(1/h) for the FP32 decision */
+    double inv_h64[3];  /* 1/h for the FP64 decision */
+    const double *phi64;  /* grid values as double, [nz][ny][nx] */
+    const float *phi32;   /* FP32 grid, or NULL when the grid is FP64 */
+} orc_geom;
+
+typedef struct {
+    double a[2][2];     /* a_ij by type (0 fluid, 1 wall), Eq. 4 */
+    double gamma;       /* Eq. 6 */
+    double kBT;         /* Eq. 8 */
+    double rc;          /* cutoff, Eq. 5 */
+    double dt;
+    double lambda;      /* Groot-Warren predictor weight */
+    double g[3];        /* body force on fluid particles */
+    uint64_t seed;
+    uint32_t replica;
+} orc_params;
+
+static int orc_mod(int a, int n)
+{
+    int m = a % n;
+    return m < 0 ? m + n : m;
+}
+
+/* Cell coordinate of an FP32 coordinate: floor(fl(x * invw)) clamped to
+ * [0, n-1]. */
+static int cell_coord(float x, float invw, int n)
+{
+    float g = x * invw;
+    float fg = floorf(g);
+    int c;
+    if (fg < 0.0f) c = 0;
+    else if (fg > (float)(n - 1)) c = n - 1;
+    else c = (int)fg;
+    return c;
+}
+
+int32_t orc_cell_of(const orc_geom *G, const float x[3])
+{
+    int cx = cell_coord(x[0], G->invw32[0], G->nc[0]);
+    int cy = cell_coord(x[1], G->invw32[1], G->nc[1]);
+    int cz = cell_coord(x[2], G->invw32[2], G->nc[2]);
+    return (cz * G->nc[1] + cy) * G->nc[0] + cx;
+}
+
+/* FP32 periodic wrap by a single box edge; returns the image shift applied. */
+static int wrap32(float *x, float L)
+{
+    if (*x >= L) { *x = *x - L; return -1; }
+    if (*x < 0.0f) { *x = *x + L; return 1; }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Phase field at a point (Sec. II.C: phi_i by linear interpolation of the
+ * finite-difference grid; trilinear in 3-D).  Nodes at (i h_x, j h_y, k h_z),
+ * periodic.  The decision forms follow lerp(a, b, t) = a + t (b - a): four
+ * lerps along x, two along y, one along z.
+ * ---------------------------------------------------------------------- */
+static float lerp32(float a, float b, float t) { return a + t * (b - a); }
+static double lerp64(double a, double b, double t) { return a + t * (b - a); }
+
+float orc_phi_decide32(const orc_geom *G, const float x[3])
+{
+    int i0[3], i1[3];
+    float t[3];
+    for (int k = 0; k < 3; ++k) {
+        float g = x[k] * G->inv_h32[k];
+        float fg = floorf(g);
+        t[k] = g - fg;
+        i0[k] = orc_mod((int)fg, G->ng[k]);
+        i1[k] = orc_mod(i0[k] + 1, G->ng[k]);
+    }
+    const float *p = G->phi32;
+    const int nx = G->ng[0], ny = G->ng[1];
+    float e[2][2];
+    for (int dz = 0; dz < 2; ++dz) {
+        int kz = dz ? i1[2] : i0[2];
+        for (int dy = 0; dy < 2; ++dy) {
+            int ky = dy ? i1[1] : i0[1];
+            const float *row = p + ((size_t)kz * ny + ky) * nx;
+            e[dz][dy] = lerp32(row[i0[0]], row[i1[0]], t[0]);
+        }
+    }
+    float y0 = lerp32(e[0][0], e[0][1], t[1]);
+    float y1 = lerp32(e[1][0], e[1][1], t[1]);
+    return lerp32(y0, y1, t[2]);
+}
+
+double orc_phi_decide64(const orc_geom *G, const float x32[3])
+{
+    int i0[3], i1[3];
+    double t[3];
+    for (int k = 0; k < 3; ++k) {
+        double g = (double)x32[k] * G->inv_h64[k];
+        double fg = floor(g);
+        t[k] = g - fg;
+        i0[k] = orc_mod((int)fg, G->ng[k]);
+        i1[k] = orc_mod(i0[k] + 1, G->ng[k]);
+    }
+    const double *p = G->phi64;
+    const int nx = G->ng[0], ny = G->ng[1];
+    double e[2][2];
+    for (int dz = 0; dz < 2; ++dz) {
+        int kz = dz ? i1[2] : i0[2];
+        for (int dy = 0; dy < 2; ++dy) {
+            int ky = dy ? i1[1] : i0[1];
+            const double *row = p + ((size_t)kz * ny + ky) * nx;
+            e[dz][dy] = lerp64(row[i0[0]], row[i1[0]], t[0]);
+        }
+    }
+    double y0 = lerp64(e[0][0], e[0][1], t[1]);
+    double y1 = lerp64(e[1][0], e[1][1], t[1]);
+    return lerp64(y0, y1, t[2]);
+}
+
+/* The phi < 0 test in the precision of the grid. */
+static int phi_negative(const orc_geom *G, const float x32[3])
+{
+    if (G->phi32) return orc_phi_decide32(G, x32) < 0.0f;
+    return orc_phi_decide64(G, x32) < 0.0;
+}
+
+/* Trilinear interpolant and its exact gradient in FP64 (physics form):
+ * Phi(x) = sum_{abc} phi_abc W_a(tx) W_b(ty) W_c(tz), W_0 = 1 - t, W_1 = t. */
+double orc_phi64(const orc_geom *G, const double x[3], double grad[3])
+{
+    int i[3][2];
+    double t[3];
+    for (int k = 0; k < 3; ++k) {
+        double g = x[k] / G->h[k];
+        double fg = floor(g);
+        t[k] = g - fg;
+        i[k][0] = orc_mod((int)fg, G->ng[k]);
+        i[k][1] = orc_mod(i[k][0] + 1, G->ng[k]);
+    }
+    const int nx = G->ng[0], ny = G->ng[1];
+    double val = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    for (int c = 0; c < 2; ++c) {
+        double wz = c ? t[2] : 1.0 - t[2], dwz = c ? 1.0 : -1.0;
+        for (int b = 0; b < 2; ++b) {
+            double wy = b ? t[1] : 1.0 - t[1], dwy = b ? 1.0 : -1.0;
+            for (int a = 0; a < 2; ++a) {
+                double wx = a ? t[0] : 1.0 - t[0], dwx = a ? 1.0 : -1.0;
+                double p = G->phi64[((size_t)i[2][c] * ny + i[1][b]) * nx + i[0][a]];
+                val += p * wx * wy * wz;
+                gx += p * dwx * wy * wz;
+                gy += p * wx * dwy * wz;
+                gz += p * wx * wy * dwz;
+            }
+        }
+    }
+    if (grad) {
+        grad[0] = gx / G->h[0];
+        grad[1] = gy / G->h[1];
+        grad[2] = gz / G->h[2];
+    }
+    return val;
+}
+
+/* ------------------------------------------------------------------------
+ * Pair force F_ij = (F^C + F^D + F^R) along e = d/r, d = r_i - r_j
+ * (Eq. 3-10 with w_C = w_R = w, w_D = w^2, w = 1 - r/rc, sigma^2 = 2 gamma kBT):
+ *   F_ij = [ a_ij w - gamma w^2 (e . (vt_i - vt_j)) + sigma w xi_ij / sqrt(dt) ] e
+ * Zero for r >= rc (Eq. 5) and for r = 0.
+ * ---------------------------------------------------------------------- */
+static void pair_force(const orc_params *P, double sigma, double inv_sqrt_dt,
+                       const double d[3], const double dv[3], int ti, int tj,
+                       uint32_t gi, uint32_t gj, uint64_t k, double out[3])
+{
+    double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    double w = 1.0 - r / P->rc;
+    if (r == 0.0 || w <= 0.0) {
+        out[0] = out[1] = out[2] = 0.0;
+        return;
+    }
+    double e[3] = {d[0] / r, d[1] / r, d[2] / r};
+    double edv = e[0] * dv[0] + e[1] * dv[1] + e[2] * dv[2];
+    double xi = orc_xi(P->seed, gi, gj, k, P->replica);
+    double mag = P->a[ti][tj] * w - P->gamma * w * w * edv + sigma * w * xi * inv_sqrt_dt;
+    out[0] = mag * e[0];
+    out[1] = mag * e[1];
+    out[2] = mag * e[2];
+}
+
+/* Cells of the FP32 shadow positions and a per-cell member list in particle
+ * index order (plain counting sort). */
+typedef struct {
+    int32_t *cell;    /* n */
+    int32_t *start;   /* ncell + 1 */
+    int32_t *list;    /* n */
+} orc_cells;
+
+static int build_cells(const orc_geom *G, int64_t n, const float *xs, orc_cells *C)
+{
+    int64_t ncell = (int64_t)G->nc[0] * G->nc[1] * G->nc[2];
+    C->cell = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    C->start = (int32_t *)calloc((size_t)ncell + 1, sizeof(int32_t));
+    C->list = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *fill = (int32_t *)calloc((size_t)ncell, sizeof(int32_t));
+    if (!C->cell || !C->start || !C->list || !fill) return -1;
+    for (int64_t p = 0; p < n; ++p) {
+        C->cell[p] = orc_cell_of(G, xs + 3 * p);
+        C->start[C->cell[p] + 1] += 1;
+    }
+    for (int64_t c = 0; c < ncell; ++c) C->start[c + 1] += C->start[c];
+    for (int64_t p = 0; p < n; ++p) {
+        int32_t c = C->cell[p];
+        C->list[C->start[c] + fill[c]++] = (int32_t)p;
+    }
+    free(fill);
+    return 0;
+}
+
+static void free_cells(orc_cells *C)
+{
+    free(C->cell); free(C->start); free(C->list);
+}
+
+/* FP32 pair decision on shadow positions: with j seen from i's neighbour
+ * cell at image shift s (per axis -1, 0, +1),
+ *   dx = fl(x_i - fl(x_j + s L)),  r2 = fl(fl(fl(dx^2) + fl(dy^2)) + fl(dz^2)),
+ * and the pair is in range iff r2 < fl32(rc^2). */
+static int pair_in_range32(const orc_geom *G, const float *xi, const float *xj,
+                           const int s[3], float rc2)
+{
+    float dx = xi[0] - (xj[0] + (float)s[0] * G->L32[0]);
+    float dy = xi[1] - (xj[1] + (float)s[1] * G->L32[1]);
+    float dz = xi[2] - (xj[2] + (float)s[2] * G->L32[2]);
+    float r2 = dx * dx + dy * dy;
+    r2 = r2 + dz * dz;
+    return r2 < rc2;
+}
+
+/* Image shift of neighbour cell coordinate c + o, o in {-1, 0, 1}. */
+static int cell_shift(int c, int o, int n, int *wrapped)
+{
+    int q = c + o;
+    if (q < 0) { *wrapped = q + n; return -1; }
+    if (q >= n) { *wrapped = q - n; return 1; }
+    *wrapped = q;
+    return 0;
+}
+
+/*
+ * Forces at the current state (Eq. 2: f_i = sum_{j != i, r_ij < rc} F_ij,
+ * plus the body force g on fluid particles).
+ *   mode 0: brute force O(N^2), minimum image, FP64 cutoff test r < rc
+ *   mode 1: brute force O(N^2), FP32 decision with the cell-derived image
+ *   mode 2: cell list (27 neighbour cells), FP32 decision
+ * Modes 1 and 2 visit exactly the same pairs.  Wall particles are frozen,
+ * so wall-wall pairs are skipped; with all_particles = 0 only fluid forces
+ * are computed (wall rows left zero), with 1 walls get their forces too.
+ */
+int orc_forces(const orc_geom *G, const orc_params *P, int64_t n,
+               const double *r, const double *vt, const float *xs,
+               const int32_t *type, const uint32_t *gid, uint64_t k,
+               int mode, int all_particles, double *f)
+{
+    const double sigma = sqrt(2.0 * P->gamma * P->kBT);
+    const double inv_sqrt_dt = 1.0 / sqrt(P->dt);
+    const float rc2 = (float)(P->rc * P->rc);
+    orc_cells C;
+    memset(&C, 0, sizeof C);
+    if (mode != 0 && build_cells(G, n, xs, &C) != 0) return -1;
+    const int64_t ncx = G->nc[0], ncy = G->nc[1];
+
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        double acc[3] = {0.0, 0.0, 0.0};
+        if (type[i] != 0 && !all_particles) {
+            f[3 * i] = f[3 * i + 1] = f[3 * i + 2] = 0.0;
+            continue;
+        }
+        if (mode == 2) {
+            int cx = (int)(C.cell[i] % ncx);
+            int cy = (int)((C.cell[i] / ncx) % ncy);
+            int cz = (int)(C.cell[i] / (ncx * ncy));
+            for (int oz = -1; oz <= 1; ++oz)
+            for (int oy = -1; oy <= 1; ++oy)
+            for (int ox = -1; ox <= 1; ++ox) {
+                int wx, wy, wz, s[3];
+                s[0] = cell_shift(cx, ox, G->nc[0], &wx);
+                s[1] = cell_shift(cy, oy, G->nc[1], &wy);
+                s[2] = cell_shift(cz, oz, G->nc[2], &wz);
+                int64_t c = ((int64_t)wz * ncy + wy) * ncx + wx;
+                for (int32_t q = C.start[c]; q < C.start[c + 1]; ++q) {
+                    int64_t j = C.list[q];
+                    if (j == i || (type[i] != 0 && type[j] != 0)) continue;
+                    if (!pair_in_range32(G, xs + 3 * i, xs + 3 * j, s, rc2)) continue;
+                    double d[3], dv[3], F[3];
+                    for (int a = 0; a < 3; ++a) {
+                        d[a] = r[3 * i + a] - (r[3 * j + a] + s[a] * G->L[a]);
+                        dv[a] = vt[3 * i + a] - vt[3 * j + a];
+                    }
+                    pair_force(P, sigma, inv_sqrt_dt, d, dv, type[i], type[j],
+                               gid[i], gid[j], k, F);
+                    acc[0] += F[0]; acc[1] += F[1]; acc[2] += F[2];
+                }
+            }
+        } else {
+            for (int64_t j = 0; j < n; ++j) {
+                if (j == i || (type[i] != 0 && type[j] != 0)) continue;
+                double d[3], dv[3], F[3];
+                if (mode == 0) {
+                    for (int a = 0; a < 3; ++a) {
+                        double dd = r[3 * i + a] - r[3 * j + a];
+                        d[a] = dd - G->L[a] * nearbyint(dd / G->L[a]);
+                    }
+                    if (sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) >= P->rc) continue;
+                } else {
+                    /* the image follows from the two particles' cells */
+                    int s[3], ok = 1;
+                    int ci = C.cell[i], cj = C.cell[j];
+                    int cc_i[3] = {(int)(ci % ncx), (int)((ci / ncx) % ncy), (int)(ci / (ncx * ncy))};
+                    int cc_j[3] = {(int)(cj % ncx), (int)((cj / ncx) % ncy), (int)(cj / (ncx * ncy))};
+                    for (int a = 0; a < 3 && ok; ++a) {
+                        int found = 0;
+                        for (int o = -1; o <= 1; ++o) {
+                            int wq, sh = cell_shift(cc_i[a], o, G->nc[a], &wq);
+                            if (wq == cc_j[a]) { s[a] = sh; found = 1; break; }
+                        }
+                        ok = found;
+                    }
+                    if (!ok || !pair_in_range32(G, xs + 3 * i, xs + 3 * j, s, rc2)) continue;
+                    for (int a = 0; a < 3; ++a)
+                        d[a] = r[3 * i + a] - (r[3 * j + a] + s[a] * G->L[a]);
+                }
+                for (int a = 0; a < 3; ++a) dv[a] = vt[3 * i + a] - vt[3 * j + a];
+                pair_force(P, sigma, inv_sqrt_dt, d, dv, type[i], type[j],
+                           gid[i], gid[j], k, F);
+                acc[0] += F[0]; acc[1] += F[1]; acc[2] += F[2];
+            }
+        }
+        if (type[i] == 0) {
+            acc[0] += P->g[0]; acc[1] += P->g[1]; acc[2] += P->g[2];
+        }
+        f[3 * i] = acc[0]; f[3 * i + 1] = acc[1]; f[3 * i + 2] = acc[2];
+    }
+    if (mode != 0) free_cells(&C);
+    return 0;
+}
+
+/* Cells of the shadow positions (decision form). */
+void orc_cells_of(const orc_geom *G, int64_t n, const float *xs, int32_t *cell)
+{
+    for (int64_t p = 0; p < n; ++p) cell[p] = orc_cell_of(G, xs + 3 * p);
+}
+
+/* Interacting pairs (gid_i, gid_j) seen from every fluid i, FP32 decision
+ * on the shadow positions through the 27 neighbour cells.  Fluid-fluid
+ * pairs appear in both orders, fluid-wall pairs once.  Returns the count
+ * (pairs beyond cap are counted, not written), or -1. */
+int64_t orc_pairs(const orc_geom *G, const orc_params *P, int64_t n,
+                  const float *xs, const int32_t *type, const uint32_t *gid,
+                  uint32_t *out, int64_t cap)
+{
+    const float rc2 = (float)(P->rc * P->rc);
+    orc_cells C;
+    if (build_cells(G, n, xs, &C) != 0) return -1;
+    const int64_t ncx = G->nc[0], ncy = G->nc[1];
+    int64_t count = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (type[i] != 0) continue;
+        int cx = (int)(C.cell[i] % ncx);
+        int cy = (int)((C.cell[i] / ncx) % ncy);
+        int cz = (int)(C.cell[i] / (ncx * ncy));
+        for (int oz = -1; oz <= 1; ++oz)
+        for (int oy = -1; oy <= 1; ++oy)
+        for (int ox = -1; ox <= 1; ++ox) {
+            int wx, wy, wz, s[3];
+            s[0] = cell_shift(cx, ox, G->nc[0], &wx);
+            s[1] = cell_shift(cy, oy, G->nc[1], &wy);
+            s[2] = cell_shift(cz, oz, G->nc[2], &wz);
+            int64_t c = ((int64_t)wz * ncy + wy) * ncx + wx;
+            for (int32_t q = C.start[c]; q < C.start[c + 1]; ++q) {
+                int64_t j = C.list[q];
+                if (j == i) continue;
+                if (!pair_in_range32(G, xs + 3 * i, xs + 3 * j, s, rc2)) continue;
+                if (count < cap) {
+                    out[2 * count] = gid[i];
+                    out[2 * count + 1] = gid[j];
+                }
+                ++count;
+            }
+        }
+    }
+    free_cells(&C);
+    return count;
+}
+
+/* Decision form of the drift: w = fl(v + fl(dt/2 * f)), x* = fl(x + fl(dt * w)),
+ * then a single-box wrap.  Returns per-axis image shifts in s. */
+static void drift32(const orc_geom *G, const orc_params *P, const float x[3],
+                    const float v[3], const float f[3], float out[3], int s[3])
+{
+    const float hdt = (float)(0.5 * P->dt);
+    const float dt = (float)P->dt;
+    for (int a = 0; a < 3; ++a) {
+        float w = v[a] + hdt * f[a];
+        float y = x[a] + dt * w;
+        s[a] = wrap32(&y, G->L32[a]);
+        out[a] = y;
+    }
+}
+
+/*
+ * One step of the method for every fluid particle (walls frozen):
+ *   1. r* = r + dt v + dt^2/2 f,  vt = v + lambda dt f   (Groot-Warren)
+ *   2. if phi(r*) < 0: bounce back (Sec. II.C, Eq. 16-17):
+ *        c1 = atanh(-phi*), c0 = atanh(phi^t),  s = c1 / (c0 + c1)
+ *        r_bb = r* - 2 s dt v^t;  if phi(r_bb) < 0 then r_bb = r^t (code 2)
+ *        r = r_bb,  v = -v^t,  vt = -v^t  (code 1 or 2)
+ *   3. k += 1;  f' = forces(r, vt) with the random numbers of evaluation k
+ *   4. non-bounced particles: v = v + dt/2 (f + f');  f = f'
+ * Positions r, v, f are FP64 arrays of n*3; xs receives the FP32 shadow
+ * positions on which the discrete decisions were taken (x* for particles that
+ * did not bounce, fl32(r_bb) for those that did); events receives 0/1/2
+ * per particle.  The periodic wrap of r* follows the FP32 decision so that
+ * FP64 positions and shadows always name the same image.
+ */
+int orc_step(const orc_geom *G, const orc_params *P, int64_t n, double *r,
+             double *v, double *f, const int32_t *type, const uint32_t *gid,
+             uint64_t *k, int32_t *events, float *xs, int mode, double *scratch_vt)
+{
+    const double dt = P->dt;
+    const double delta = 0x1p-20;
+    double *vt = scratch_vt;
+    double *vold = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    double *fnew = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    if (!vold || !fnew) { free(vold); free(fnew); return -1; }
+
+    for (int64_t i = 0; i < n; ++i) {
+        events[i] = 0;
+        for (int a = 0; a < 3; ++a) vold[3 * i + a] = v[3 * i + a];
+        if (type[i] != 0) {
+            for (int a = 0; a < 3; ++a) {
+                vt[3 * i + a] = 0.0;
+                xs[3 * i + a] = (float)r[3 * i + a];
+            }
+            continue;
+        }
+        float x32[3], v32[3], f32[3], y32[3];
+        int s[3];
+        for (int a = 0; a < 3; ++a) {
+            x32[a] = (float)r[3 * i + a];
+            v32[a] = (float)v[3 * i + a];
+            f32[a] = (float)f[3 * i + a];
+        }
+        drift32(G, P, x32, v32, f32, y32, s);
+        double rs[3];
+        for (int a = 0; a < 3; ++a) {
+            rs[a] = r[3 * i + a] + dt * v[3 * i + a] + 0.5 * dt * dt * f[3 * i + a]
+                    + s[a] * G->L[a];
+            vt[3 * i + a] = v[3 * i + a] + P->lambda * dt * f[3 * i + a];
+        }
+        if (!phi_negative(G, y32)) {
+            for (int a = 0; a < 3; ++a) {
+                r[3 * i + a] = rs[a];
+                xs[3 * i + a] = y32[a];
+            }
+            continue;
+        }
+        /* bounce-back, Eq. 16-17 */
+        double rt[3] = {r[3 * i], r[3 * i + 1], r[3 * i + 2]};
+        double phis = orc_phi64(G, rs, NULL);
+        double phit = orc_phi64(G, rt, NULL);
+        double a1 = -phis, a0 = phit;
+        if (a1 < 0.0) a1 = 0.0;
+        if (a1 > 1.0 - delta) a1 = 1.0 - delta;
+        if (a0 < 0.0) a0 = 0.0;
+        if (a0 > 1.0 - delta) a0 = 1.0 - delta;
+        double c1 = atanh(a1), c0 = atanh(a0);
+        double sfrac = (c1 > 0.0) ? c1 / (c0 + c1) : 0.0;
+        double rbb[3];
+        float bb32[3];
+        for (int a = 0; a < 3; ++a) rbb[a] = rs[a] - 2.0 * sfrac * dt * v[3 * i + a];
+        for (int a = 0; a < 3; ++a) {
+            bb32[a] = (float)rbb[a];
+            int sh = wrap32(&bb32[a], G->L32[a]);
+            rbb[a] += sh * G->L[a];
+        }
+        int code = 1;
+        if (phi_negative(G, bb32)) {
+            code = 2;
+            for (int a = 0; a < 3; ++a) {
+                rbb[a] = rt[a];
+                bb32[a] = (float)rt[a];
+            }
+        }
+        events[i] = code;
+        for (int a = 0; a < 3; ++a) {
+            r[3 * i + a] = rbb[a];
+            xs[3 * i + a] = bb32[a];
+            vt[3 * i + a] = -v[3 * i + a];
+            v[3 * i + a] = -v[3 * i + a];
+        }
+    }
+
+    *k += 1;
+    int rc = orc_forces(G, P, n, r, vt, xs, type, gid, *k, mode, 0, fnew);
+    if (rc == 0) {
+        for (int64_t i = 0; i < n; ++i) {
+            if (type[i] != 0) continue;
+            for (int a = 0; a < 3; ++a) {
+                if (events[i] == 0)
+                    v[3 * i + a] = vold[3 * i + a] + 0.5 * dt * (f[3 * i + a] + fnew[3 * i + a]);
+                f[3 * i + a] = fnew[3 * i + a];
+            }
+        }
+    }
+    free(vold);
+    free(fnew);
+    return rc;
+}
+
+/* Conservative potential energy sum_{pairs} a_ij rc/2 (1 - r/rc)^2 (the
+ * potential of Eq. 4-5), brute force with minimum image; wall-wall pairs
+ * excluded (they are frozen and never interact). */
+double orc_potential(const orc_geom *G, const orc_params *P, int64_t n,
+                     const double *r, const int32_t *type)
+{
+    double U = 0.0;
+    #pragma omp parallel for reduction(+:U) schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t j = i + 1; j < n; ++j) {
+            if (type[i] != 0 && type[j] != 0) continue;
+            double d2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                double dd = r[3 * i + a] - r[3 * j + a];
+                dd -= G->L[a] * nearbyint(dd / G->L[a]);
+                d2 += dd * dd;
+            }
+            double rr = sqrt(d2);
+            if (rr < P->rc) {
+                double w = 1.0 - rr / P->rc;
+                U += 0.5 * P->a[type[i]][type[j]] * P->rc * w * w;
+            }
+        }
+    }
+    return U;
+}
+
+/* Binned fluid observables along one axis (Sec. III.A: density, temperature
+ * and stream velocity per bin): count, sum v_x, sum |v|^2 per bin. */
+void orc_profile(const orc_geom *G, int64_t n, const double *r, const double *v,
+                 const int32_t *type, int axis, int nbins, double *count,
+                 double *sum_vx, double *sum_v2, double *sum_v)
+{
+    for (int b = 0; b < nbins; ++b) {
+        count[b] = sum_vx[b] = sum_v2[b] = 0.0;
+        if (sum_v) sum_v[3 * b] = sum_v[3 * b + 1] = sum_v[3 * b + 2] = 0.0;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        if (type[i] != 0) continue;
+        double x = r[3 * i + axis];
+        x -= G->L[axis] * floor(x / G->L[axis]);
+        int b = (int)floor(x / G->L[axis] * nbins);
+        if (b < 0) b = 0;
+        if (b >= nbins) b = nbins - 1;
+        count[b] += 1.0;
+        sum_vx[b] += v[3 * i];
+        sum_v2[b] += v[3 * i] * v[3 * i] + v[3 * i + 1] * v[3 * i + 1] + v[3 * i + 2] * v[3 * i + 2];
+        if (sum_v) {
+            sum_v[3 * b] += v[3 * i];
+            sum_v[3 * b + 1] += v[3 * i + 1];
+            sum_v[3 * b + 2] += v[3 * i + 2];
+        }
+    }
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

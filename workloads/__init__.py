@@ -1,0 +1,473 @@
+"""Seeded synthetic inputs for the DPD step with phase-field no-slip walls.
+
+This module builds what a simulation starts from: the periodic box, the
+signed distance to the solid, the phase-field grid phi = tanh(d / width) of
+the equilibrium profile (Sec. II.B, Eq. 14, with sqrt(2)*eps = width), fluid
+particles where phi > 0 and frozen wall particles where phi < 0 (Sec. II.C),
+Maxwell velocities, and the DPD parameters of each workload.
+
+It holds none of the time step's arithmetic: no pair forces, no random
+numbers of the force, no integration, no interpolation of phi at a particle
+and no reflection.  Particles are classified against the grid by the minimum
+and maximum of the 8 grid nodes around them, which is a conservative test,
+not the method's interpolation.  Both the oracle-based tests and the GPU path
+take their inputs from here, so the two never share arithmetic.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import math
+
+import numpy as np
+
+__all__ = [
+    "System", "slab_system", "sinusoid_cylinder_system", "porous_system",
+    "sinusoid_slit_system", "replica_systems", "tiny_slab_system",
+    "corner_minmax", "maxwell_velocities", "bulk_system",
+]
+
+
+@dataclass
+class System:
+    """One periodic box of fluid + frozen wall particles and its phase field.
+
+    pos, vel: (N, 3) float32; type: (N,) int32 (0 fluid, 1 wall);
+    gid: (N,) uint32, a permutation of 0..N-1;
+    phi: (nz, ny, nx) grid of node values, node (i, j, k) at (i*h, j*h, k*h);
+    params: a (2x2 list: fluid-fluid, fluid-wall), gamma, kBT, rc, dt, lam,
+    g (3,), seed, replica.
+    """
+    name: str
+    L: np.ndarray
+    pos: np.ndarray
+    vel: np.ndarray
+    type: np.ndarray
+    gid: np.ndarray
+    phi: np.ndarray
+    h: np.ndarray
+    params: dict
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.pos.shape[0])
+
+    @property
+    def n_fluid(self) -> int:
+        return int(np.count_nonzero(self.type == 0))
+
+    @property
+    def n_wall(self) -> int:
+        return int(np.count_nonzero(self.type == 1))
+
+
+def default_params(a_ff=25.0, a_fs=25.0, gamma=4.5, kBT=1.0, rc=1.0, dt=0.01,
+                   lam=0.65, g=(0.0, 0.0, 0.0), seed=1234, replica=0) -> dict:
+    return dict(a=[[float(a_ff), float(a_fs)], [float(a_fs), float(a_fs)]],
+                gamma=float(gamma), kBT=float(kBT), rc=float(rc), dt=float(dt),
+                lam=float(lam), g=[float(x) for x in g], seed=int(seed),
+                replica=int(replica))
+
+
+# ----------------------------------------------------------------------------
+# geometry helpers
+# ----------------------------------------------------------------------------
+
+def _periodic_abs(x, period):
+    x = np.mod(x, period)
+    return np.minimum(x, period - x)
+
+
+def _slab_distance(z, lo, hi, Lz):
+    """Signed distance to a fluid slab lo < z < hi in a box periodic in z."""
+    z = np.mod(z, Lz)
+    dist = np.minimum(_periodic_abs(z - lo, Lz), _periodic_abs(z - hi, Lz))
+    inside = (z > lo) & (z < hi)
+    return np.where(inside, dist, -dist)
+
+
+def _sinusoid_distance(x, z, base, amp, period, iters=30):
+    """Unsigned distance from (x, z) to the curve z = base + amp*sin(2 pi x/period).
+
+    The nearest curve point is found by Newton's method on the squared
+    distance, started from the vertical projection; the curve's radius of
+    curvature (>= period^2 / (4 pi^2 |amp|)) is large against the distances
+    that matter here (phi = tanh(d/0.5) saturates beyond |d| ~ 5).
+    """
+    k = 2.0 * math.pi / period
+    x0 = np.asarray(x, dtype=np.float64)
+    z0 = np.asarray(z, dtype=np.float64)
+    t = x0.copy()
+    for _ in range(iters):
+        zc = base + amp * np.sin(k * t)
+        dz = amp * k * np.cos(k * t)
+        ddz = -amp * k * k * np.sin(k * t)
+        gfun = (t - x0) + (zc - z0) * dz
+        gpr = 1.0 + dz * dz + (zc - z0) * ddz
+        gpr = np.where(gpr > 0.1, gpr, 0.1)
+        t = t - gfun / gpr
+    zc = base + amp * np.sin(k * t)
+    return np.hypot(t - x0, zc - z0)
+
+
+def _grid_nodes(L, h):
+    n = np.rint(np.asarray(L) / np.asarray(h)).astype(np.int64)
+    if not np.allclose(n * np.asarray(h), L):
+        raise ValueError("box edges must be multiples of the grid spacing")
+    return n
+
+
+def _phi_from_distance(d, width, dtype):
+    return np.tanh(d / width).astype(dtype)
+
+
+def corner_minmax(grid, h, pos):
+    """Min and max of the 8 grid nodes of the grid cell holding each position.
+
+    grid is (nz, ny, nx) with node (i, j, k) at (i*hx, j*hy, k*hz), periodic.
+    Used only to classify generated particles conservatively.
+    """
+    nz, ny, nx = grid.shape
+    p = np.asarray(pos, dtype=np.float64)
+    i0 = np.floor(p[:, 0] / h[0]).astype(np.int64)
+    j0 = np.floor(p[:, 1] / h[1]).astype(np.int64)
+    k0 = np.floor(p[:, 2] / h[2]).astype(np.int64)
+    mn = np.full(p.shape[0], np.inf)
+    mx = np.full(p.shape[0], -np.inf)
+    for dk in (0, 1):
+        kk = np.mod(k0 + dk, nz)
+        for dj in (0, 1):
+            jj = np.mod(j0 + dj, ny)
+            for di in (0, 1):
+                ii = np.mod(i0 + di, nx)
+                v = grid[kk, jj, ii].astype(np.float64)
+                mn = np.minimum(mn, v)
+                mx = np.maximum(mx, v)
+    return mn, mx
+
+
+def maxwell_velocities(rng, n, kBT, mass=1.0):
+    """Gaussian velocities at temperature kBT with zero net momentum."""
+    v = rng.normal(0.0, math.sqrt(kBT / mass), size=(n, 3))
+    if n > 1:
+        v -= v.mean(axis=0, keepdims=True)
+    return v
+
+
+def _uniform_candidates(rng, L, rho):
+    n = int(round(rho * float(np.prod(L))))
+    return rng.random((n, 3)) * np.asarray(L)[None, :]
+
+
+def _fcc_lattice(L, rho):
+    """FCC lattice of number density ~rho whose unit cells tile the box."""
+    a = (4.0 / rho) ** (1.0 / 3.0)
+    n = np.maximum(1, np.rint(np.asarray(L) / a)).astype(np.int64)
+    ax = np.asarray(L) / n
+    base = np.array([[0, 0, 0], [0.5, 0.5, 0], [0.5, 0, 0.5], [0, 0.5, 0.5]])
+    g = np.stack(np.meshgrid(np.arange(n[0]), np.arange(n[1]), np.arange(n[2]),
+                             indexing="ij"), axis=-1).reshape(-1, 3)
+    pts = (g[:, None, :] + base[None, :, :]).reshape(-1, 3) * ax[None, :]
+    return pts + 0.25 * ax[None, :]
+
+
+def _assemble(name, L, fluid, wall, kBT, rng, phi, h, params, meta):
+    nf, nw = fluid.shape[0], wall.shape[0]
+    pos = np.concatenate([fluid, wall], axis=0)
+    pos = np.mod(pos, np.asarray(L)[None, :])
+    vel = np.zeros_like(pos)
+    vel[:nf] = maxwell_velocities(rng, nf, kBT)
+    typ = np.concatenate([np.zeros(nf, np.int32), np.ones(nw, np.int32)])
+    # gids are a seeded permutation so that gid order is not storage order
+    gid = rng.permutation(nf + nw).astype(np.uint32)
+    pos32 = pos.astype(np.float32)
+    # float32 rounding can land exactly on L; keep every coordinate in [0, L)
+    for k in range(3):
+        col = pos32[:, k]
+        col[col >= np.float32(L[k])] = np.float32(0.0)
+    meta = dict(meta)
+    meta.update(n_fluid=int(nf), n_wall=int(nw))
+    return System(name=name, L=np.asarray(L, dtype=np.float64), pos=pos32,
+                  vel=vel.astype(np.float32), type=typ, gid=gid, phi=phi,
+                  h=np.asarray(h, dtype=np.float64), params=params, meta=meta)
+
+
+def _classify(phi, h, pts, fluid=True):
+    """Conservative side test for particles whose analytic distance already
+    puts them on one side: fluid needs every surrounding node >= 0 (so the
+    interpolated phi cannot be negative), walls every node <= 0."""
+    mn, mx = corner_minmax(phi, h, pts)
+    if fluid:
+        return mn >= 0.0
+    return mx <= 0.0
+
+
+# ----------------------------------------------------------------------------
+# workloads
+# ----------------------------------------------------------------------------
+
+def slab_system(L=(10.0, 10.0, 10.0), wall=1.5, rho=3.0, h=0.25, width=0.5,
+                grid_dtype=np.float64, seed_fluid=0, seed_wall=1, params=None,
+                wall_fill="uniform", name="poiseuille_slit"):
+    """Plane channel: fluid slab wall < z < Lz - wall, walls elsewhere.
+
+    Plane Poiseuille workload: 10^3 box, density 3, 1.5-thick wall slabs at
+    each z end (which wrap into one 3-thick wall), phi = tanh(d/0.5) on a
+    0.25-spaced float64 grid.  Walls are random particles at the fluid
+    density (as in Sec. III.A, where randomly placed particles with phi < 0
+    become the solid); wall_fill="fcc" gives a jittered FCC lattice instead.
+    """
+    L = np.asarray(L, dtype=np.float64)
+    lo, hi = wall, L[2] - wall
+    n = _grid_nodes(L, (h, h, h))
+    zs = np.arange(n[2]) * h
+    d1 = _slab_distance(zs, lo, hi, L[2])
+    d = np.broadcast_to(d1[:, None, None], (n[2], n[1], n[0]))
+    phi = _phi_from_distance(np.ascontiguousarray(d), width, grid_dtype)
+    rng_f = np.random.default_rng(seed_fluid)
+    cand = _uniform_candidates(rng_f, L, rho)
+    dz = _slab_distance(cand[:, 2], lo, hi, L[2])
+    keep = (dz > 0) & _classify(phi, (h, h, h), cand, fluid=True)
+    fluid = cand[keep]
+    rng_w = np.random.default_rng(seed_wall)
+    if wall_fill == "fcc":
+        lat = _fcc_lattice(L, rho)
+        lat = lat[_slab_distance(lat[:, 2], lo, hi, L[2]) < 0]
+        jit = lat + rng_w.uniform(-0.1, 0.1, size=lat.shape)
+        ok = _slab_distance(jit[:, 2], lo, hi, L[2]) < 0
+        jit[~ok, 2] = lat[~ok, 2]
+        wallp = jit
+    else:
+        c = _uniform_candidates(rng_w, L, rho)
+        wallp = c[_slab_distance(c[:, 2], lo, hi, L[2]) < 0]
+    wallp = wallp[_classify(phi, (h, h, h), np.mod(wallp, L), fluid=False)]
+    params = params or default_params(g=(0.02, 0.0, 0.0))
+    rng_v = np.random.default_rng(seed_fluid + 1000)
+    return _assemble(name, L, fluid, wallp, params["kBT"], rng_v, phi,
+                     (h, h, h), params, dict(lo=lo, hi=hi, width=width))
+
+
+def tiny_slab_system(L=(4.0, 4.0, 6.0), wall=1.0, rho=3.0, seed=7, g=(0.05, 0, 0),
+                     grid_dtype=np.float32, **kw):
+    """A few hundred particles: small enough for O(N^2) checks."""
+    p = default_params(g=g, seed=seed, **kw)
+    return slab_system(L=L, wall=wall, rho=rho, grid_dtype=grid_dtype,
+                       seed_fluid=seed, seed_wall=seed + 1, params=p,
+                       wall_fill="uniform", name="tiny_slab")
+
+
+def _sin_cyl_distance(x, z, Lx, Lz, base, amp, period, radius, cx, cz):
+    """Signed distance (fluid > 0) for a channel between z_b = base + amp*sin
+    and its mirror z_t = Lz - z_b, periodic in z, minus an optional cylinder
+    of `radius` along y centred at (cx, cz)."""
+    x = np.asarray(x, dtype=np.float64)
+    z = np.mod(np.asarray(z, dtype=np.float64), Lz)
+    zb_c = np.mod(z - (base - Lz / 2), Lz) + (base - Lz / 2)
+    zt_c = np.mod(z - (Lz - base - Lz / 2), Lz) + (Lz - base - Lz / 2)
+    dist = np.minimum(_sinusoid_distance(x, zb_c, base, amp, period),
+                      _sinusoid_distance(x, zt_c, Lz - base, -amp, period))
+    zb = base + amp * np.sin(2 * math.pi * x / period)
+    inside = (z > zb) & (z < Lz - zb)
+    d = np.where(inside, dist, -dist)
+    if radius > 0:
+        dx = np.mod(x - cx + Lx / 2, Lx) - Lx / 2
+        d_cyl = np.hypot(dx, z - cz) - radius
+        d = np.minimum(d, d_cyl)
+    return d
+
+
+def sinusoid_cylinder_system(L=(40.0, 40.0, 80.0), rho=3.0, h=0.25, width=0.5,
+                             base=4.0, amp=2.0, radius=6.0, seed=10, params=None,
+                             grid_dtype=np.float32, wall_band=None,
+                             name="sinusoid_channel_cylinder"):
+    """Sinusoidal channel z = 4 + 2 sin(2 pi x/40) (mirrored at the top) with a
+    cylinder of radius 6 along y at the box centre; walls fill phi < 0."""
+    L = np.asarray(L, dtype=np.float64)
+    n = _grid_nodes(L, (h, h, h))
+    xs = np.arange(n[0]) * h
+    zs = np.arange(n[2]) * h
+    X, Z = np.meshgrid(xs, zs, indexing="xy")          # (nz, nx)
+    dxz = _sin_cyl_distance(X, Z, L[0], L[2], base, amp, L[0], radius,
+                            L[0] / 2, L[2] / 2)
+    d = np.broadcast_to(dxz[:, None, :], (n[2], n[1], n[0]))
+    phi = _phi_from_distance(np.ascontiguousarray(d), width, grid_dtype)
+    rng = np.random.default_rng(seed)
+    cand = _uniform_candidates(rng, L, rho)
+    dc = _sin_cyl_distance(cand[:, 0], cand[:, 2], L[0], L[2], base, amp, L[0],
+                           radius, L[0] / 2, L[2] / 2)
+    fl = (dc > 0) & _classify(phi, (h, h, h), cand, fluid=True)
+    wl = (dc < 0) & _classify(phi, (h, h, h), cand, fluid=False)
+    if wall_band is not None:
+        wl &= dc > -wall_band
+    params = params or default_params(g=(0.01, 0.0, 0.0), seed=seed)
+    return _assemble(name, L, cand[fl], cand[wl], params["kBT"], rng, phi,
+                     (h, h, h), params, dict(base=base, amp=amp, radius=radius))
+
+
+def sinusoid_slit_system(L=(20.0, 20.0, 20.0), rho=3.0, h=0.25, width=0.5,
+                         base=3.0, amp=2.0, wall_band=1.5, seed=40, params=None,
+                         grid_dtype=np.float32, name="sinusoid_slit"):
+    """Slit with sinusoidal walls z = 3 + 2 sin(2 pi x/20), mirrored at the
+    top, and a 1.5-thick band of wall particles (differentiation workload)."""
+    return sinusoid_cylinder_system(L=L, rho=rho, h=h, width=width, base=base,
+                                    amp=amp, radius=0.0, seed=seed,
+                                    params=params or default_params(g=(0.02, 0, 0), seed=seed),
+                                    grid_dtype=grid_dtype, wall_band=wall_band,
+                                    name=name)
+
+
+def gaussian_random_field(n, h, corr_len, rng, dtype=np.float32):
+    """Periodic Gaussian random field with covariance exp(-r^2 / (2 l^2)).
+
+    White noise on the grid filtered in Fourier space by exp(-k^2 l^2 / 4),
+    the square root of the Gaussian spectrum; normalised to unit variance.
+    """
+    import scipy.fft as sfft
+    noise = rng.standard_normal(size=tuple(n[::-1]), dtype=np.float32)
+    spec = sfft.rfftn(noise, workers=-1)
+    del noise
+    kz = 2 * np.pi * np.fft.fftfreq(n[2], d=h).astype(np.float32)
+    ky = 2 * np.pi * np.fft.fftfreq(n[1], d=h).astype(np.float32)
+    kx = 2 * np.pi * np.fft.rfftfreq(n[0], d=h).astype(np.float32)
+    c = np.float32(corr_len * corr_len / 4.0)
+    spec *= np.exp(-c * kz * kz)[:, None, None]
+    spec *= np.exp(-c * ky * ky)[None, :, None]
+    spec *= np.exp(-c * kx * kx)[None, None, :]
+    f = sfft.irfftn(spec, s=tuple(n[::-1]), workers=-1).astype(dtype, copy=False)
+    del spec
+    f -= f.mean()
+    f /= f.std()
+    return f
+
+
+def porous_system(Lbox=128.0, rho=4.0, h=0.25, width=0.5, corr_len=6.0,
+                  porosity=0.35, wall_band=1.5, seed_field=20, seed_particles=21,
+                  params=None, name=None):
+    """Porous medium: a thresholded Gaussian random field (correlation length
+    6) with fluid where the field is below its `porosity` quantile; wall
+    particles at the fluid density within `wall_band` of the interface.
+
+    The signed distance near the interface is (thr - f)/|grad f| (central
+    differences), clipped to +-3, where phi = tanh(d/0.5) is saturated.
+    """
+    L = np.array([Lbox, Lbox, Lbox], dtype=np.float64)
+    n = _grid_nodes(L, (h, h, h))
+    rng = np.random.default_rng(seed_field)
+    f = gaussian_random_field(n, h, corr_len, rng)
+    sample = f.reshape(-1)[:: max(1, f.size // 4_000_000)]
+    thr = np.float32(np.quantile(sample, porosity))
+    g2 = np.zeros_like(f)
+    for ax in range(3):
+        gax = (np.roll(f, -1, axis=ax) - np.roll(f, 1, axis=ax)) * np.float32(0.5 / h)
+        g2 += gax * gax
+        del gax
+    np.sqrt(g2, out=g2)
+    np.maximum(g2, np.float32(1e-6), out=g2)
+    d = (thr - f) / g2
+    del f, g2
+    np.clip(d, -3.0, 3.0, out=d)
+    phi = np.tanh(d * np.float32(1.0 / width)).astype(np.float32)
+    prng = np.random.default_rng(seed_particles)
+    cand = _uniform_candidates(prng, L, rho)
+    mn, mx = corner_minmax(phi, (h, h, h), cand)
+    fl = mn > 0.0
+    dmin, _ = corner_minmax(d, (h, h, h), cand)
+    wl = (mx < 0.0) & (dmin > -wall_band)
+    del d
+    params = params or default_params(a_ff=25.0, a_fs=35.0, g=(0.005, 0, 0),
+                                      seed=seed_particles)
+    return _assemble(name or f"porous_grf_{int(Lbox)}", L, cand[fl], cand[wl],
+                     params["kBT"], prng, phi, (h, h, h), params,
+                     dict(porosity=porosity, corr_len=corr_len, threshold=float(thr)))
+
+
+def replica_systems(count=256, seed=30, rho=3.0, h=0.25, width=0.5,
+                    edge_range=(8.0, 24.0)):
+    """Independent replica boxes of uneven size and geometry.
+
+    Edges are drawn per axis uniformly in edge_range and rounded to the grid
+    spacing; geometry is a slit (1.5-thick walls), a cylinder along y of
+    radius 3-10 (clipped to fit), or a pack of overlapping spheres of radius
+    1.5-3 added until the porosity drawn from [0.4, 0.6] is reached.  Each
+    replica has its own a in [15, 35], gamma in [3, 6] and g_x in
+    [0.005, 0.03]; walls fill phi < 0.
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for r in range(count):
+        L = np.round(rng.uniform(*edge_range, size=3) / h) * h
+        kind = int(rng.integers(0, 3))
+        a = float(rng.uniform(15, 35))
+        gamma = float(rng.uniform(3, 6))
+        gx = float(rng.uniform(0.005, 0.03))
+        p = default_params(a_ff=a, a_fs=a, gamma=gamma, g=(gx, 0, 0),
+                           seed=seed + 1 + r, replica=r)
+        out.append(_replica(r, L, kind, rng, rho, h, width, p))
+    return out
+
+
+def _replica(r, L, kind, rng, rho, h, width, params):
+    n = _grid_nodes(L, (h, h, h))
+    zs = np.arange(n[2]) * h
+    xs = np.arange(n[0]) * h
+    ys = np.arange(n[1]) * h
+    if kind == 0:
+        dfun = lambda p: _slab_distance(p[..., 2], 1.5, L[2] - 1.5, L[2])
+        meta = dict(kind="slit")
+    elif kind == 1:
+        rad = min(float(rng.uniform(3, 10)), min(L[0], L[2]) / 2 - 1.5)
+        cx, cz = L[0] / 2, L[2] / 2
+
+        def dfun(p, rad=rad, cx=cx, cz=cz):
+            dx = np.mod(p[..., 0] - cx + L[0] / 2, L[0]) - L[0] / 2
+            dz = np.mod(p[..., 2] - cz + L[2] / 2, L[2]) - L[2] / 2
+            return np.hypot(dx, dz) - rad
+        meta = dict(kind="cylinder", radius=rad)
+    else:
+        target = float(rng.uniform(0.4, 0.6))
+        centres, radii = [], []
+        Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+        nodes = np.stack([X, Y, Z], axis=-1)
+        solid = np.zeros(X.shape, dtype=bool)
+        while True:
+            c = rng.random(3) * L
+            rr = float(rng.uniform(1.5, 3.0))
+            dd = np.mod(nodes - c + L / 2, L) - L / 2
+            solid |= (dd * dd).sum(-1) < rr * rr
+            centres.append(c)
+            radii.append(rr)
+            if 1.0 - solid.mean() <= target or len(centres) > 2000:
+                break
+        centres_a = np.array(centres)
+        radii_a = np.array(radii)
+
+        def dfun(p, C=centres_a, R=radii_a):
+            flat = p.reshape(-1, 3)
+            best = np.full(flat.shape[0], np.inf)
+            for c, rr in zip(C, R):
+                dd = np.mod(flat - c + L / 2, L) - L / 2
+                best = np.minimum(best, np.sqrt((dd * dd).sum(-1)) - rr)
+            return best.reshape(p.shape[:-1])
+        meta = dict(kind="spheres", porosity_target=target, n_spheres=len(centres))
+    Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+    d = dfun(np.stack([X, Y, Z], axis=-1))
+    phi = _phi_from_distance(d, width, np.float32)
+    cand = _uniform_candidates(rng, L, rho)
+    dc = dfun(cand)
+    fl = (dc > 0) & _classify(phi, (h, h, h), cand, fluid=True)
+    wl = (dc < 0) & _classify(phi, (h, h, h), cand, fluid=False)
+    return _assemble(f"replica_{r}", L, cand[fl], cand[wl], params["kBT"], rng,
+                     phi, (h, h, h), params, meta)
+
+
+def bulk_system(L=(8.0, 8.0, 8.0), rho=3.0, h=0.5, seed=3, params=None,
+                grid_dtype=np.float32, name="bulk_periodic"):
+    """Fully periodic fluid with no walls (phi = +1 everywhere)."""
+    L = np.asarray(L, dtype=np.float64)
+    n = _grid_nodes(L, (h, h, h))
+    phi = np.ones((n[2], n[1], n[0]), dtype=grid_dtype)
+    rng = np.random.default_rng(seed)
+    cand = _uniform_candidates(rng, L, rho)
+    params = params or default_params(seed=seed)
+    return _assemble(name, L, cand, np.zeros((0, 3)), params["kBT"], rng, phi,
+                     (h, h, h), params, {})

@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Throughput of the DPD step with phase-field no-slip walls on one MI355X.
+
+One step = the whole hot path on one batch of synthetic particles: drift +
+phase-field bounce-back + binning, the counting-sort cell list, and the
+pairwise conservative + dissipative + random force with the velocity update
+(all in the library's HIP kernels).  Inputs are resident in HBM before the
+timed region; the timed region is exactly --steps steps between two stream
+synchronisations.  Prints one JSON line on stdout; progress goes to stderr.
+
+Default workload: porous medium (thresholded Gaussian random field,
+correlation length 6, porosity 0.35) in a 164^3 periodic box at density 4,
+phi on a 656^3 float32 grid, ~8.5M fluid + wall particles.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one lane-op per
+# lane per clock (no packed FP32, integer and FP32 alike).
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Per-unit VALU work of the pair-force kernel (lane-ops): an interacting pair
+# costs ~40 for the force, ~100 for Philox4x32-10 and ~20 for Box-Muller; a
+# candidate pair test ~10.
+OPS_PER_PAIR = 160
+OPS_PER_CANDIDATE = 10
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_workload(name):
+    import workloads
+    if name == "porous164":
+        return workloads.porous_system(Lbox=164.0, name="porous_grf_164")
+    if name == "porous128":
+        return workloads.porous_system(Lbox=128.0, name="porous_grf_128")
+    if name == "channel":
+        return workloads.sinusoid_cylinder_system()
+    if name == "slab":
+        return workloads.slab_system()
+    raise ValueError(name)
+
+
+def algorithmic_counts(sim, system):
+    """Interacting pairs (from the library's own pair count) and candidate
+    pairs (sum over fluid particles of the particles in their 27 cells)."""
+    import numpy as np
+    from paper_1807_09896_amd import binding
+    pairs = binding.dpd_neighbor_pairs(sim.ctx, None, 0)
+    st = sim.state()
+    cell = st["cell_of"].cpu().numpy()
+    typ = np.empty_like(system.type)
+    typ[system.gid] = system.type
+    L = system.L
+    rc = system.params["rc"]
+    nc = [int(math.floor(x / rc)) for x in L]
+    ncell = nc[0] * nc[1] * nc[2]
+    nf_c = np.bincount(cell[typ == 0], minlength=ncell).reshape(nc[2], nc[1], nc[0])
+    all_c = np.bincount(cell, minlength=ncell).reshape(nc[2], nc[1], nc[0]).astype(np.int64)
+    S = np.zeros_like(all_c)
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                S += np.roll(all_c, (dz, dy, dx), axis=(0, 1, 2))
+    cands = int((nf_c.astype(np.int64) * S).sum() - nf_c.sum())
+    return pairs, cands, ncell
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="porous164",
+                    choices=["porous164", "porous128", "channel", "slab"])
+    ap.add_argument("--timing-steps", type=int, default=20,
+                    help="steps of the per-kernel HIP-event pass")
+    ap.add_argument("--cpu-steps", type=int, default=2,
+                    help="oracle steps of the CPU baseline (0 skips it)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1807_09896_amd as dpd
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    system = make_workload(args.workload)
+    log("workload %s: %d particles (%d fluid, %d wall), phi %s %s, generated in %.1fs"
+        % (system.name, system.n, system.n_fluid, system.n_wall, system.phi.shape,
+           system.phi.dtype, time.time() - t0))
+    sim = dpd.Simulation(system)
+    cnt0 = sim.counters()
+    log("created:", cnt0)
+
+    sim.step(args.warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    sim.step(args.steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    sec = tb - ta
+    ms_per_step = sec * 1e3 / max(args.steps, 1)
+    value = system.n * args.steps / sec
+    log("timed %d steps: %.4f ms/step, %.4e particle-steps/s" % (args.steps, ms_per_step, value))
+
+    # per-kernel HIP events on the library stream
+    sim.kernel_times(1)
+    lk0 = sim.counters()
+    sim.step(args.timing_steps)
+    kt = sim.kernel_times(0)
+    lk1 = sim.counters()
+    for k, (ms, c) in kt.items():
+        if c:
+            log("  %-24s %9.4f ms/launch x %d" % (k, ms / c, c))
+    f_ms, f_n = kt["pair_force"]
+    force_ms = f_ms / max(f_n, 1)
+    pairs, cands, ncell = algorithmic_counts(sim, system)
+    lookups = (lk1["phi_lookups"] - lk0["phi_lookups"]) / max(args.timing_steps, 1)
+    ops = pairs * OPS_PER_PAIR + cands * OPS_PER_CANDIDATE
+    achieved_tops = ops / (force_ms * 1e-3) / 1e12
+    nf, nw = system.n_fluid, system.n_wall
+    b_alg = nf * (72 + 16 + 28 + 12 + 1) + 16 * nw + 8 * ncell + (
+        64 if system.phi.dtype == np.float64 else 32) * lookups
+    step_gbs = b_alg / (ms_per_step * 1e-3) / 1e9
+    log("pairs %d (%.2f per fluid), candidates %d, phi lookups/step %.0f, B_alg %.1f MB"
+        % (pairs, pairs / max(nf, 1), cands, lookups, b_alg / 1e6))
+
+    prof_dir = os.path.join(ROOT, "profiles")
+    traffic = None
+    tfile = os.path.join(prof_dir, "pair_force_%s_traffic.json" % args.workload)
+    if os.path.exists(tfile):
+        with open(tfile) as fh:
+            tr = json.load(fh)
+        if tr.get("kernel_source_hash") == kernel_source_hash():
+            traffic = tr.get("bytes_per_launch")
+
+    cpu = None
+    if args.cpu_steps > 0:
+        import oracle
+        oracle.build_oracle(force=False)
+        log("cpu baseline: oracle on %d threads, %d steps of the same workload"
+            % (oracle.num_threads(), args.cpu_steps))
+        o = oracle.Oracle(system)
+        tc = time.perf_counter()
+        o.step(args.cpu_steps)
+        tcs = time.perf_counter() - tc
+        cpu = {"value": system.n * args.cpu_steps / tcs, "unit": "particle-steps/s",
+               "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": "%d full steps of the same %d-particle workload (FP64 C oracle, "
+                         "OpenMP over particles), %.1f s" % (args.cpu_steps, system.n, tcs)}
+        log("cpu baseline %.4e particle-steps/s in %.1fs" % (cpu["value"], tcs))
+
+    out = {
+        "metric": "particle-steps/s",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": system.name, "particles": system.n, "fluid": nf, "wall": nw,
+                   "box": [float(x) for x in system.L], "density": 4.0 if "porous" in system.name else 3.0,
+                   "phi_grid": list(system.phi.shape), "phi_dtype": str(system.phi.dtype),
+                   "dt": system.params["dt"], "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "kernel": "pair_force", "achieved": achieved_tops,
+                     "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved_tops / VALU_PEAK_TOPS,
+                     "traffic": traffic, "avg_launch_ms": force_ms,
+                     "ops_per_launch": ops, "pairs": pairs, "candidates": cands},
+        "step_hbm": {"algorithmic_bytes": b_alg, "achieved_GBs": step_gbs,
+                     "peak_GBs": HBM_PEAK_GBS, "frac": step_gbs / HBM_PEAK_GBS},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    sim.close()
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("device.h", "kernels.hip"):
+        with open(os.path.join(ROOT, "paper_1807_09896_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+if __name__ == "__main__":
+    main()

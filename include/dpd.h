@@ -1,0 +1,226 @@
+/*
+ * dpd.h -- C ABI of the MI355X (gfx950) library for one DPD time step of
+ * fluid particles and frozen wall particles with phase-field bounce-back
+ * (Xu & Meakin, "A phase field approach to no slip boundary conditions in
+ * dissipative particle dynamics and other particle models for fluid flow in
+ * geometrically complex confined systems").
+ *
+ * Every entry point returns an int status: DPD_OK (0) or a negative DPD_E_*
+ * code; nothing throws or aborts across the ABI.  dpd_last_error() gives a
+ * message for the last failure of a context.  Errors detected on the device
+ * (non-finite state, a displacement above half a cell in one step) are
+ * latched in a device status word and returned by the next dpd_sync() or
+ * getter.  A context is used by one host thread at a time.
+ *
+ * Units: the cutoff rc is the length unit of the paper (Eq. 5) but is a
+ * parameter here; mass is 1.  The box is periodic along x, y and z.
+ *
+ * Memory: unless a struct says otherwise, pointers handed to the library
+ * are borrowed for the duration of the call.  Outputs are caller-owned
+ * device buffers written asynchronously on the context stream; they are
+ * valid once the stream has reached that point (dpd_sync() or any stream
+ * synchronisation).  Device memory of a context comes from the caller's
+ * allocator when one is given (e.g. PyTorch's caching allocator), from
+ * hipMalloc otherwise, and is released by dpd_destroy().
+ */
+#ifndef DPD_H
+#define DPD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    DPD_OK = 0,
+    DPD_E_INVAL = -1,     /* bad argument, shape or inconsistent input */
+    DPD_E_NOMEM = -2,     /* device allocation failed */
+    DPD_E_DEVICE = -3,    /* no usable gfx950 device, or a HIP runtime error */
+    DPD_E_UNSTABLE = -4,  /* non-finite state, or a particle moved > half a cell */
+    DPD_E_STATE = -5      /* call not valid in the current state */
+};
+
+enum {
+    DPD_TYPE_FLUID = 0,
+    DPD_TYPE_WALL = 1
+};
+
+/* params.flags */
+enum {
+    DPD_FLAG_NO_MASK = 1  /* test phi for every particle, not only in cells
+                             near the interface (results are identical) */
+};
+
+typedef struct dpd_ctx dpd_ctx;
+
+/* Periodic box [0, L[0]) x [0, L[1]) x [0, L[2]). */
+typedef struct {
+    double L[3];
+} dpd_box;
+
+/* Particles (Sec. II.A: positions r_i and velocities v_i, Eq. 1-2; Sec. II.C:
+ * fluid particles where phi > 0, frozen wall particles where phi <= 0).
+ *   n     number of particles, fluid and wall together
+ *   pos   n x 3 float32, row-major, each coordinate in [0, L)
+ *   vel   n x 3 float32 (rows of wall particles are ignored: walls are frozen)
+ *   type  n int32, DPD_TYPE_FLUID or DPD_TYPE_WALL
+ *   gid   n uint32, a permutation of 0..n-1 naming the particle in the
+ *         random-number counter and in every getter's row order; NULL means
+ *         gid = row index
+ *   on_device  nonzero when the four pointers are device memory */
+typedef struct {
+    int64_t n;
+    const float *pos;
+    const float *vel;
+    const int32_t *type;
+    const uint32_t *gid;
+    int32_t on_device;
+} dpd_particles;
+
+/* Phase field phi(x) on a periodic node-centred grid (Sec. II.B-C): node
+ * (i, j, k) sits at (i h[0], j h[1], k h[2]); n[d] h[d] must equal L[d].
+ * data holds n[2] x n[1] x n[0] values (x fastest) of dtype 4 (float32) or
+ * 8 (float64); -1 is solid, +1 fluid, the interface is phi = 0.  The grid is
+ * copied at create; the discrete phi < 0 test runs in the grid's precision. */
+typedef struct {
+    int32_t n[3];
+    double h[3];
+    int32_t dtype;
+    const void *data;
+    int32_t on_device;
+} dpd_phi_grid;
+
+/* DPD parameters (Eq. 4-10 and the Groot-Warren integrator).
+ *   a       2 x 2 conservative amplitudes a_ij by type, row-major
+ *           {a_ff, a_fw, a_wf, a_ww}; a_fw must equal a_wf; a_ww is unused
+ *           (wall-wall pairs never interact)
+ *   gamma   dissipative coefficient; sigma = sqrt(2 gamma kBT) (Eq. 8)
+ *   kBT     temperature
+ *   rc      cutoff; the box must hold at least 3 cells of width >= rc per axis
+ *   dt      time step (> 0)
+ *   lambda  predictor weight of the modified velocity-Verlet (0.65 typical,
+ *           0.5 is plain velocity-Verlet)
+ *   g       body force per fluid particle
+ *   seed    64-bit key of the random numbers
+ *   replica replica id entering the random-number counter (< 65536)
+ *   flags   DPD_FLAG_* */
+typedef struct {
+    double a[4];
+    double gamma;
+    double kBT;
+    double rc;
+    double dt;
+    double lambda;
+    double g[3];
+    uint64_t seed;
+    uint32_t replica;
+    int32_t flags;
+} dpd_params;
+
+/* Optional device allocator (e.g. PyTorch's caching allocator through the
+ * Python binding).  alloc returns device memory of at least `bytes` bytes
+ * aligned to 256 bytes, or NULL; free releases it.  Either may be called
+ * from any library call of the context, with the context stream. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *stream, void *user);
+    void (*free)(void *ptr, void *stream, void *user);
+    void *user;
+} dpd_allocator;
+
+/* Create a context on the current HIP device (Sec. II: the problem is the box,
+ * the particles, a_ij, gamma, kBT, rc, dt, the body force and the phase field).
+ * Validates the inputs (DPD_E_INVAL: shapes, non-finite values, box < 3 cells,
+ * asymmetric a, dt <= 0, gid not a permutation, a fluid particle with
+ * phi < 0, grid not matching the box), copies them to device memory, sorts
+ * the frozen wall particles into their cells once, marks the cells next to
+ * the interface, and computes the initial forces f(0) with random-number
+ * index k = 0.  hip_stream (a hipStream_t, NULL for the null stream) is the
+ * stream of every later call.  alloc may be NULL.  On success *out owns the
+ * context; on failure *out is NULL. */
+int dpd_create(const dpd_box *box, const dpd_particles *particles,
+               const dpd_params *params, const dpd_phi_grid *phi,
+               const dpd_allocator *alloc, void *hip_stream, dpd_ctx **out);
+
+/* Advance n >= 0 time steps, asynchronously on the context stream.  One step
+ * (Sec. II.A and II.C): the modified velocity-Verlet drift and prediction;
+ * for particles whose new position has phi < 0, bounce-back with the
+ * reflected position of Eq. 17 (or the start position if that is still in
+ * the solid) and v = -v^t; a counting-sort cell list of the new positions;
+ * the pairwise conservative + dissipative + random force (Eq. 3-10) with the
+ * pair-symmetric counter-based random number xi_ij(k); the velocity update. */
+int dpd_step(dpd_ctx *ctx, int64_t n);
+
+/* Forces f at the current state (the force carried into the next step, the
+ * sum of Eq. 2 plus the body force), written as n x 3 float32 rows in gid
+ * order to the device buffer f_out; wall rows are zero. */
+int dpd_forces(dpd_ctx *ctx, float *f_out);
+
+/* Current state in gid order, into device buffers; any pointer may be NULL.
+ *   pos     n x 3 float32 positions (walls: their fixed positions)
+ *   vel     n x 3 float32 velocities (walls: zero)
+ *   events  n int32: the last step's bounce-back code per particle,
+ *           0 none, 1 reflected by Eq. 17, 2 returned to the start position
+ *   cell_of n int32: cell index (cz * ncy + cy) * ncx + cx of the position,
+ *           cx = min(ncx - 1, floor(fl32(x * fl32(ncx / Lx)))) */
+int dpd_get_state(dpd_ctx *ctx, float *pos, float *vel, int32_t *events,
+                  int32_t *cell_of);
+
+/* Replace the fluid state: pos, vel, force are n x 3 float32 rows in gid
+ * order (wall rows are ignored; walls keep their positions), k the index of
+ * the random numbers the forces were evaluated with.  Host or device memory
+ * per on_device.  Positions must lie in [0, L) and satisfy phi >= 0. */
+int dpd_set_state(dpd_ctx *ctx, const float *pos, const float *vel,
+                  const float *force, uint64_t k, int32_t on_device);
+
+/* Interacting pairs at the current positions, as seen from each fluid
+ * particle i: every (gid_i, gid_j) with j != i in the 27 cells around i and
+ * fl32(dx^2 + dy^2 + dz^2) < fl32(rc^2) (dx = fl(x_i - fl(x_j + s L)), s the
+ * image shift of the neighbour cell).  Fluid-fluid pairs appear in both
+ * orders, fluid-wall pairs once.  pairs is a device buffer of cap x 2 uint32
+ * (unordered); *count (host) receives the total, which may exceed cap (only
+ * cap pairs are written then).  Synchronises the stream. */
+int dpd_neighbor_pairs(dpd_ctx *ctx, uint32_t *pairs, int64_t cap, int64_t *count);
+
+/* Binned fluid observables along `axis` (0, 1, 2) in nbins equal bins
+ * (Sec. III.A: density, temperature and stream velocity per bin), into the
+ * device buffer out of nbins x 5 float64: count, sum v_x, sum v_y, sum v_z,
+ * sum |v|^2. */
+int dpd_profile(dpd_ctx *ctx, int32_t axis, int32_t nbins, double *out);
+
+/* Counters since create, into host out[10]: steps, k, bounce-backs (code 1),
+ * returns to start (code 2), n_fluid, n_wall, cells, near-interface cells,
+ * phi evaluations at drifted positions (particles in near-interface cells),
+ * displacements above half a cell.  Synchronises the stream. */
+int dpd_counters(dpd_ctx *ctx, int64_t *out);
+
+/* Per-kernel timing with HIP events on the context stream.  enable = 1
+ * starts recording (dpd_step then times each kernel launch), 0 stops.
+ * When out is not NULL it receives, for the kernels named by
+ * dpd_kernel_name(0..DPD_NUM_KERNELS-1), the summed milliseconds in out_ms
+ * and the number of timed launches in out_launches.  Synchronises. */
+#define DPD_NUM_KERNELS 8
+int dpd_kernel_times(dpd_ctx *ctx, int32_t enable, double *out_ms, int64_t *out_launches);
+const char *dpd_kernel_name(int32_t i);
+
+/* Wait for the context stream and return any latched device error. */
+int dpd_sync(dpd_ctx *ctx);
+
+/* Message of the last failure of ctx (or of the last failed create when ctx
+ * is NULL); never NULL. */
+const char *dpd_last_error(const dpd_ctx *ctx);
+
+/* Release the context and its device memory (synchronises first). */
+void dpd_destroy(dpd_ctx *ctx);
+
+/* Device-to-device copy of `bytes` bytes by a plain streaming kernel (no
+ * library call), on hip_stream: the reference kernel of known traffic that
+ * hardware byte counters are calibrated against. */
+int dpd_copy_probe(void *dst, const void *src, size_t bytes, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DPD_H */

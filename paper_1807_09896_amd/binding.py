@@ -1,0 +1,281 @@
+"""ctypes binding of libdpdphi.so (include/dpd.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  Functions carry the C names; device buffers are torch tensors
+on the current HIP device and the library runs on torch's current stream.
+There is no CPU fallback: without the built library or a gfx950 device every
+call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdpdphi.so")
+
+DPD_OK = 0
+DPD_E_INVAL = -1
+DPD_E_NOMEM = -2
+DPD_E_DEVICE = -3
+DPD_E_UNSTABLE = -4
+DPD_E_STATE = -5
+DPD_FLAG_NO_MASK = 1
+DPD_NUM_KERNELS = 8
+
+_ERRNAMES = {DPD_E_INVAL: "DPD_E_INVAL", DPD_E_NOMEM: "DPD_E_NOMEM",
+             DPD_E_DEVICE: "DPD_E_DEVICE", DPD_E_UNSTABLE: "DPD_E_UNSTABLE",
+             DPD_E_STATE: "DPD_E_STATE"}
+
+# Every exported symbol declared in include/dpd.h.
+EXPORTED = ["dpd_create", "dpd_step", "dpd_forces", "dpd_get_state", "dpd_set_state",
+            "dpd_neighbor_pairs", "dpd_profile", "dpd_counters", "dpd_kernel_times",
+            "dpd_kernel_name", "dpd_sync", "dpd_last_error", "dpd_destroy", "dpd_copy_probe"]
+
+
+class DPDError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (_ERRNAMES.get(code, str(code)), msg))
+        self.code = code
+
+
+class dpd_box(C.Structure):
+    _fields_ = [("L", C.c_double * 3)]
+
+
+class dpd_particles(C.Structure):
+    _fields_ = [("n", C.c_int64), ("pos", C.c_void_p), ("vel", C.c_void_p),
+                ("type", C.c_void_p), ("gid", C.c_void_p), ("on_device", C.c_int32)]
+
+
+class dpd_phi_grid(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("h", C.c_double * 3), ("dtype", C.c_int32),
+                ("data", C.c_void_p), ("on_device", C.c_int32)]
+
+
+class dpd_params(C.Structure):
+    _fields_ = [("a", C.c_double * 4), ("gamma", C.c_double), ("kBT", C.c_double),
+                ("rc", C.c_double), ("dt", C.c_double), ("lambda_", C.c_double),
+                ("g", C.c_double * 3), ("seed", C.c_uint64), ("replica", C.c_uint32),
+                ("flags", C.c_int32)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class dpd_allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", C.c_void_p)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the built library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libdpdphi.so is not built (run __graft_entry__.build() or "
+                           "python -m paper_1807_09896_amd.build)")
+    L = C.CDLL(path)
+    P = C.c_void_p
+    L.dpd_create.argtypes = [P, P, P, P, P, P, C.POINTER(P)]
+    L.dpd_create.restype = C.c_int
+    L.dpd_step.argtypes = [P, C.c_int64]
+    L.dpd_step.restype = C.c_int
+    L.dpd_forces.argtypes = [P, P]
+    L.dpd_forces.restype = C.c_int
+    L.dpd_get_state.argtypes = [P, P, P, P, P]
+    L.dpd_get_state.restype = C.c_int
+    L.dpd_set_state.argtypes = [P, P, P, P, C.c_uint64, C.c_int32]
+    L.dpd_set_state.restype = C.c_int
+    L.dpd_neighbor_pairs.argtypes = [P, P, C.c_int64, C.POINTER(C.c_int64)]
+    L.dpd_neighbor_pairs.restype = C.c_int
+    L.dpd_profile.argtypes = [P, C.c_int32, C.c_int32, P]
+    L.dpd_profile.restype = C.c_int
+    L.dpd_counters.argtypes = [P, P]
+    L.dpd_counters.restype = C.c_int
+    L.dpd_kernel_times.argtypes = [P, C.c_int32, P, P]
+    L.dpd_kernel_times.restype = C.c_int
+    L.dpd_kernel_name.argtypes = [C.c_int32]
+    L.dpd_kernel_name.restype = C.c_char_p
+    L.dpd_sync.argtypes = [P]
+    L.dpd_sync.restype = C.c_int
+    L.dpd_last_error.argtypes = [P]
+    L.dpd_last_error.restype = C.c_char_p
+    L.dpd_destroy.argtypes = [P]
+    L.dpd_destroy.restype = None
+    L.dpd_copy_probe.argtypes = [P, P, C.c_size_t, P]
+    L.dpd_copy_probe.restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(rc, ctx=None):
+    if rc != DPD_OK:
+        msg = load_library().dpd_last_error(ctx).decode()
+        raise DPDError(rc, msg)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if hasattr(t, "data_ptr"):
+        return C.c_void_p(t.data_ptr())
+    return C.c_void_p(t.ctypes.data)
+
+
+class TorchAllocator:
+    """dpd_allocator backed by torch's caching allocator on one device."""
+
+    def __init__(self, device):
+        import torch
+        self._torch = torch
+        self.device = device
+        self.live = {}
+        self._alloc = ALLOC_FN(self._do_alloc)
+        self._free = FREE_FN(self._do_free)
+        self.struct = dpd_allocator(self._alloc, self._free, None)
+
+    def _do_alloc(self, nbytes, stream, user):
+        t = self._torch.empty(int(nbytes), dtype=self._torch.uint8, device=self.device)
+        p = t.data_ptr()
+        self.live[p] = t
+        return p
+
+    def _do_free(self, ptr, stream, user):
+        self.live.pop(int(ptr or 0), None)
+
+
+def _stream_handle(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+# ---------------------------------------------------------------------------
+# C-named entry points (thin marshalling)
+# ---------------------------------------------------------------------------
+
+def dpd_create(L, pos, vel, type_, gid, params, phi, h, stream=None, use_torch_allocator=True,
+               flags=0):
+    """Create a context from host numpy arrays (or device tensors).
+
+    params: dict with a (2x2), gamma, kBT, rc, dt, lam, g, seed, replica.
+    phi: (nz, ny, nx) float32/float64 array; h: grid spacing (3,).
+    Returns (ctx handle, keepalive) where keepalive must outlive the context.
+    """
+    import torch
+    lib = load_library()
+    if not torch.cuda.is_available():
+        raise DPDError(DPD_E_DEVICE, "no HIP device visible to torch")
+    on_dev = int(hasattr(pos, "data_ptr"))
+    n = int(pos.shape[0])
+    keep = []
+
+    def host(a, dt):
+        a = np.ascontiguousarray(a, dtype=dt)
+        keep.append(a)
+        return a
+
+    if on_dev:
+        ppos, pvel, ptyp = pos, vel, type_
+        pgid = gid
+    else:
+        ppos = host(pos, np.float32)
+        pvel = host(vel, np.float32)
+        ptyp = host(type_, np.int32)
+        pgid = host(gid, np.uint32) if gid is not None else None
+    parts = dpd_particles(n, _ptr(ppos), _ptr(pvel), _ptr(ptyp), _ptr(pgid), on_dev)
+    box = dpd_box((C.c_double * 3)(*[float(x) for x in L]))
+    phi_a = phi if hasattr(phi, "data_ptr") else np.ascontiguousarray(phi)
+    if not hasattr(phi, "data_ptr"):
+        keep.append(phi_a)
+    dt = 8 if phi_a.dtype in (np.float64,) or str(phi_a.dtype) == "torch.float64" else 4
+    nz, ny, nx = (int(x) for x in phi_a.shape)
+    grid = dpd_phi_grid((C.c_int32 * 3)(nx, ny, nz), (C.c_double * 3)(*[float(x) for x in h]),
+                        dt, _ptr(phi_a), int(hasattr(phi, "data_ptr")))
+    a = params["a"]
+    prm = dpd_params((C.c_double * 4)(a[0][0], a[0][1], a[1][0], a[1][1]), params["gamma"],
+                     params["kBT"], params["rc"], params["dt"], params["lam"],
+                     (C.c_double * 3)(*params["g"]),
+                     int(params["seed"]) & 0xFFFFFFFFFFFFFFFF, int(params["replica"]),
+                     int(flags))
+    alloc = None
+    if use_torch_allocator:
+        alloc = TorchAllocator(torch.device("cuda", torch.cuda.current_device()))
+        keep.append(alloc)
+    ctx = C.c_void_p()
+    rc = lib.dpd_create(C.byref(box), C.byref(parts), C.byref(prm), C.byref(grid),
+                        C.byref(alloc.struct) if alloc else None, _stream_handle(stream),
+                        C.byref(ctx))
+    _check(rc, None)
+    return ctx, keep
+
+
+def dpd_step(ctx, n):
+    _check(load_library().dpd_step(ctx, int(n)), ctx)
+
+
+def dpd_forces(ctx, f_out):
+    _check(load_library().dpd_forces(ctx, _ptr(f_out)), ctx)
+
+
+def dpd_get_state(ctx, pos=None, vel=None, events=None, cell_of=None):
+    _check(load_library().dpd_get_state(ctx, _ptr(pos), _ptr(vel), _ptr(events), _ptr(cell_of)), ctx)
+
+
+def dpd_set_state(ctx, pos, vel, force, k):
+    on_dev = int(hasattr(pos, "data_ptr"))
+    if not on_dev:
+        pos = np.ascontiguousarray(pos, np.float32)
+        vel = np.ascontiguousarray(vel, np.float32)
+        force = np.ascontiguousarray(force, np.float32)
+    _check(load_library().dpd_set_state(ctx, _ptr(pos), _ptr(vel), _ptr(force), int(k), on_dev), ctx)
+
+
+def dpd_neighbor_pairs(ctx, pairs, cap):
+    cnt = C.c_int64(0)
+    _check(load_library().dpd_neighbor_pairs(ctx, _ptr(pairs), int(cap), C.byref(cnt)), ctx)
+    return int(cnt.value)
+
+
+def dpd_profile(ctx, axis, nbins, out):
+    _check(load_library().dpd_profile(ctx, int(axis), int(nbins), _ptr(out)), ctx)
+
+
+def dpd_counters(ctx):
+    out = np.zeros(10, np.int64)
+    _check(load_library().dpd_counters(ctx, _ptr(out)), ctx)
+    keys = ["steps", "k", "bounce", "fallback", "n_fluid", "n_wall", "cells", "mask_cells",
+            "phi_lookups", "unstable"]
+    return dict(zip(keys, (int(x) for x in out)))
+
+
+def dpd_kernel_times(ctx, enable):
+    ms = np.zeros(DPD_NUM_KERNELS, np.float64)
+    cnt = np.zeros(DPD_NUM_KERNELS, np.int64)
+    _check(load_library().dpd_kernel_times(ctx, int(enable), _ptr(ms), _ptr(cnt)), ctx)
+    lib = load_library()
+    return {lib.dpd_kernel_name(i).decode(): (float(ms[i]), int(cnt[i]))
+            for i in range(DPD_NUM_KERNELS)}
+
+
+def dpd_sync(ctx):
+    _check(load_library().dpd_sync(ctx), ctx)
+
+
+def dpd_last_error(ctx=None):
+    return load_library().dpd_last_error(ctx).decode()
+
+
+def dpd_destroy(ctx):
+    load_library().dpd_destroy(ctx)
+
+
+def dpd_copy_probe(dst, src, nbytes, stream=None):
+    _check(load_library().dpd_copy_probe(_ptr(dst), _ptr(src), int(nbytes), _stream_handle(stream)))

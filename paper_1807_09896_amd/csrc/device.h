@@ -1,0 +1,197 @@
+// Device-side building blocks of the DPD step for gfx950: launch-parameter
+// structs, the counter-based random numbers, the discrete decisions (cell of
+// a position, pair within the cutoff, phi < 0) and the trilinear phase field.
+//
+// Decisions are written with contraction disabled so that each FP32 (or FP64)
+// operation rounds exactly once, in the order written; the physics arithmetic
+// around them is free to contract.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dpd {
+
+// Geometry of one box, passed by value to kernels.
+struct KGeom {
+  float L[3];        // box edges (float32)
+  float invw[3];     // fl32(ncell / L): cell decision scale
+  int nc[3];         // cells per axis (>= 3)
+  int ng[3];         // phi grid nodes per axis (x, y, z)
+  float inv_h[3];    // fl32(1 / h) for an FP32 grid
+  double inv_h64[3]; // 1 / h for an FP64 grid
+  float h[3];        // grid spacing (float32), for gradients
+};
+
+// DPD parameters of one box (Eq. 4-10 and the Groot-Warren integrator).
+struct KParams {
+  float a_ff, a_fw;     // conservative amplitudes, fluid-fluid and fluid-wall
+  float gamma;          // dissipative coefficient
+  float sigma_rdt;      // sigma / sqrt(dt), sigma = sqrt(2 gamma kBT)
+  float rc2;            // fl32(rc^2), the cutoff decision
+  float inv_rc;         // 1 / rc
+  float dt, hdt;        // dt and fl32(dt / 2)
+  float lamdt;          // lambda * dt
+  float g[3];           // body force on fluid particles
+  float max_disp2;      // (half the smallest cell width)^2
+  uint32_t key0, key1;  // seed words
+  uint32_t replica;
+};
+
+// Device status counters, read back by the host at sync points.
+struct Status {
+  unsigned long long bounce;     // bounce-backs by Eq. 17 (code 1)
+  unsigned long long fallback;   // returns to the start position (code 2)
+  unsigned long long unstable;   // displacement above half a cell
+  unsigned long long nonfinite;  // non-finite positions or forces
+  unsigned long long bad_phi;    // fluid particles with phi < 0 at create
+  unsigned long long bad_grid;   // non-finite phi grid values at create
+  unsigned long long lookups;    // phi evaluations at drifted positions
+  unsigned long long pad;
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Ten rounds; each round
+// takes the 64-bit products of two counter words with 0xD2511F53 and
+// 0xCD9E8D57 and mixes their halves with the other words and the key; the
+// key is bumped by 0x9E3779B9, 0xBB67AE85 between rounds.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox10(uint32_t &c0, uint32_t &c1, uint32_t &c2,
+                                         uint32_t &c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+// Gaussian xi_ij for force evaluation k (Eq. 7).  Counter (min gid, max gid,
+// k low word, (k >> 32 & 0xFFFF) | replica << 16), key = seed: the same for
+// (i, j) and (j, i).  Box-Muller: u1 = ((x0 >> 9) + 1/2) 2^-23 in (0, 1),
+// u2 = (x1 >> 9) 2^-23, xi = sqrt(-2 ln u1) cos(2 pi u2).
+__device__ __forceinline__ float pair_gauss(uint32_t gi, uint32_t gj, uint32_t klo,
+                                           uint32_t khi_rep, uint32_t key0, uint32_t key1) {
+  uint32_t c0 = min(gi, gj), c1 = max(gi, gj), c2 = klo, c3 = khi_rep;
+  philox10(c0, c1, c2, c3, key0, key1);
+  const float u1 = (float)(c0 >> 9) * 0x1p-23f + 0x1p-24f;
+  const float u2 = (float)(c1 >> 9) * 0x1p-23f;
+  return sqrtf(-2.0f * logf(u1)) * cospif(2.0f * u2);
+}
+
+// ---------------------------------------------------------------------------
+// Decisions (no contraction).
+// ---------------------------------------------------------------------------
+
+// Cell coordinate: floor(fl(x * invw)) clamped to [0, n - 1] (a NaN maps to
+// cell 0 so that no index leaves its array).
+__device__ __forceinline__ int cell_coord(float x, float invw, int n) {
+#pragma clang fp contract(off)
+  const float g = floorf(x * invw);
+  return g >= 0.0f ? (g > (float)(n - 1) ? n - 1 : (int)g) : 0;
+}
+
+__device__ __forceinline__ int cell_index(const KGeom &G, float x, float y, float z, int &cx,
+                                          int &cy, int &cz) {
+  cx = cell_coord(x, G.invw[0], G.nc[0]);
+  cy = cell_coord(y, G.invw[1], G.nc[1]);
+  cz = cell_coord(z, G.invw[2], G.nc[2]);
+  return (cz * G.nc[1] + cy) * G.nc[0] + cx;
+}
+
+// Single-edge periodic wrap in FP32.
+__device__ __forceinline__ float wrap1(float x, float L) {
+#pragma clang fp contract(off)
+  return x >= L ? x - L : (x < 0.0f ? x + L : x);
+}
+
+// Drift of the Groot-Warren step in decision form: w = fl(v + fl(hdt f)),
+// x* = fl(x + fl(dt w)), then the single-edge wrap.
+__device__ __forceinline__ float drift1(float x, float v, float f, float hdt, float dt, float L) {
+#pragma clang fp contract(off)
+  const float w = v + hdt * f;
+  const float y = x + dt * w;
+  return wrap1(y, L);
+}
+
+// Pair decision: r2 = fl(fl(fl(dx^2) + fl(dy^2)) + fl(dz^2)) with
+// d = fl(x_i - x_j'), x_j' = fl(x_j + s L) precomputed per neighbour cell.
+__device__ __forceinline__ float pair_r2(float dx, float dy, float dz) {
+#pragma clang fp contract(off)
+  const float s = dx * dx + dy * dy;
+  return s + dz * dz;
+}
+
+__device__ __forceinline__ float sub_nc(float a, float b) {
+#pragma clang fp contract(off)
+  return a - b;
+}
+
+__device__ __forceinline__ float add_nc(float a, float b) {
+#pragma clang fp contract(off)
+  return a + b;
+}
+
+// ---------------------------------------------------------------------------
+// Phase field: trilinear interpolation of the periodic node grid (decision
+// form lerp(a, b, t) = fl(a + fl(t fl(b - a))): four lerps in x, two in y,
+// one in z), and the gradient of the same interpolant.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T lerp_nc(T a, T b, T t) {
+#pragma clang fp contract(off)
+  return a + t * (b - a);
+}
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+  i = i % n;
+  return i < 0 ? i + n : i;
+}
+
+template <typename T> struct GridScale;
+template <> struct GridScale<float> {
+  static __device__ __forceinline__ float inv_h(const KGeom &G, int k) { return G.inv_h[k]; }
+  static __device__ __forceinline__ float coord(float x) { return x; }
+};
+template <> struct GridScale<double> {
+  static __device__ __forceinline__ double inv_h(const KGeom &G, int k) { return G.inv_h64[k]; }
+  static __device__ __forceinline__ double coord(float x) { return (double)x; }
+};
+
+template <typename T>
+__device__ __forceinline__ T phi_at(const T *__restrict__ grid, const KGeom &G, float x, float y,
+                                    float z) {
+#pragma clang fp contract(off)
+  const float p[3] = {x, y, z};
+  int i0[3], i1[3];
+  T t[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const T g = GridScale<T>::coord(p[k]) * GridScale<T>::inv_h(G, k);
+    const T fg = floor(g);
+    t[k] = g - fg;
+    i0[k] = wrapi((int)fg, G.ng[k]);
+    i1[k] = i0[k] + 1 == G.ng[k] ? 0 : i0[k] + 1;
+  }
+  const size_t nx = (size_t)G.ng[0], nxy = nx * (size_t)G.ng[1];
+  const T *r00 = grid + (size_t)i0[2] * nxy + (size_t)i0[1] * nx;
+  const T *r01 = grid + (size_t)i0[2] * nxy + (size_t)i1[1] * nx;
+  const T *r10 = grid + (size_t)i1[2] * nxy + (size_t)i0[1] * nx;
+  const T *r11 = grid + (size_t)i1[2] * nxy + (size_t)i1[1] * nx;
+  const T e00 = lerp_nc(r00[i0[0]], r00[i1[0]], t[0]);
+  const T e01 = lerp_nc(r01[i0[0]], r01[i1[0]], t[0]);
+  const T e10 = lerp_nc(r10[i0[0]], r10[i1[0]], t[0]);
+  const T e11 = lerp_nc(r11[i0[0]], r11[i1[0]], t[0]);
+  const T y0 = lerp_nc(e00, e01, t[1]);
+  const T y1 = lerp_nc(e10, e11, t[1]);
+  return lerp_nc(y0, y1, t[2]);
+}
+
+}  // namespace dpd

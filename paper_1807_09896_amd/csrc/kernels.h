@@ -1,0 +1,97 @@
+// Host-side launchers of the DPD kernels (defined in kernels.hip).  All take
+// the stream to launch on and return the hipError_t of the launch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device.h"
+
+namespace dpd {
+
+// Number of scan blocks for n cells (each block scans kScanChunk counts).
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanChunk = kScanThreads * kScanItems;
+inline int scan_blocks(int64_t n) { return (int)((n + kScanChunk - 1) / kScanChunk); }
+
+// Upload: pack host-order rows of one particle class into float4 arrays.
+hipError_t launch_pack(hipStream_t s, int64_t n, const float *pos, const float *vel,
+                       const uint32_t *gid, const int64_t *rows, float4 *pos4, float4 *vel4,
+                       float4 *vt4, float4 *frc4);
+
+// Cell of each position (float4 x,y,z) and its rank within the cell by an
+// atomic counter: counting-sort pass 1.
+hipError_t launch_bin(hipStream_t s, const KGeom &G, int64_t n, const float4 *pos4,
+                      int32_t *cell_of, int32_t *rank_of, int32_t *count);
+
+// Exclusive scan of count[0..ncell) into start[0..ncell] (start[ncell] =
+// total), count reset to 0, in three launches: per-block sums, a scan of
+// the block sums, and the per-block scans with their offsets.
+hipError_t launch_scan_reduce(hipStream_t s, int64_t ncell, const int32_t *count, int32_t *bsum);
+hipError_t launch_scan_top(hipStream_t s, int nblocks, int32_t *bsum);
+hipError_t launch_scan_down(hipStream_t s, int64_t ncell, int32_t *count, int32_t *start,
+                            const int32_t *bsum);
+
+// idx[start[cell_of[p]] + rank_of[p]] = p, then each cell's run sorted by p.
+hipError_t launch_scatter(hipStream_t s, int64_t n, const int32_t *cell_of,
+                          const int32_t *rank_of, const int32_t *start, int32_t *idx);
+hipError_t launch_sort_cells(hipStream_t s, int64_t ncell, const int32_t *start, int32_t *idx);
+
+// out[s] = in[idx[s]] for up to three float4 arrays (NULL skipped).
+hipError_t launch_permute(hipStream_t s, int64_t n, const int32_t *idx, const float4 *a_in,
+                          float4 *a_out, const float4 *b_in, float4 *b_out, const float4 *c_in,
+                          float4 *c_out);
+
+// Near-interface cell mask: 1 if any phi node that a trilinear lookup from
+// inside the cell can touch (one node of margin) is negative.
+hipError_t launch_mask(hipStream_t s, const KGeom &G, const void *grid, int grid_f64,
+                       double wx, double wy, double wz, double hx, double hy, double hz,
+                       int64_t ncell, uint8_t *mask);
+
+// Count non-finite grid values (create-time validation).
+hipError_t launch_check_grid(hipStream_t s, const void *grid, int grid_f64, int64_t count,
+                             Status *st);
+
+// Count fluid particles with phi < 0 (create-time validation).
+hipError_t launch_check_phi(hipStream_t s, const KGeom &G, const void *grid, int grid_f64,
+                            int64_t n, const float4 *pos4, Status *st);
+
+// Fused drift + predicted velocity + phi test + bounce-back + binning.
+hipError_t launch_integrate(hipStream_t s, const KGeom &G, const KParams &P, int64_t nf,
+                            float4 *pos4, const float4 *vel4, const float4 *frc4, float4 *vt4,
+                            int32_t *cell_of, int32_t *rank_of, int32_t *count,
+                            const uint8_t *mask, int use_mask, const void *grid, int grid_f64,
+                            Status *st);
+
+// Pair forces (Eq. 3-10) + body force + velocity update, writing the state
+// in cell-sorted slot order.  init = 1: forces only (velocities unchanged).
+hipError_t launch_force(hipStream_t s, const KGeom &G, const KParams &P, int64_t nf, int init,
+                        const float4 *pos4, const float4 *vt4, const float4 *vel4,
+                        const float4 *frc4, const int32_t *idx, const int32_t *cstart,
+                        const float4 *wpos4, const int32_t *wcstart, float4 *pos_out,
+                        float4 *vel_out, float4 *frc_out, uint64_t k, Status *st);
+
+// Interacting pairs (gid_i, gid_j) from each fluid particle.
+hipError_t launch_pairs(hipStream_t s, const KGeom &G, const KParams &P, int64_t nf,
+                        const float4 *pos4, const int32_t *idx, const int32_t *cstart,
+                        const float4 *wpos4, const int32_t *wcstart, uint32_t *pairs,
+                        int64_t cap, unsigned long long *counter);
+
+// Export rows by gid.
+hipError_t launch_export(hipStream_t s, const KGeom &G, int64_t n, const float4 *pos4,
+                         const float4 *vel4, const float4 *frc4, int wall, float *pos,
+                         float *vel, float *frc, int32_t *events, int32_t *cell_of);
+
+// Import fluid rows by gid (set_state): pos4[s] = (pos[gid], gid), ...
+hipError_t launch_import(hipStream_t s, int64_t nf, float4 *pos4, float4 *vel4, float4 *frc4,
+                         const float *pos, const float *vel, const float *frc);
+
+// Fluid profile along an axis: count, sum vx, vy, vz, |v|^2 per bin.
+hipError_t launch_profile(hipStream_t s, const KGeom &G, int64_t nf, const float4 *pos4,
+                          const float4 *vel4, int axis, int nbins, double *out);
+
+hipError_t launch_fill_zero(hipStream_t s, void *p, size_t bytes);
+hipError_t launch_copy(hipStream_t s, void *dst, const void *src, size_t bytes);
+
+}  // namespace dpd

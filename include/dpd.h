@@ -189,10 +189,11 @@ int dpd_neighbor_pairs(dpd_ctx *ctx, uint32_t *pairs, int64_t cap, int64_t *coun
  * sum |v|^2. */
 int dpd_profile(dpd_ctx *ctx, int32_t axis, int32_t nbins, double *out);
 
-/* Counters since create, into host out[10]: steps, k, bounce-backs (code 1),
- * returns to start (code 2), n_fluid, n_wall, cells, near-interface cells,
- * phi evaluations at drifted positions (particles in near-interface cells),
- * displacements above half a cell.  Synchronises the stream. */
+/* Counters into host out[10]: steps since create, k, bounce-backs (code 1)
+ * and returns to start (code 2) since create, n_fluid, n_wall, cells, grid
+ * cubes with a negative corner (the only cubes where phi can be < 0), fluid
+ * particles now inside such cubes (those that interpolate phi in a step),
+ * displacements above half a cell since create.  Synchronises the stream. */
 int dpd_counters(dpd_ctx *ctx, int64_t *out);
 
 /* Per-kernel timing with HIP events on the context stream.  enable = 1
@@ -213,6 +214,18 @@ const char *dpd_last_error(const dpd_ctx *ctx);
 
 /* Release the context and its device memory (synchronises first). */
 void dpd_destroy(dpd_ctx *ctx);
+
+/* The pair random numbers of Eq. 7 exactly as the force kernel draws them:
+ * for pair m, Philox4x32-10 (Salmon et al., SC'11) with counter
+ * (min(gi, gj), max(gi, gj), k & 0xFFFFFFFF, (k >> 32 & 0xFFFF) | replica << 16)
+ * and key (seed & 0xFFFFFFFF, seed >> 32); words (device, n x 4 uint32) gets
+ * the four output words and xi (device, n float32) the Gaussian
+ * sqrt(-2 ln u1) cos(2 pi u2) with u1 = ((w0 >> 9) + 1/2) 2^-23 and
+ * u2 = (w1 >> 9) 2^-23.  Either output may be NULL.  gi, gj are device
+ * arrays of n uint32.  Runs on hip_stream; for tests and diagnostics. */
+int dpd_pair_random(uint64_t seed, uint64_t k, uint32_t replica, const uint32_t *gi,
+                    const uint32_t *gj, int64_t n, uint32_t *words, float *xi,
+                    void *hip_stream);
 
 /* Device-to-device copy of `bytes` bytes by a plain streaming kernel (no
  * library call), on hip_stream: the reference kernel of known traffic that

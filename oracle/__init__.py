@@ -63,6 +63,7 @@ def lib():
         L.orc_xi.restype = C.c_double
         L.orc_xi_fill.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_int64, C.c_uint64,
                                   C.c_uint32, P]
+        L.orc_pairs_random.argtypes = [C.c_uint64, P, P, C.c_int64, C.c_uint64, C.c_uint32, P, P]
         L.orc_cell_of.argtypes = [P, P]
         L.orc_cell_of.restype = C.c_int32
         L.orc_phi_decide32.argtypes = [P, P]
@@ -107,6 +108,18 @@ def xi_fill(seed, gi, gj0, count, k, replica=0):
     out = np.zeros(int(count), np.float64)
     lib().orc_xi_fill(seed, gi, gj0, int(count), k, replica, _p(out))
     return out
+
+
+def pairs_random(seed, gi, gj, k, replica=0):
+    """Philox words (n, 4) and xi (n,) of the pairs (gi[m], gj[m])."""
+    gi = np.ascontiguousarray(gi, np.uint32)
+    gj = np.ascontiguousarray(gj, np.uint32)
+    n = gi.shape[0]
+    words = np.zeros((n, 4), np.uint32)
+    xi_out = np.zeros(n, np.float64)
+    lib().orc_pairs_random(int(seed) & 0xFFFFFFFFFFFFFFFF, _p(gi), _p(gj), n, int(k),
+                           int(replica), _p(words), _p(xi_out))
+    return words, xi_out
 
 
 def cell_counts(L, rc):

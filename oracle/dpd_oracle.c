@@ -100,6 +100,18 @@ void orc_xi_fill(uint64_t seed, uint32_t gi, uint32_t gj0, int64_t count,
         out[m] = orc_xi(seed, gi, gj0 + (uint32_t)m, k, replica);
 }
 
+/* Philox words and xi for arrays of pairs (gi[m], gj[m]) at evaluation k;
+ * words (n x 4) or xi (n) may be NULL. */
+void orc_pairs_random(uint64_t seed, const uint32_t *gi, const uint32_t *gj, int64_t n,
+                      uint64_t k, uint32_t replica, uint32_t *words, double *xi)
+{
+    #pragma omp parallel for schedule(static)
+    for (int64_t m = 0; m < n; ++m) {
+        if (words) orc_uniform_pair(seed, gi[m], gj[m], k, replica, words + 4 * m);
+        if (xi) xi[m] = orc_xi(seed, gi[m], gj[m], k, replica);
+    }
+}
+
 /* ------------------------------------------------------------------------
  * Geometry shared by every routine below.
  * ---------------------------------------------------------------------- */

@@ -32,7 +32,8 @@ _ERRNAMES = {DPD_E_INVAL: "DPD_E_INVAL", DPD_E_NOMEM: "DPD_E_NOMEM",
 # Every exported symbol declared in include/dpd.h.
 EXPORTED = ["dpd_create", "dpd_step", "dpd_forces", "dpd_get_state", "dpd_set_state",
             "dpd_neighbor_pairs", "dpd_profile", "dpd_counters", "dpd_kernel_times",
-            "dpd_kernel_name", "dpd_sync", "dpd_last_error", "dpd_destroy", "dpd_copy_probe"]
+            "dpd_kernel_name", "dpd_sync", "dpd_last_error", "dpd_destroy", "dpd_copy_probe",
+            "dpd_pair_random"]
 
 
 class DPDError(RuntimeError):
@@ -111,6 +112,8 @@ def load_library(path: str = LIB_PATH):
     L.dpd_destroy.restype = None
     L.dpd_copy_probe.argtypes = [P, P, C.c_size_t, P]
     L.dpd_copy_probe.restype = C.c_int
+    L.dpd_pair_random.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, P, P, C.c_int64, P, P, P]
+    L.dpd_pair_random.restype = C.c_int
     _lib = L
     return L
 
@@ -279,3 +282,10 @@ def dpd_destroy(ctx):
 
 def dpd_copy_probe(dst, src, nbytes, stream=None):
     _check(load_library().dpd_copy_probe(_ptr(dst), _ptr(src), int(nbytes), _stream_handle(stream)))
+
+
+def dpd_pair_random(seed, k, replica, gi, gj, words=None, xi=None, stream=None):
+    n = int(gi.shape[0])
+    _check(load_library().dpd_pair_random(int(seed) & 0xFFFFFFFFFFFFFFFF, int(k), int(replica),
+                                          _ptr(gi), _ptr(gj), n, _ptr(words), _ptr(xi),
+                                          _stream_handle(stream)))

@@ -59,9 +59,10 @@ struct dpd_ctx {
   float4 *wpos = nullptr;
   int32_t *wcstart = nullptr;
   void *grid = nullptr;
-  uint8_t *mask = nullptr;
+  uint32_t *bits = nullptr;   // near-interface grid cubes, one bit each
+  int64_t nwords = 0;
   int use_mask = 1;
-  int64_t mask_cells = 0;
+  int64_t flagged_cubes = 0;
   Status *status = nullptr;
   unsigned long long *pair_counter = nullptr;
 
@@ -257,7 +258,7 @@ int one_step(dpd_ctx *c) {
   HIP_TRY(c, timed(c, K_INTEGRATE, [&] {
             return dpd::launch_integrate(c->stream, c->G, c->P, c->nf, c->pos[a], c->vel[a],
                                          c->frc[a], c->vt, c->cell_of, c->rank_of, c->count,
-                                         c->mask, c->use_mask, c->grid, c->grid_f64, c->status);
+                                         c->bits, c->use_mask, c->grid, c->grid_f64, c->status);
           }));
   int rc = scan_scatter_sort(c);
   if (rc) return rc;
@@ -451,13 +452,14 @@ int dpd_create(const dpd_box *box, const dpd_particles *pp, const dpd_params *pr
   c->wpos = (float4 *)dalloc(c, 16 * nw);
   c->wcstart = (int32_t *)dalloc(c, 4 * ((size_t)ncell + 1));
   c->grid = dalloc(c, gbytes);
-  c->mask = (uint8_t *)dalloc(c, (size_t)ncell);
+  c->nwords = ((int64_t)phi->n[0] * phi->n[1] * phi->n[2] + 31) / 32;
+  c->bits = (uint32_t *)dalloc(c, 4 * (size_t)c->nwords);
   c->status = (Status *)dalloc(c, sizeof(Status));
   c->pair_counter = (unsigned long long *)dalloc(c, 8);
   for (int b = 0; b < 2; ++b)
     if (!c->pos[b] || !c->vel[b] || !c->frc[b]) return bail(fail(c, DPD_E_NOMEM, "device allocation failed"));
   if (!c->vt || !c->cell_of || !c->rank_of || !c->idx || !c->count || !c->cstart || !c->bsum ||
-      !c->wpos || !c->wcstart || !c->grid || !c->mask || !c->status || !c->pair_counter)
+      !c->wpos || !c->wcstart || !c->grid || !c->bits || !c->status || !c->pair_counter)
     return bail(fail(c, DPD_E_NOMEM, "device allocation failed"));
 
   // ---- upload ----
@@ -522,10 +524,7 @@ int dpd_create(const dpd_box *box, const dpd_particles *pp, const dpd_params *pr
   }
   // near-interface mask and create-time phi check
   {
-    const double wx = box->L[0] / nc[0], wy = box->L[1] / nc[1], wz = box->L[2] / nc[2];
-    chk(dpd::launch_mask(c->stream, c->G, c->grid, c->grid_f64, wx, wy, wz, phi->h[0], phi->h[1],
-                         phi->h[2], ncell, c->mask),
-        "mask");
+    chk(dpd::launch_cube_mask(c->stream, c->G, c->grid, c->grid_f64, c->nwords, c->bits), "mask");
     chk(dpd::launch_check_grid(c->stream, c->grid, c->grid_f64,
                                (int64_t)phi->n[0] * phi->n[1] * phi->n[2], c->status),
         "check grid");
@@ -540,12 +539,13 @@ int dpd_create(const dpd_box *box, const dpd_particles *pp, const dpd_params *pr
     if (st.bad_phi)
       return bail(fail(c, DPD_E_INVAL,
                        std::to_string(st.bad_phi) + " fluid particles start at phi < 0"));
-    std::vector<uint8_t> hm((size_t)ncell);
-    chk(hipMemcpy(hm.data(), c->mask, (size_t)ncell, hipMemcpyDeviceToHost), "mask readback");
+    std::vector<uint32_t> hb((size_t)c->nwords);
+    chk(hipMemcpy(hb.data(), c->bits, 4 * (size_t)c->nwords, hipMemcpyDeviceToHost),
+        "mask readback");
     if (rc) return bail(rc);
     int64_t m = 0;
-    for (uint8_t v : hm) m += v;
-    c->mask_cells = m;
+    for (uint32_t v : hb) m += __builtin_popcount(v);
+    c->flagged_cubes = m;
   }
   // initial cell list and forces f(0) with k = 0
   c->cur = 0;
@@ -674,9 +674,15 @@ int dpd_counters(dpd_ctx *c, int64_t *out) {
   out[4] = c->nf;
   out[5] = c->nw;
   out[6] = c->ncell;
-  out[7] = c->mask_cells;
-  out[8] = (int64_t)st.lookups;
+  out[7] = c->flagged_cubes;
   out[9] = (int64_t)st.unstable;
+  // fluid particles now in flagged cubes (those that interpolate phi)
+  HIP_TRY(c, dpd::launch_fill_zero(c->stream, &c->status->lookups, 8));
+  HIP_TRY(c, dpd::launch_count_flagged(c->stream, c->G, c->grid_f64, c->nf, c->pos[c->cur],
+                                       c->bits, &c->status->lookups));
+  rc = read_status(c, st);
+  if (rc) return rc;
+  out[8] = (int64_t)st.lookups;
   return DPD_OK;
 }
 
@@ -709,6 +715,15 @@ void dpd_destroy(dpd_ctx *c) {
   (void)hipStreamSynchronize(c->stream);
   release_all(c);
   delete c;
+}
+
+int dpd_pair_random(uint64_t seed, uint64_t k, uint32_t replica, const uint32_t *gi,
+                    const uint32_t *gj, int64_t n, uint32_t *words, float *xi, void *hip_stream) {
+  if (n < 0 || (n > 0 && (!gi || !gj))) return DPD_E_INVAL;
+  if (replica >= 65536u) return DPD_E_INVAL;
+  hipError_t e = dpd::launch_pair_random((hipStream_t)hip_stream, seed, k, replica, gi, gj, n,
+                                         words, xi);
+  return e == hipSuccess ? DPD_OK : DPD_E_DEVICE;
 }
 
 int dpd_copy_probe(void *dst, const void *src, size_t bytes, void *hip_stream) {

@@ -83,7 +83,10 @@ __device__ __forceinline__ float pair_gauss(uint32_t gi, uint32_t gj, uint32_t k
   philox10(c0, c1, c2, c3, key0, key1);
   const float u1 = (float)(c0 >> 9) * 0x1p-23f + 0x1p-24f;
   const float u2 = (float)(c1 >> 9) * 0x1p-23f;
-  return sqrtf(-2.0f * logf(u1)) * cospif(2.0f * u2);
+  // -2 ln u1 = -2 ln2 log2 u1 (v_log_f32); cos(2 pi u2) is v_cos_f32(u2),
+  // whose argument is in revolutions.
+  const float m2ln = fmaxf(-2.0f * 0.693147180559945f * __builtin_amdgcn_logf(u1), 0.0f);
+  return __builtin_amdgcn_sqrtf(m2ln) * __builtin_amdgcn_cosf(u2);
 }
 
 // ---------------------------------------------------------------------------
@@ -165,33 +168,67 @@ template <> struct GridScale<double> {
   static __device__ __forceinline__ double coord(float x) { return (double)x; }
 };
 
+// Grid cube holding a point: lower node indices (periodic) and the local
+// coordinates t in [0, 1] along each axis (decision form).
 template <typename T>
-__device__ __forceinline__ T phi_at(const T *__restrict__ grid, const KGeom &G, float x, float y,
-                                    float z) {
-#pragma clang fp contract(off)
-  const float p[3] = {x, y, z};
+struct GridLoc {
   int i0[3], i1[3];
   T t[3];
+};
+
+template <typename T>
+__device__ __forceinline__ GridLoc<T> grid_locate(const KGeom &G, float x, float y, float z) {
+#pragma clang fp contract(off)
+  const float p[3] = {x, y, z};
+  GridLoc<T> L;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const T g = GridScale<T>::coord(p[k]) * GridScale<T>::inv_h(G, k);
     const T fg = floor(g);
-    t[k] = g - fg;
-    i0[k] = wrapi((int)fg, G.ng[k]);
-    i1[k] = i0[k] + 1 == G.ng[k] ? 0 : i0[k] + 1;
+    L.t[k] = g - fg;
+    L.i0[k] = wrapi((int)fg, G.ng[k]);
+    L.i1[k] = L.i0[k] + 1 == G.ng[k] ? 0 : L.i0[k] + 1;
   }
+  return L;
+}
+
+// Linear index of the grid cube whose lower corner is node i0.
+template <typename T>
+__device__ __forceinline__ size_t cube_index(const KGeom &G, const GridLoc<T> &L) {
+  return ((size_t)L.i0[2] * (size_t)G.ng[1] + (size_t)L.i0[1]) * (size_t)G.ng[0] + (size_t)L.i0[0];
+}
+
+template <typename T>
+__device__ __forceinline__ T phi_interp(const T *__restrict__ grid, const KGeom &G,
+                                        const GridLoc<T> &L) {
+#pragma clang fp contract(off)
   const size_t nx = (size_t)G.ng[0], nxy = nx * (size_t)G.ng[1];
-  const T *r00 = grid + (size_t)i0[2] * nxy + (size_t)i0[1] * nx;
-  const T *r01 = grid + (size_t)i0[2] * nxy + (size_t)i1[1] * nx;
-  const T *r10 = grid + (size_t)i1[2] * nxy + (size_t)i0[1] * nx;
-  const T *r11 = grid + (size_t)i1[2] * nxy + (size_t)i1[1] * nx;
-  const T e00 = lerp_nc(r00[i0[0]], r00[i1[0]], t[0]);
-  const T e01 = lerp_nc(r01[i0[0]], r01[i1[0]], t[0]);
-  const T e10 = lerp_nc(r10[i0[0]], r10[i1[0]], t[0]);
-  const T e11 = lerp_nc(r11[i0[0]], r11[i1[0]], t[0]);
-  const T y0 = lerp_nc(e00, e01, t[1]);
-  const T y1 = lerp_nc(e10, e11, t[1]);
-  return lerp_nc(y0, y1, t[2]);
+  const T *r00 = grid + (size_t)L.i0[2] * nxy + (size_t)L.i0[1] * nx;
+  const T *r01 = grid + (size_t)L.i0[2] * nxy + (size_t)L.i1[1] * nx;
+  const T *r10 = grid + (size_t)L.i1[2] * nxy + (size_t)L.i0[1] * nx;
+  const T *r11 = grid + (size_t)L.i1[2] * nxy + (size_t)L.i1[1] * nx;
+  const T e00 = lerp_nc(r00[L.i0[0]], r00[L.i1[0]], L.t[0]);
+  const T e01 = lerp_nc(r01[L.i0[0]], r01[L.i1[0]], L.t[0]);
+  const T e10 = lerp_nc(r10[L.i0[0]], r10[L.i1[0]], L.t[0]);
+  const T e11 = lerp_nc(r11[L.i0[0]], r11[L.i1[0]], L.t[0]);
+  const T y0 = lerp_nc(e00, e01, L.t[1]);
+  const T y1 = lerp_nc(e10, e11, L.t[1]);
+  return lerp_nc(y0, y1, L.t[2]);
+}
+
+template <typename T>
+__device__ __forceinline__ T phi_at(const T *__restrict__ grid, const KGeom &G, float x, float y,
+                                    float z) {
+  return phi_interp(grid, G, grid_locate<T>(G, x, y, z));
+}
+
+// Map a hardware block index to a logical one so that each of the 8 XCDs
+// (which receive blocks round-robin) works on one contiguous eighth of the
+// index space and its L2 sees one spatial region.  gridDim.x must be a
+// multiple of 8; logical indices past the work are idle.
+__device__ __forceinline__ int xcd_block() {
+  const int per = (int)(gridDim.x >> 3);
+  return (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
 }
 
 }  // namespace dpd

@@ -43,11 +43,15 @@ hipError_t launch_permute(hipStream_t s, int64_t n, const int32_t *idx, const fl
                           float4 *a_out, const float4 *b_in, float4 *b_out, const float4 *c_in,
                           float4 *c_out);
 
-// Near-interface cell mask: 1 if any phi node that a trilinear lookup from
-// inside the cell can touch (one node of margin) is negative.
-hipError_t launch_mask(hipStream_t s, const KGeom &G, const void *grid, int grid_f64,
-                       double wx, double wy, double wz, double hx, double hy, double hz,
-                       int64_t ncell, uint8_t *mask);
+// Near-interface mask: one bit per grid cube, set when a corner is negative
+// (nwords = ceil(cubes / 32)).
+hipError_t launch_cube_mask(hipStream_t s, const KGeom &G, const void *grid, int grid_f64,
+                            int64_t nwords, uint32_t *bits);
+
+// Count fluid particles whose grid cube is flagged into *out (added).
+hipError_t launch_count_flagged(hipStream_t s, const KGeom &G, int grid_f64, int64_t nf,
+                                const float4 *pos4, const uint32_t *bits,
+                                unsigned long long *out);
 
 // Count non-finite grid values (create-time validation).
 hipError_t launch_check_grid(hipStream_t s, const void *grid, int grid_f64, int64_t count,
@@ -61,7 +65,7 @@ hipError_t launch_check_phi(hipStream_t s, const KGeom &G, const void *grid, int
 hipError_t launch_integrate(hipStream_t s, const KGeom &G, const KParams &P, int64_t nf,
                             float4 *pos4, const float4 *vel4, const float4 *frc4, float4 *vt4,
                             int32_t *cell_of, int32_t *rank_of, int32_t *count,
-                            const uint8_t *mask, int use_mask, const void *grid, int grid_f64,
+                            const uint32_t *bits, int use_mask, const void *grid, int grid_f64,
                             Status *st);
 
 // Pair forces (Eq. 3-10) + body force + velocity update, writing the state
@@ -77,6 +81,11 @@ hipError_t launch_pairs(hipStream_t s, const KGeom &G, const KParams &P, int64_t
                         const float4 *pos4, const int32_t *idx, const int32_t *cstart,
                         const float4 *wpos4, const int32_t *wcstart, uint32_t *pairs,
                         int64_t cap, unsigned long long *counter);
+
+// Random numbers of given pairs: Philox words (n x 4) and xi (n), either NULL.
+hipError_t launch_pair_random(hipStream_t s, uint64_t seed, uint64_t k, uint32_t replica,
+                              const uint32_t *gi, const uint32_t *gj, int64_t n, uint32_t *words,
+                              float *xi);
 
 // Export rows by gid.
 hipError_t launch_export(hipStream_t s, const KGeom &G, int64_t n, const float4 *pos4,

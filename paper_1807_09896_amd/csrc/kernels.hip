@@ -208,32 +208,42 @@ __global__ void k_permute(int64_t n, const int32_t *__restrict__ idx, const floa
 // ---------------------------------------------------------------------------
 // Phase field: near-interface mask and create-time check
 // ---------------------------------------------------------------------------
+// One bit per grid cube (the cube with lower corner node (i, j, k)): set if
+// any of its 8 corner nodes is negative.  A trilinear value inside a cube
+// whose corners are all >= 0 is >= 0 in the rounding of the decision form
+// (each lerp of non-negative values is non-negative), so particles in
+// unflagged cubes cannot have phi < 0 and skip the interpolation.
 template <typename T>
-__global__ void k_mask(const KGeom G, const T *__restrict__ grid, double wx, double wy, double wz,
-                       double hx, double hy, double hz, int64_t ncell, uint8_t *mask) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncell) return;
-  const int cx = (int)(c % G.nc[0]);
-  const int cy = (int)((c / G.nc[0]) % G.nc[1]);
-  const int cz = (int)(c / ((int64_t)G.nc[0] * G.nc[1]));
-  const int x0 = (int)floor(cx * wx / hx) - 1, x1 = (int)ceil((cx + 1) * wx / hx) + 1;
-  const int y0 = (int)floor(cy * wy / hy) - 1, y1 = (int)ceil((cy + 1) * wy / hy) + 1;
-  const int z0 = (int)floor(cz * wz / hz) - 1, z1 = (int)ceil((cz + 1) * wz / hz) + 1;
+__global__ void k_cube_mask(const KGeom G, const T *__restrict__ grid, int64_t nwords,
+                            uint32_t *__restrict__ bits) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= nwords) return;
+  const int64_t ncube = (int64_t)G.ng[0] * G.ng[1] * G.ng[2];
   const size_t nx = (size_t)G.ng[0], nxy = nx * (size_t)G.ng[1];
-  uint8_t m = 0;
-  for (int k = z0; k <= z1 && !m; ++k) {
-    const size_t kk = (size_t)wrapi(k, G.ng[2]);
-    for (int j = y0; j <= y1 && !m; ++j) {
-      const T *row = grid + kk * nxy + (size_t)wrapi(j, G.ng[1]) * nx;
-      for (int i = x0; i <= x1; ++i) {
-        if (row[wrapi(i, G.ng[0])] < (T)0) {
-          m = 1;
-          break;
-        }
+  uint32_t word = 0;
+  for (int b = 0; b < 32; ++b) {
+    const int64_t q = w * 32 + b;
+    if (q >= ncube) break;
+    const int i = (int)(q % G.ng[0]);
+    const int j = (int)((q / G.ng[0]) % G.ng[1]);
+    const int k = (int)(q / ((int64_t)G.ng[0] * G.ng[1]));
+    const int i1 = i + 1 == G.ng[0] ? 0 : i + 1;
+    const int j1 = j + 1 == G.ng[1] ? 0 : j + 1;
+    const int k1 = k + 1 == G.ng[2] ? 0 : k + 1;
+    bool neg = false;
+    for (int dk = 0; dk < 2; ++dk)
+      for (int dj = 0; dj < 2; ++dj) {
+        const T *row = grid + (size_t)(dk ? k1 : k) * nxy + (size_t)(dj ? j1 : j) * nx;
+        neg |= row[i] < (T)0;
+        neg |= row[i1] < (T)0;
       }
-    }
+    if (neg) word |= 1u << b;
   }
-  mask[c] = m;
+  bits[w] = word;
+}
+
+__device__ __forceinline__ bool cube_flagged(const uint32_t *__restrict__ bits, size_t q) {
+  return (bits[q >> 5] >> (q & 31)) & 1u;
 }
 
 template <typename T>
@@ -263,8 +273,8 @@ __global__ __launch_bounds__(kBlock) void k_integrate(
     const KGeom G, const KParams P, int64_t nf, float4 *__restrict__ pos4,
     const float4 *__restrict__ vel4, const float4 *__restrict__ frc4, float4 *__restrict__ vt4,
     int32_t *__restrict__ cell_of, int32_t *__restrict__ rank_of, int32_t *__restrict__ count,
-    const uint8_t *__restrict__ mask, int use_mask, const T *__restrict__ grid, Status *st) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t *__restrict__ bits, int use_mask, const T *__restrict__ grid, Status *st) {
+  const int64_t p = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
   if (p >= nf) return;
   const float4 x = pos4[p];
   const float4 v = vel4[p];
@@ -291,16 +301,9 @@ __global__ __launch_bounds__(kBlock) void k_integrate(
   int cx, cy, cz;
   int c = cell_index(G, xs, ys, zs, cx, cy, cz);
   int event = 0;
-  const bool look = !use_mask || mask[c];
-  {
-    // one atomic per wavefront for the lookup counter
-    const unsigned long long act = __ballot(1);
-    const unsigned long long hit = __ballot(look);
-    if (__lane_id() == __ffsll((long long)act) - 1 && hit)
-      atomicAdd(&st->lookups, (unsigned long long)__popcll(hit));
-  }
-  if (look) {
-    const T phis = phi_at(grid, G, xs, ys, zs);
+  const GridLoc<T> loc = grid_locate<T>(G, xs, ys, zs);
+  if (!use_mask || cube_flagged(bits, cube_index(G, loc))) {
+    const T phis = phi_interp(grid, G, loc);
     if (phis < (T)0) {
       // Eq. 16-17: distances beyond and before the interface from atanh(phi)
       const T phit = phi_at(grid, G, x.x, x.y, x.z);
@@ -337,9 +340,46 @@ __global__ __launch_bounds__(kBlock) void k_integrate(
   rank_of[p] = atomicAdd(&count[c], 1);
 }
 
+// Number of fluid particles whose grid cube is flagged (the particles that
+// interpolate phi in a step), one atomic per block.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_count_flagged(const KGeom G, int64_t nf,
+                                                          const float4 *__restrict__ pos4,
+                                                          const uint32_t *__restrict__ bits,
+                                                          unsigned long long *out) {
+  __shared__ int lds[kBlock];
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int v = 0;
+  if (p < nf) {
+    const float4 x = pos4[p];
+    v = cube_flagged(bits, cube_index(G, grid_locate<T>(G, x.x, x.y, x.z))) ? 1 : 0;
+  }
+  lds[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) lds[threadIdx.x] += lds[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && lds[0]) atomicAdd(out, (unsigned long long)lds[0]);
+}
+
 // ---------------------------------------------------------------------------
 // Pair force (Eq. 3-10), body force, velocity update
+//
+// One thread per fluid particle i, in cell-sorted slot order.  The 27
+// neighbour cells are scanned for candidates (fluid run, then wall run of
+// each cell) with the FP32 cutoff decision; hits are appended to the
+// thread's column of an LDS list (slot-major, so a wavefront's appends touch
+// 64 different banks).  When the list is full or the scan is done, the
+// thread evaluates the listed pairs densely: the random number and force
+// arithmetic run only for pairs inside the cutoff, and a wavefront's lanes
+// stay converged for min(count) iterations instead of diverging on every
+// candidate.  Sums run in candidate order, so results are deterministic.
 // ---------------------------------------------------------------------------
+constexpr int kForceBlock = 256;
+constexpr int kListCap = 24;
+constexpr uint32_t kWallBit = 0x80000000u;
+
 struct Acc {
   float x, y, z;
 };
@@ -360,8 +400,38 @@ __device__ __forceinline__ void add_pair(Acc &acc, float dx, float dy, float dz,
   acc.z += mag * ez;
 }
 
+// Minimum-image component (|d| < L/2 for every pair within the cutoff).
+__device__ __forceinline__ float min_image(float d, float L) {
+  return d > 0.5f * L ? d - L : (d < -0.5f * L ? d + L : d);
+}
+
+// Scan state of one thread over its 27 neighbour cells.
+struct Scan {
+  int nbr;         // next neighbour cell code, 0..27
+  int t, t_end;    // current run [t, t_end)
+  bool wall;       // current run is the wall run of the cell
+  int c;           // current cell
+  float sx, sy, sz;
+};
+
+__device__ __forceinline__ void scan_cell(const KGeom &G, int cx, int cy, int cz, int code,
+                                          Scan &S) {
+  const int ox = code % 3 - 1, oy = (code / 3) % 3 - 1, oz = code / 9 - 1;
+  int qx = cx + ox, qy = cy + oy, qz = cz + oz;
+  S.sx = 0.f;
+  S.sy = 0.f;
+  S.sz = 0.f;
+  if (qx < 0) { qx += G.nc[0]; S.sx = -G.L[0]; }
+  else if (qx >= G.nc[0]) { qx -= G.nc[0]; S.sx = G.L[0]; }
+  if (qy < 0) { qy += G.nc[1]; S.sy = -G.L[1]; }
+  else if (qy >= G.nc[1]) { qy -= G.nc[1]; S.sy = G.L[1]; }
+  if (qz < 0) { qz += G.nc[2]; S.sz = -G.L[2]; }
+  else if (qz >= G.nc[2]) { qz -= G.nc[2]; S.sz = G.L[2]; }
+  S.c = (qz * G.nc[1] + qy) * G.nc[0] + qx;
+}
+
 template <bool INIT>
-__global__ __launch_bounds__(kBlock) void k_force(
+__global__ __launch_bounds__(kForceBlock) void k_force(
     const KGeom G, const KParams P, int64_t nf, const float4 *__restrict__ pos4,
     const float4 *__restrict__ vt4, const float4 *__restrict__ vel4,
     const float4 *__restrict__ frc4, const int32_t *__restrict__ idx,
@@ -369,7 +439,8 @@ __global__ __launch_bounds__(kBlock) void k_force(
     const int32_t *__restrict__ wcstart, float4 *__restrict__ pos_out,
     float4 *__restrict__ vel_out, float4 *__restrict__ frc_out, uint32_t klo, uint32_t khi,
     Status *st) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ uint32_t list[kListCap * kForceBlock];
+  const int64_t s = (int64_t)xcd_block() * kForceBlock + threadIdx.x;
   if (s >= nf) return;
   const int i = idx[s];
   const float4 pi = pos4[i];
@@ -377,50 +448,81 @@ __global__ __launch_bounds__(kBlock) void k_force(
   const uint32_t gi = __float_as_uint(pi.w);
   int cx, cy, cz;
   cell_index(G, pi.x, pi.y, pi.z, cx, cy, cz);
+  uint32_t *mine = list + threadIdx.x;
   Acc acc = {0.f, 0.f, 0.f};
-  for (int oz = -1; oz <= 1; ++oz) {
-    int qz = cz + oz;
-    float sz = 0.f;
-    if (qz < 0) { qz += G.nc[2]; sz = -G.L[2]; }
-    else if (qz >= G.nc[2]) { qz -= G.nc[2]; sz = G.L[2]; }
-    for (int oy = -1; oy <= 1; ++oy) {
-      int qy = cy + oy;
-      float sy = 0.f;
-      if (qy < 0) { qy += G.nc[1]; sy = -G.L[1]; }
-      else if (qy >= G.nc[1]) { qy -= G.nc[1]; sy = G.L[1]; }
-      for (int ox = -1; ox <= 1; ++ox) {
-        int qx = cx + ox;
-        float sx = 0.f;
-        if (qx < 0) { qx += G.nc[0]; sx = -G.L[0]; }
-        else if (qx >= G.nc[0]) { qx -= G.nc[0]; sx = G.L[0]; }
-        const int c = (qz * G.nc[1] + qy) * G.nc[0] + qx;
-        const int f0 = cstart[c], f1 = cstart[c + 1];
-        for (int t = f0; t < f1; ++t) {
-          const int j = idx[t];
-          if (j == i) continue;
-          const float4 pj = pos4[j];
-          const float dx = sub_nc(pi.x, add_nc(pj.x, sx));
-          const float dy = sub_nc(pi.y, add_nc(pj.y, sy));
-          const float dz = sub_nc(pi.z, add_nc(pj.z, sz));
-          const float r2 = pair_r2(dx, dy, dz);
-          if (r2 < P.rc2 && r2 > 0.0f) {
-            const float4 vtj = vt4[j];
-            add_pair(acc, dx, dy, dz, r2, vti.x - vtj.x, vti.y - vtj.y, vti.z - vtj.z, P.a_ff,
-                     P, gi, __float_as_uint(pj.w), klo, khi);
-          }
+  Scan S;
+  S.nbr = 0;
+  S.t = 0;
+  S.t_end = 0;
+  S.wall = true;
+  S.c = 0;
+  S.sx = S.sy = S.sz = 0.f;
+  bool done = false;
+  while (!done) {
+    int cnt = 0;
+    while (cnt < kListCap) {
+      if (S.t >= S.t_end) {
+        if (!S.wall) {
+          // fluid run of this cell done: its wall run next
+          S.wall = true;
+          S.t = wcstart[S.c];
+          S.t_end = wcstart[S.c + 1];
+          continue;
         }
-        const int w0 = wcstart[c], w1 = wcstart[c + 1];
-        for (int t = w0; t < w1; ++t) {
-          const float4 pw = wpos4[t];
-          const float dx = sub_nc(pi.x, add_nc(pw.x, sx));
-          const float dy = sub_nc(pi.y, add_nc(pw.y, sy));
-          const float dz = sub_nc(pi.z, add_nc(pw.z, sz));
-          const float r2 = pair_r2(dx, dy, dz);
-          if (r2 < P.rc2 && r2 > 0.0f)
-            add_pair(acc, dx, dy, dz, r2, vti.x, vti.y, vti.z, P.a_fw, P, gi,
-                     __float_as_uint(pw.w), klo, khi);
+        if (S.nbr == 27) {
+          done = true;
+          break;
         }
+        scan_cell(G, cx, cy, cz, S.nbr, S);
+        ++S.nbr;
+        S.wall = false;
+        S.t = cstart[S.c];
+        S.t_end = cstart[S.c + 1];
+        continue;
       }
+      float4 pj;
+      uint32_t tag;
+      if (S.wall) {
+        pj = wpos4[S.t];
+        tag = (uint32_t)S.t | kWallBit;
+      } else {
+        const int j = idx[S.t];
+        pj = pos4[j];
+        tag = (uint32_t)j;
+        if (j == i) tag = 0xFFFFFFFFu;
+      }
+      ++S.t;
+      const float dx = sub_nc(pi.x, add_nc(pj.x, S.sx));
+      const float dy = sub_nc(pi.y, add_nc(pj.y, S.sy));
+      const float dz = sub_nc(pi.z, add_nc(pj.z, S.sz));
+      const float r2 = pair_r2(dx, dy, dz);
+      if (r2 < P.rc2 && r2 > 0.0f && tag != 0xFFFFFFFFu) {
+        mine[cnt * kForceBlock] = tag;
+        ++cnt;
+      }
+    }
+    // dense evaluation of the listed pairs
+    for (int q = 0; q < cnt; ++q) {
+      const uint32_t tag = mine[q * kForceBlock];
+      float4 pj;
+      float dvx = vti.x, dvy = vti.y, dvz = vti.z;
+      float a;
+      if (tag & kWallBit) {
+        pj = wpos4[tag & ~kWallBit];
+        a = P.a_fw;
+      } else {
+        pj = pos4[tag];
+        const float4 vtj = vt4[tag];
+        dvx -= vtj.x;
+        dvy -= vtj.y;
+        dvz -= vtj.z;
+        a = P.a_ff;
+      }
+      const float dx = min_image(pi.x - pj.x, G.L[0]);
+      const float dy = min_image(pi.y - pj.y, G.L[1]);
+      const float dz = min_image(pi.z - pj.z, G.L[2]);
+      const float r2 = dx * dx + dy * dy + dz * dz;
+      add_pair(acc, dx, dy, dz, r2, dvx, dvy, dvz, a, P, gi, __float_as_uint(pj.w), klo, khi);
     }
   }
   const float fx = acc.x + P.g[0], fy = acc.y + P.g[1], fz = acc.z + P.g[2];
@@ -444,62 +546,98 @@ __global__ __launch_bounds__(kBlock) void k_force(
   frc_out[s] = make_float4(fx, fy, fz, 0.f);
 }
 
-// Interacting pairs with the same decision as the force kernel.
+// Interacting pairs with the same decision as the force kernel.  Each thread
+// counts its pairs, a wavefront reserves room with one atomic, then the
+// pairs are written.
+__device__ __forceinline__ int pairs_of(const KGeom &G, const KParams &P, int i, float4 pi,
+                                        int cx, int cy, int cz, const float4 *__restrict__ pos4,
+                                        const int32_t *__restrict__ idx,
+                                        const int32_t *__restrict__ cstart,
+                                        const float4 *__restrict__ wpos4,
+                                        const int32_t *__restrict__ wcstart, uint32_t *out,
+                                        int64_t base, int64_t cap) {
+  int n = 0;
+  const uint32_t gi = __float_as_uint(pi.w);
+  for (int code = 0; code < 27; ++code) {
+    Scan S;
+    scan_cell(G, cx, cy, cz, code, S);
+    for (int pass = 0; pass < 2; ++pass) {
+      const int t0 = pass ? wcstart[S.c] : cstart[S.c];
+      const int t1 = pass ? wcstart[S.c + 1] : cstart[S.c + 1];
+      for (int t = t0; t < t1; ++t) {
+        float4 pj;
+        if (pass) {
+          pj = wpos4[t];
+        } else {
+          const int j = idx[t];
+          if (j == i) continue;
+          pj = pos4[j];
+        }
+        const float dx = sub_nc(pi.x, add_nc(pj.x, S.sx));
+        const float dy = sub_nc(pi.y, add_nc(pj.y, S.sy));
+        const float dz = sub_nc(pi.z, add_nc(pj.z, S.sz));
+        if (pair_r2(dx, dy, dz) < P.rc2) {
+          if (out && base + n < cap) {
+            out[2 * (base + n)] = gi;
+            out[2 * (base + n) + 1] = __float_as_uint(pj.w);
+          }
+          ++n;
+        }
+      }
+    }
+  }
+  return n;
+}
+
 __global__ __launch_bounds__(kBlock) void k_pairs(
     const KGeom G, const KParams P, int64_t nf, const float4 *__restrict__ pos4,
     const int32_t *__restrict__ idx, const int32_t *__restrict__ cstart,
     const float4 *__restrict__ wpos4, const int32_t *__restrict__ wcstart, uint32_t *pairs,
     int64_t cap, unsigned long long *counter) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nf) return;
-  const int i = idx[s];
-  const float4 pi = pos4[i];
-  const uint32_t gi = __float_as_uint(pi.w);
-  int cx, cy, cz;
-  cell_index(G, pi.x, pi.y, pi.z, cx, cy, cz);
-  for (int oz = -1; oz <= 1; ++oz) {
-    int qz = cz + oz;
-    float sz = 0.f;
-    if (qz < 0) { qz += G.nc[2]; sz = -G.L[2]; }
-    else if (qz >= G.nc[2]) { qz -= G.nc[2]; sz = G.L[2]; }
-    for (int oy = -1; oy <= 1; ++oy) {
-      int qy = cy + oy;
-      float sy = 0.f;
-      if (qy < 0) { qy += G.nc[1]; sy = -G.L[1]; }
-      else if (qy >= G.nc[1]) { qy -= G.nc[1]; sy = G.L[1]; }
-      for (int ox = -1; ox <= 1; ++ox) {
-        int qx = cx + ox;
-        float sx = 0.f;
-        if (qx < 0) { qx += G.nc[0]; sx = -G.L[0]; }
-        else if (qx >= G.nc[0]) { qx -= G.nc[0]; sx = G.L[0]; }
-        const int c = (qz * G.nc[1] + qy) * G.nc[0] + qx;
-        for (int pass = 0; pass < 2; ++pass) {
-          const int t0 = pass ? wcstart[c] : cstart[c];
-          const int t1 = pass ? wcstart[c + 1] : cstart[c + 1];
-          for (int t = t0; t < t1; ++t) {
-            float4 pj;
-            if (pass) {
-              pj = wpos4[t];
-            } else {
-              const int j = idx[t];
-              if (j == i) continue;
-              pj = pos4[j];
-            }
-            const float dx = sub_nc(pi.x, add_nc(pj.x, sx));
-            const float dy = sub_nc(pi.y, add_nc(pj.y, sy));
-            const float dz = sub_nc(pi.z, add_nc(pj.z, sz));
-            if (pair_r2(dx, dy, dz) < P.rc2) {
-              const unsigned long long q = atomicAdd(counter, 1ull);
-              if ((int64_t)q < cap) {
-                pairs[2 * q] = gi;
-                pairs[2 * q + 1] = __float_as_uint(pj.w);
-              }
-            }
-          }
-        }
-      }
-    }
+  const bool act = s < nf;
+  int i = 0, cx = 0, cy = 0, cz = 0;
+  float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
+  int n = 0;
+  if (act) {
+    i = idx[s];
+    pi = pos4[i];
+    cell_index(G, pi.x, pi.y, pi.z, cx, cy, cz);
+    n = pairs_of(G, P, i, pi, cx, cy, cz, pos4, idx, cstart, wpos4, wcstart, nullptr, 0, 0);
   }
+  // wavefront-inclusive prefix of n, one atomic per wavefront
+  const int lane = (int)__lane_id();
+  int incl = n;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int v = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += v;
+  }
+  const int total = __shfl(incl, 63, 64);
+  unsigned long long base = 0;
+  if (lane == 63 && total > 0) base = atomicAdd(counter, (unsigned long long)total);
+  base = __shfl(base, 63, 64);
+  if (act && pairs && n > 0)
+    pairs_of(G, P, i, pi, cx, cy, cz, pos4, idx, cstart, wpos4, wcstart, pairs,
+             (int64_t)base + incl - n, cap);
+}
+
+// The random numbers of given pairs (the same device functions as the force
+// kernel): the four Philox words and xi.
+__global__ void k_pair_random(uint32_t key0, uint32_t key1, uint32_t klo, uint32_t khi,
+                              const uint32_t *__restrict__ gi, const uint32_t *__restrict__ gj,
+                              int64_t n, uint32_t *words, float *xi) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const uint32_t a = gi[p], b = gj[p];
+  if (words) {
+    uint32_t c0 = min(a, b), c1 = max(a, b), c2 = klo, c3 = khi;
+    philox10(c0, c1, c2, c3, key0, key1);
+    words[4 * p] = c0;
+    words[4 * p + 1] = c1;
+    words[4 * p + 2] = c2;
+    words[4 * p + 3] = c3;
+  }
+  if (xi) xi[p] = pair_gauss(a, b, klo, khi, key0, key1);
 }
 
 // ---------------------------------------------------------------------------
@@ -624,15 +762,23 @@ hipError_t launch_permute(hipStream_t s, int64_t n, const int32_t *idx, const fl
   return hipGetLastError();
 }
 
-hipError_t launch_mask(hipStream_t s, const KGeom &G, const void *grid, int grid_f64,
-                       double wx, double wy, double wz, double hx, double hy, double hz,
-                       int64_t ncell, uint8_t *mask) {
+hipError_t launch_cube_mask(hipStream_t s, const KGeom &G, const void *grid, int grid_f64,
+                            int64_t nwords, uint32_t *bits) {
   if (grid_f64)
-    k_mask<double><<<grid_for(ncell), kBlock, 0, s>>>(G, (const double *)grid, wx, wy, wz, hx,
-                                                      hy, hz, ncell, mask);
+    k_cube_mask<double><<<grid_for(nwords), kBlock, 0, s>>>(G, (const double *)grid, nwords, bits);
   else
-    k_mask<float><<<grid_for(ncell), kBlock, 0, s>>>(G, (const float *)grid, wx, wy, wz, hx, hy,
-                                                     hz, ncell, mask);
+    k_cube_mask<float><<<grid_for(nwords), kBlock, 0, s>>>(G, (const float *)grid, nwords, bits);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_flagged(hipStream_t s, const KGeom &G, int grid_f64, int64_t nf,
+                                const float4 *pos4, const uint32_t *bits,
+                                unsigned long long *out) {
+  if (nf <= 0) return hipSuccess;
+  if (grid_f64)
+    k_count_flagged<double><<<grid_for(nf), kBlock, 0, s>>>(G, nf, pos4, bits, out);
+  else
+    k_count_flagged<float><<<grid_for(nf), kBlock, 0, s>>>(G, nf, pos4, bits, out);
   return hipGetLastError();
 }
 
@@ -658,20 +804,25 @@ hipError_t launch_check_phi(hipStream_t s, const KGeom &G, const void *grid, int
   return hipGetLastError();
 }
 
+// Grid of 8k blocks covering n items with the XCD mapping of xcd_block().
+inline unsigned xcd_grid(int64_t n, int block) {
+  const int64_t nb = (n + block - 1) / block;
+  return (unsigned)(((nb + 7) / 8) * 8);
+}
+
 hipError_t launch_integrate(hipStream_t s, const KGeom &G, const KParams &P, int64_t nf,
                             float4 *pos4, const float4 *vel4, const float4 *frc4, float4 *vt4,
                             int32_t *cell_of, int32_t *rank_of, int32_t *count,
-                            const uint8_t *mask, int use_mask, const void *grid, int grid_f64,
+                            const uint32_t *bits, int use_mask, const void *grid, int grid_f64,
                             Status *st) {
   if (nf <= 0) return hipSuccess;
+  const unsigned nb = xcd_grid(nf, kBlock);
   if (grid_f64)
-    k_integrate<double><<<grid_for(nf), kBlock, 0, s>>>(G, P, nf, pos4, vel4, frc4, vt4, cell_of,
-                                                        rank_of, count, mask, use_mask,
-                                                        (const double *)grid, st);
+    k_integrate<double><<<nb, kBlock, 0, s>>>(G, P, nf, pos4, vel4, frc4, vt4, cell_of, rank_of,
+                                              count, bits, use_mask, (const double *)grid, st);
   else
-    k_integrate<float><<<grid_for(nf), kBlock, 0, s>>>(G, P, nf, pos4, vel4, frc4, vt4, cell_of,
-                                                       rank_of, count, mask, use_mask,
-                                                       (const float *)grid, st);
+    k_integrate<float><<<nb, kBlock, 0, s>>>(G, P, nf, pos4, vel4, frc4, vt4, cell_of, rank_of,
+                                             count, bits, use_mask, (const float *)grid, st);
   return hipGetLastError();
 }
 
@@ -683,14 +834,13 @@ hipError_t launch_force(hipStream_t s, const KGeom &G, const KParams &P, int64_t
   if (nf <= 0) return hipSuccess;
   const uint32_t klo = (uint32_t)k;
   const uint32_t khi = ((uint32_t)(k >> 32) & 0xFFFFu) | (P.replica << 16);
+  const unsigned nb = xcd_grid(nf, kForceBlock);
   if (init)
-    k_force<true><<<grid_for(nf), kBlock, 0, s>>>(G, P, nf, pos4, vt4, vel4, frc4, idx, cstart,
-                                                  wpos4, wcstart, pos_out, vel_out, frc_out, klo,
-                                                  khi, st);
+    k_force<true><<<nb, kForceBlock, 0, s>>>(G, P, nf, pos4, vt4, vel4, frc4, idx, cstart, wpos4,
+                                             wcstart, pos_out, vel_out, frc_out, klo, khi, st);
   else
-    k_force<false><<<grid_for(nf), kBlock, 0, s>>>(G, P, nf, pos4, vt4, vel4, frc4, idx, cstart,
-                                                   wpos4, wcstart, pos_out, vel_out, frc_out,
-                                                   klo, khi, st);
+    k_force<false><<<nb, kForceBlock, 0, s>>>(G, P, nf, pos4, vt4, vel4, frc4, idx, cstart, wpos4,
+                                              wcstart, pos_out, vel_out, frc_out, klo, khi, st);
   return hipGetLastError();
 }
 
@@ -701,6 +851,16 @@ hipError_t launch_pairs(hipStream_t s, const KGeom &G, const KParams &P, int64_t
   if (nf <= 0) return hipSuccess;
   k_pairs<<<grid_for(nf), kBlock, 0, s>>>(G, P, nf, pos4, idx, cstart, wpos4, wcstart, pairs,
                                           cap, counter);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_random(hipStream_t s, uint64_t seed, uint64_t k, uint32_t replica,
+                              const uint32_t *gi, const uint32_t *gj, int64_t n, uint32_t *words,
+                              float *xi) {
+  if (n <= 0) return hipSuccess;
+  const uint32_t khi = ((uint32_t)(k >> 32) & 0xFFFFu) | (replica << 16);
+  k_pair_random<<<grid_for(n), kBlock, 0, s>>>((uint32_t)seed, (uint32_t)(seed >> 32),
+                                                (uint32_t)k, khi, gi, gj, n, words, xi);
   return hipGetLastError();
 }
 

@@ -339,6 +339,36 @@ def test_edge_cases(dpd, oracle_lib):
     sim.close()
 
 
+def test_random_stream_matches_oracle(dpd, oracle_lib):
+    """The GPU's Philox4x32-10 words equal the oracle's bit for bit, and its
+    FP32 Box-Muller xi (hardware log2, sqrt and cos) stays within 3e-5 of the
+    oracle's FP64 xi (|xi| <= 5.8)."""
+    import torch
+    rng = np.random.default_rng(2)
+    n = 1 << 20
+    gi = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+    gj = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+    gi[:10] = gj[:10]              # equal gids too
+    dgi = torch.from_numpy(gi.view(np.int32)).cuda()
+    dgj = torch.from_numpy(gj.view(np.int32)).cuda()
+    worst = 0.0
+    for seed, k, rep in [(1234, 0, 0), (2**40 + 7, 2**33 + 5, 17), (2**64 - 1, 2**48 - 1, 65535)]:
+        words = torch.empty((n, 4), dtype=torch.int32, device="cuda")
+        xi = torch.empty(n, dtype=torch.float32, device="cuda")
+        dpd.binding.dpd_pair_random(seed, k, rep, dgi, dgj, words, xi)
+        torch.cuda.synchronize()
+        w_or, xi_or = oracle_lib.pairs_random(seed, gi, gj, k, rep)
+        assert np.array_equal(words.cpu().numpy().view(np.uint32), w_or)
+        d = np.abs(xi.cpu().numpy().astype(np.float64) - xi_or)
+        worst = max(worst, float(d.max()))
+        # symmetric in (i, j)
+        xi_sw = torch.empty(n, dtype=torch.float32, device="cuda")
+        dpd.binding.dpd_pair_random(seed, k, rep, dgj, dgi, None, xi_sw)
+        assert torch.equal(xi, xi_sw)
+    say("max |xi_gpu - xi_oracle| = %.3g" % worst)
+    assert worst < 3e-5
+
+
 def test_kernel_timing_and_copy_probe(dpd):
     import torch
     s = workloads.slab_system()

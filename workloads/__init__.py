@@ -342,14 +342,21 @@ def gaussian_random_field(n, h, corr_len, rng, dtype=np.float32):
 
 def porous_system(Lbox=128.0, rho=4.0, h=0.25, width=0.5, corr_len=6.0,
                   porosity=0.35, wall_band=1.5, seed_field=20, seed_particles=21,
-                  params=None, name=None):
+                  params=None, name=None, device=None):
     """Porous medium: a thresholded Gaussian random field (correlation length
     6) with fluid where the field is below its `porosity` quantile; wall
     particles at the fluid density within `wall_band` of the interface.
 
     The signed distance near the interface is (thr - f)/|grad f| (central
     differences), clipped to +-3, where phi = tanh(d/0.5) is saturated.
+
+    device: a torch device ("cuda") builds the same construction with torch
+    on that device (its own seeded generator, so the values differ from the
+    numpy path but the statistics are the same); used for the large boxes.
     """
+    if device is not None:
+        return _porous_system_torch(Lbox, rho, h, width, corr_len, porosity, wall_band,
+                                    seed_field, seed_particles, params, name, device)
     L = np.array([Lbox, Lbox, Lbox], dtype=np.float64)
     n = _grid_nodes(L, (h, h, h))
     rng = np.random.default_rng(seed_field)
@@ -471,3 +478,85 @@ def bulk_system(L=(8.0, 8.0, 8.0), rho=3.0, h=0.5, seed=3, params=None,
     params = params or default_params(seed=seed)
     return _assemble(name, L, cand, np.zeros((0, 3)), params["kBT"], rng, phi,
                      (h, h, h), params, {})
+
+
+def _porous_system_torch(Lbox, rho, h, width, corr_len, porosity, wall_band, seed_field,
+                         seed_particles, params, name, device):
+    import torch
+    dev = torch.device(device)
+    L = np.array([Lbox, Lbox, Lbox], dtype=np.float64)
+    n = _grid_nodes(L, (h, h, h))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(int(seed_field))
+    shape = (int(n[2]), int(n[1]), int(n[0]))
+    f = torch.randn(shape, generator=gen, device=dev, dtype=torch.float32)
+    spec = torch.fft.rfftn(f)
+    del f
+    c = corr_len * corr_len / 4.0
+    kz = 2 * math.pi * torch.fft.fftfreq(shape[0], d=h, device=dev)
+    ky = 2 * math.pi * torch.fft.fftfreq(shape[1], d=h, device=dev)
+    kx = 2 * math.pi * torch.fft.rfftfreq(shape[2], d=h, device=dev)
+    spec *= torch.exp(-c * kz * kz)[:, None, None]
+    spec *= torch.exp(-c * ky * ky)[None, :, None]
+    spec *= torch.exp(-c * kx * kx)[None, None, :]
+    f = torch.fft.irfftn(spec, s=shape)
+    del spec
+    f = (f - f.mean()) / f.std()
+    flat = f.reshape(-1)
+    sample = flat[:: max(1, flat.numel() // 4_000_000)]
+    thr = torch.quantile(sample, porosity)
+    g2 = torch.zeros_like(f)
+    for ax in range(3):
+        gax = (torch.roll(f, -1, dims=ax) - torch.roll(f, 1, dims=ax)) * (0.5 / h)
+        g2 += gax * gax
+        del gax
+    g2 = torch.sqrt(g2).clamp_(min=1e-6)
+    d = ((thr - f) / g2).clamp_(-3.0, 3.0)
+    del f, g2
+    phi = torch.tanh(d * (1.0 / width))
+    pgen = torch.Generator(device=dev)
+    pgen.manual_seed(int(seed_particles))
+    ncand = int(round(rho * float(np.prod(L))))
+    cand = torch.rand((ncand, 3), generator=pgen, device=dev, dtype=torch.float64) * float(Lbox)
+
+    def cmm(grid):
+        i0 = torch.floor(cand / h).long()
+        mn = torch.full((ncand,), float("inf"), device=dev)
+        mx = torch.full((ncand,), float("-inf"), device=dev)
+        for dz in (0, 1):
+            kk = (i0[:, 2] + dz) % shape[0]
+            for dy in (0, 1):
+                jj = (i0[:, 1] + dy) % shape[1]
+                for dx in (0, 1):
+                    ii = (i0[:, 0] + dx) % shape[2]
+                    v = grid[kk, jj, ii]
+                    mn = torch.minimum(mn, v)
+                    mx = torch.maximum(mx, v)
+        return mn, mx
+
+    mn, mx = cmm(phi)
+    fl = mn > 0.0
+    dmin, _ = cmm(d)
+    wl = (mx < 0.0) & (dmin > -wall_band)
+    del d
+    fluid = cand[fl].cpu().numpy()
+    wall = cand[wl].cpu().numpy()
+    nf, nw = fluid.shape[0], wall.shape[0]
+    vel = torch.randn((nf, 3), generator=pgen, device=dev, dtype=torch.float64)
+    vel = vel - vel.mean(dim=0, keepdim=True)
+    perm = torch.randperm(nf + nw, generator=pgen, device=dev)
+    phi_np = phi.cpu().numpy()
+    del phi
+    params = params or default_params(a_ff=25.0, a_fs=35.0, g=(0.005, 0, 0),
+                                      seed=seed_particles)
+    pos = np.concatenate([fluid, wall], axis=0)
+    pos32 = np.mod(pos, Lbox).astype(np.float32)
+    pos32[pos32 >= np.float32(Lbox)] = np.float32(0.0)
+    velall = np.zeros_like(pos32)
+    velall[:nf] = (vel * math.sqrt(params["kBT"])).cpu().numpy().astype(np.float32)
+    typ = np.concatenate([np.zeros(nf, np.int32), np.ones(nw, np.int32)])
+    return System(name=name or f"porous_grf_{int(Lbox)}", L=L, pos=pos32, vel=velall, type=typ,
+                  gid=perm.cpu().numpy().astype(np.uint32), phi=phi_np,
+                  h=np.array([h, h, h]), params=params,
+                  meta=dict(porosity=porosity, corr_len=corr_len, threshold=float(thr),
+                            n_fluid=int(nf), n_wall=int(nw), generator="torch"))

@@ -90,6 +90,9 @@ def main():
                     help="steps of the per-kernel HIP-event pass")
     ap.add_argument("--cpu-steps", type=int, default=2,
                     help="oracle steps of the CPU baseline (0 skips it)")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="after the run, copy this many MiB with the library's plain copy "
+                         "kernel (the reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -144,6 +147,16 @@ def main():
     step_gbs = b_alg / (ms_per_step * 1e-3) / 1e9
     log("pairs %d (%.2f per fluid), candidates %d, phi lookups/step %.0f, B_alg %.1f MB"
         % (pairs, pairs / max(nf, 1), cands, lookups, b_alg / 1e6))
+
+    if args.copy_probe_mb > 0:
+        from paper_1807_09896_amd import binding
+        nbytes = args.copy_probe_mb << 20
+        a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        binding.dpd_copy_probe(b, a, nbytes)
+        torch.cuda.synchronize()
+        log("copy probe: %d bytes read and written by k_copy16" % nbytes)
+        del a, b
 
     prof_dir = os.path.join(ROOT, "profiles")
     traffic = None

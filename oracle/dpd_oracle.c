@@ -343,16 +343,18 @@ static void free_cells(orc_cells *C)
 
 /* FP32 pair decision on shadow positions: with j seen from i's neighbour
  * cell at image shift s (per axis -1, 0, +1),
- *   dx = fl(x_i - fl(x_j + s L)),  r2 = fl(fl(fl(dx^2) + fl(dy^2)) + fl(dz^2)),
- * and the pair is in range iff r2 < fl32(rc^2). */
+ *   dx = fl(fl(x_i - s L) - x_j),  r2 = fma(dz, dz, fma(dy, dy, fl(dx^2)))
+ * (each fma rounded once), and the pair is in range iff r2 < fl32(rc^2). */
 static int pair_in_range32(const orc_geom *G, const float *xi, const float *xj,
                            const int s[3], float rc2)
 {
-    float dx = xi[0] - (xj[0] + (float)s[0] * G->L32[0]);
-    float dy = xi[1] - (xj[1] + (float)s[1] * G->L32[1]);
-    float dz = xi[2] - (xj[2] + (float)s[2] * G->L32[2]);
-    float r2 = dx * dx + dy * dy;
-    r2 = r2 + dz * dz;
+    float ax = xi[0] - (float)s[0] * G->L32[0];
+    float ay = xi[1] - (float)s[1] * G->L32[1];
+    float az = xi[2] - (float)s[2] * G->L32[2];
+    float dx = ax - xj[0];
+    float dy = ay - xj[1];
+    float dz = az - xj[2];
+    float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
     return r2 < rc2;
 }
 

@@ -14,7 +14,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libdpdphi.so")
+# DPD_LIB overrides the library path (e.g. to compare builds of the kernels)
+LIB_PATH = os.environ.get("DPD_LIB") or os.path.join(_HERE, "libdpdphi.so")
 
 DPD_OK = 0
 DPD_E_INVAL = -1

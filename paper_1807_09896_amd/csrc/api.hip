@@ -8,7 +8,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/dpd.h"
+#include "dpd.h"
 #include "device.h"
 #include "kernels.h"
 
@@ -56,8 +56,11 @@ struct dpd_ctx {
   int32_t *cell_of = nullptr, *rank_of = nullptr, *count = nullptr, *cstart = nullptr,
           *idx = nullptr, *bsum = nullptr;
   int nscan = 0;
-  float4 *wpos = nullptr;
-  int32_t *wcstart = nullptr;
+  int32_t *wcstart = nullptr;   // exclusive scan of wall counts per cell (static)
+  int32_t *wcell = nullptr;     // cell of each cell-sorted wall (static)
+  int32_t *idx_all = nullptr;   // merged per-cell runs: walls (nf + w), then fluid
+  int32_t *start_all = nullptr; // start of each cell's merged run
+  int32_t *fluid_off = nullptr; // start of each cell's fluid part in the merged run
   void *grid = nullptr;
   uint32_t *bits = nullptr;   // near-interface grid cubes, one bit each
   int64_t nwords = 0;
@@ -228,14 +231,20 @@ int scan_scatter_sort(dpd_ctx *c) {
           }));
   HIP_TRY(c, timed(c, K_SCAN_TOP, [&] { return dpd::launch_scan_top(c->stream, c->nscan, c->bsum); }));
   HIP_TRY(c, timed(c, K_SCAN_DOWN, [&] {
-            return dpd::launch_scan_down(c->stream, c->ncell, c->count, c->cstart, c->bsum);
+            return dpd::launch_scan_down(c->stream, c->ncell, c->count, c->cstart, c->bsum,
+                                         c->wcstart, c->start_all, c->fluid_off);
           }));
   HIP_TRY(c, timed(c, K_SCATTER, [&] {
             return dpd::launch_scatter(c->stream, c->nf, c->cell_of, c->rank_of, c->cstart,
                                        c->idx);
           }));
   HIP_TRY(c, timed(c, K_SORT, [&] {
-            return dpd::launch_sort_cells(c->stream, c->ncell, c->cstart, c->idx);
+            return dpd::launch_sort_cells(c->stream, c->ncell, c->cstart, c->idx, c->fluid_off,
+                                          c->idx_all);
+          }));
+  HIP_TRY(c, timed(c, K_OTHER, [&] {
+            return dpd::launch_fill_walls(c->stream, c->nw, c->nf, c->wcell, c->wcstart,
+                                          c->start_all, c->idx_all);
           }));
   return DPD_OK;
 }
@@ -244,9 +253,9 @@ int scan_scatter_sort(dpd_ctx *c) {
 int force_pass(dpd_ctx *c, int init) {
   const int a = c->cur, b = 1 - c->cur;
   HIP_TRY(c, timed(c, K_FORCE, [&] {
-            return dpd::launch_force(c->stream, c->G, c->P, c->nf, init, c->pos[a], c->vt,
-                                     c->vel[a], c->frc[a], c->idx, c->cstart, c->wpos,
-                                     c->wcstart, c->pos[b], c->vel[b], c->frc[b], c->k,
+            return dpd::launch_force(c->stream, c->G, c->P, c->nf, c->nw, init, c->pos[a], c->vt,
+                                     c->vel[a], c->frc[a], c->idx, c->idx_all, c->start_all,
+                                     c->pos[b], c->vel[b], c->frc[b], c->k,
                                      c->status);
           }));
   c->cur = b;
@@ -437,11 +446,11 @@ int dpd_create(const dpd_box *box, const dpd_particles *pp, const dpd_params *pr
   const size_t nf = (size_t)c->nf, nw = (size_t)c->nw;
   const size_t gbytes = (size_t)phi->n[0] * phi->n[1] * phi->n[2] * (size_t)phi->dtype;
   for (int b = 0; b < 2; ++b) {
-    c->pos[b] = (float4 *)dalloc(c, 16 * nf);
+    c->pos[b] = (float4 *)dalloc(c, 16 * (nf + nw + 1));
     c->vel[b] = (float4 *)dalloc(c, 16 * nf);
     c->frc[b] = (float4 *)dalloc(c, 16 * nf);
   }
-  c->vt = (float4 *)dalloc(c, 16 * nf);
+  c->vt = (float4 *)dalloc(c, 16 * (nf + nw + 1));
   c->cell_of = (int32_t *)dalloc(c, 4 * (nf > nw ? nf : nw));
   c->rank_of = (int32_t *)dalloc(c, 4 * (nf > nw ? nf : nw));
   c->idx = (int32_t *)dalloc(c, 4 * (nf > nw ? nf : nw));
@@ -449,8 +458,11 @@ int dpd_create(const dpd_box *box, const dpd_particles *pp, const dpd_params *pr
   c->cstart = (int32_t *)dalloc(c, 4 * ((size_t)ncell + 1));
   c->nscan = dpd::scan_blocks(ncell);
   c->bsum = (int32_t *)dalloc(c, 4 * (size_t)c->nscan);
-  c->wpos = (float4 *)dalloc(c, 16 * nw);
   c->wcstart = (int32_t *)dalloc(c, 4 * ((size_t)ncell + 1));
+  c->wcell = (int32_t *)dalloc(c, 4 * nw);
+  c->idx_all = (int32_t *)dalloc(c, 4 * (nf + nw));
+  c->start_all = (int32_t *)dalloc(c, 4 * ((size_t)ncell + 1));
+  c->fluid_off = (int32_t *)dalloc(c, 4 * (size_t)ncell);
   c->grid = dalloc(c, gbytes);
   c->nwords = ((int64_t)phi->n[0] * phi->n[1] * phi->n[2] + 31) / 32;
   c->bits = (uint32_t *)dalloc(c, 4 * (size_t)c->nwords);
@@ -459,7 +471,7 @@ int dpd_create(const dpd_box *box, const dpd_particles *pp, const dpd_params *pr
   for (int b = 0; b < 2; ++b)
     if (!c->pos[b] || !c->vel[b] || !c->frc[b]) return bail(fail(c, DPD_E_NOMEM, "device allocation failed"));
   if (!c->vt || !c->cell_of || !c->rank_of || !c->idx || !c->count || !c->cstart || !c->bsum ||
-      !c->wpos || !c->wcstart || !c->grid || !c->bits || !c->status || !c->pair_counter)
+      !c->wcell || !c->idx_all || !c->start_all || !c->fluid_off || !c->wcstart || !c->grid || !c->bits || !c->status || !c->pair_counter)
     return bail(fail(c, DPD_E_NOMEM, "device allocation failed"));
 
   // ---- upload ----
@@ -507,15 +519,27 @@ int dpd_create(const dpd_box *box, const dpd_particles *pp, const dpd_params *pr
     }
     chk(dpd::launch_scan_reduce(c->stream, ncell, c->count, c->bsum), "scan");
     chk(dpd::launch_scan_top(c->stream, c->nscan, c->bsum), "scan");
-    chk(dpd::launch_scan_down(c->stream, ncell, c->count, c->wcstart, c->bsum), "scan");
+    chk(dpd::launch_scan_down(c->stream, ncell, c->count, c->wcstart, c->bsum, nullptr, nullptr,
+                              nullptr),
+        "scan");
     if (nw > 0) {
+      // walls sorted by cell into the tail of both position buffers (static),
+      // with zero predicted velocity
       chk(dpd::launch_scatter(c->stream, (int64_t)nw, c->cell_of, c->rank_of, c->wcstart, c->idx),
           "scatter walls");
-      chk(dpd::launch_sort_cells(c->stream, ncell, c->wcstart, c->idx), "sort walls");
-      chk(dpd::launch_permute(c->stream, (int64_t)nw, c->idx, wtmp, c->wpos, nullptr, nullptr,
-                              nullptr, nullptr),
+      chk(dpd::launch_sort_cells(c->stream, ncell, c->wcstart, c->idx, nullptr, nullptr),
+          "sort walls");
+      chk(dpd::launch_permute(c->stream, (int64_t)nw, c->idx, wtmp, c->pos[0] + nf, nullptr,
+                              nullptr, nullptr, nullptr),
           "permute walls");
+      chk(hipMemcpyAsync(c->pos[1] + nf, c->pos[0] + nf, 16 * nw, hipMemcpyDeviceToDevice,
+                         c->stream),
+          "copy walls");
+      chk(dpd::launch_fill_zero(c->stream, c->vt + nf, 16 * nw), "zero wall velocities");
+      chk(dpd::launch_cells(c->stream, c->G, (int64_t)nw, c->pos[0] + nf, c->wcell), "wall cells");
     }
+    chk(dpd::launch_set_pad(c->stream, c->pos[0] + nf + nw, c->vt + nf + nw), "pad");
+    chk(dpd::launch_set_pad(c->stream, c->pos[1] + nf + nw, nullptr), "pad");
     chk(hipStreamSynchronize(c->stream), "sync");
     for (void *q : {(void *)dpos, (void *)dvel, (void *)dgid, (void *)drows_f, (void *)drows_w,
                     (void *)wtmp})
@@ -586,7 +610,8 @@ int dpd_get_state(dpd_ctx *c, float *pos, float *vel, int32_t *events, int32_t *
   if (!c) return DPD_E_INVAL;
   HIP_TRY(c, dpd::launch_export(c->stream, c->G, c->nf, c->pos[c->cur], c->vel[c->cur],
                                 c->frc[c->cur], 0, pos, vel, nullptr, events, cell_of));
-  HIP_TRY(c, dpd::launch_export(c->stream, c->G, c->nw, c->wpos, nullptr, nullptr, 1, pos, vel,
+  HIP_TRY(c, dpd::launch_export(c->stream, c->G, c->nw, c->pos[c->cur] + c->nf, nullptr, nullptr,
+                                1, pos, vel,
                                 nullptr, events, cell_of));
   return latched_error(c);
 }
@@ -644,8 +669,8 @@ int dpd_neighbor_pairs(dpd_ctx *c, uint32_t *pairs, int64_t cap, int64_t *count)
                              c->count));
   int rc = scan_scatter_sort(c);
   if (rc) return rc;
-  HIP_TRY(c, dpd::launch_pairs(c->stream, c->G, c->P, c->nf, c->pos[c->cur], c->idx, c->cstart,
-                               c->wpos, c->wcstart, pairs, cap, c->pair_counter));
+  HIP_TRY(c, dpd::launch_pairs(c->stream, c->G, c->P, c->nf, c->pos[c->cur], c->idx, c->idx_all,
+                               c->start_all, pairs, cap, c->pair_counter));
   unsigned long long cnt = 0;
   HIP_TRY(c, hipMemcpyAsync(&cnt, c->pair_counter, 8, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));

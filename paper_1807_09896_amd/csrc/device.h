@@ -124,12 +124,11 @@ __device__ __forceinline__ float drift1(float x, float v, float f, float hdt, fl
   return wrap1(y, L);
 }
 
-// Pair decision: r2 = fl(fl(fl(dx^2) + fl(dy^2)) + fl(dz^2)) with
-// d = fl(x_i - x_j'), x_j' = fl(x_j + s L) precomputed per neighbour cell.
+// Pair decision: r2 = fma(dz, dz, fma(dy, dy, fl(dx^2))) with
+// d = fl(x_i' - x_j), x_i' = fl(x_i - s L) taken once per neighbour cell.
 __device__ __forceinline__ float pair_r2(float dx, float dy, float dz) {
 #pragma clang fp contract(off)
-  const float s = dx * dx + dy * dy;
-  return s + dz * dz;
+  return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
 }
 
 __device__ __forceinline__ float sub_nc(float a, float b) {

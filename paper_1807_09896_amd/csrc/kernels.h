@@ -31,12 +31,26 @@ hipError_t launch_bin(hipStream_t s, const KGeom &G, int64_t n, const float4 *po
 hipError_t launch_scan_reduce(hipStream_t s, int64_t ncell, const int32_t *count, int32_t *bsum);
 hipError_t launch_scan_top(hipStream_t s, int nblocks, int32_t *bsum);
 hipError_t launch_scan_down(hipStream_t s, int64_t ncell, int32_t *count, int32_t *start,
-                            const int32_t *bsum);
+                            const int32_t *bsum, const int32_t *wstart, int32_t *start_all,
+                            int32_t *fluid_off);
 
-// idx[start[cell_of[p]] + rank_of[p]] = p, then each cell's run sorted by p.
+// idx[start[cell_of[p]] + rank_of[p]] = p, then each cell's run sorted by p
+// (and copied to the fluid part of the merged run when idx_all is given).
 hipError_t launch_scatter(hipStream_t s, int64_t n, const int32_t *cell_of,
                           const int32_t *rank_of, const int32_t *start, int32_t *idx);
-hipError_t launch_sort_cells(hipStream_t s, int64_t ncell, const int32_t *start, int32_t *idx);
+hipError_t launch_sort_cells(hipStream_t s, int64_t ncell, const int32_t *start, int32_t *idx,
+                             const int32_t *fluid_off, int32_t *idx_all);
+
+// Wall part of the merged per-cell runs (walls stored at index nf + w).
+hipError_t launch_fill_walls(hipStream_t s, int64_t nw, int64_t nf, const int32_t *wcell,
+                             const int32_t *wstart, const int32_t *start_all, int32_t *idx_all);
+
+// Write the pad entry (far-away position, zero velocity) at pos4[0], vt4[0].
+hipError_t launch_set_pad(hipStream_t s, float4 *pos4, float4 *vt4);
+
+// Cell index of each position.
+hipError_t launch_cells(hipStream_t s, const KGeom &G, int64_t n, const float4 *pos4,
+                        int32_t *cell);
 
 // out[s] = in[idx[s]] for up to three float4 arrays (NULL skipped).
 hipError_t launch_permute(hipStream_t s, int64_t n, const int32_t *idx, const float4 *a_in,
@@ -70,17 +84,19 @@ hipError_t launch_integrate(hipStream_t s, const KGeom &G, const KParams &P, int
 
 // Pair forces (Eq. 3-10) + body force + velocity update, writing the state
 // in cell-sorted slot order.  init = 1: forces only (velocities unchanged).
-hipError_t launch_force(hipStream_t s, const KGeom &G, const KParams &P, int64_t nf, int init,
+// pos4 and vt4 hold nf fluid entries, the nw walls and one pad entry.
+hipError_t launch_force(hipStream_t s, const KGeom &G, const KParams &P, int64_t nf, int64_t nw,
+                        int init,
                         const float4 *pos4, const float4 *vt4, const float4 *vel4,
-                        const float4 *frc4, const int32_t *idx, const int32_t *cstart,
-                        const float4 *wpos4, const int32_t *wcstart, float4 *pos_out,
-                        float4 *vel_out, float4 *frc_out, uint64_t k, Status *st);
+                        const float4 *frc4, const int32_t *idx, const int32_t *idx_all,
+                        const int32_t *start_all, float4 *pos_out, float4 *vel_out,
+                        float4 *frc_out, uint64_t k, Status *st);
 
 // Interacting pairs (gid_i, gid_j) from each fluid particle.
 hipError_t launch_pairs(hipStream_t s, const KGeom &G, const KParams &P, int64_t nf,
-                        const float4 *pos4, const int32_t *idx, const int32_t *cstart,
-                        const float4 *wpos4, const int32_t *wcstart, uint32_t *pairs,
-                        int64_t cap, unsigned long long *counter);
+                        const float4 *pos4, const int32_t *idx, const int32_t *idx_all,
+                        const int32_t *start_all, uint32_t *pairs, int64_t cap,
+                        unsigned long long *counter);
 
 // Random numbers of given pairs: Philox words (n x 4) and xi (n), either NULL.
 hipError_t launch_pair_random(hipStream_t s, uint64_t seed, uint64_t k, uint32_t replica,

@@ -7,7 +7,10 @@
 // state of slot s (the s-th particle of the cell list) to slot s of the next
 // buffers, so each step's integrate kernel streams a nearly sorted array and
 // the force kernel's gathers of neighbour cells hit consecutive addresses.
-// Frozen wall particles are sorted by cell once, at create.
+// Frozen wall particles are sorted by cell once, at create, and stored after
+// the fluid in the position and predicted-velocity arrays (index nf + w, with
+// zero predicted velocity), so that one merged list per cell (walls first,
+// then fluid) serves the neighbour search without a fluid/wall branch.
 #include <hip/hip_runtime.h>
 
 #include "device.h"
@@ -126,10 +129,14 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_top(int nb, int32_t *__re
 }
 
 // Each thread owns kScanItems consecutive cells; the block's cells are read
-// through LDS so that global loads and stores stay coalesced.
-__global__ __launch_bounds__(kScanThreads) void k_scan_down(int64_t n, int32_t *__restrict__ count,
-                                                            int32_t *__restrict__ start,
-                                                            const int32_t *__restrict__ bsum) {
+// through LDS so that global loads and stores stay coalesced.  With wall
+// offsets wstart (exclusive scan of the static wall counts) it also writes
+// the merged runs: start_all[c] = start[c] + wstart[c] begins cell c's run of
+// walls then fluid, fluid_off[c] = start_all[c] + (walls in c) its fluid part.
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(
+    int64_t n, int32_t *__restrict__ count, int32_t *__restrict__ start,
+    const int32_t *__restrict__ bsum, const int32_t *__restrict__ wstart,
+    int32_t *__restrict__ start_all, int32_t *__restrict__ fluid_off) {
   __shared__ int tile[kScanChunk + kScanChunk / 32];
   __shared__ int lds[kScanThreads];
   const int64_t base = (int64_t)blockIdx.x * kScanChunk;
@@ -162,10 +169,20 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(int64_t n, int32_t *
   for (int k = 0; k < kScanItems; ++k) {
     const int local = k * kScanThreads + threadIdx.x;
     const int64_t i = base + local;
-    if (i < n) start[i] = tile[local + local / 32];
+    if (i < n) {
+      const int st = tile[local + local / 32];
+      start[i] = st;
+      if (wstart) {
+        const int w0 = wstart[i], w1 = wstart[i + 1];
+        start_all[i] = st + w0;
+        fluid_off[i] = st + w1;
+      }
+    }
   }
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kScanThreads - 1)
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kScanThreads - 1) {
     start[n] = bsum[blockIdx.x] + total;
+    if (wstart) start_all[n] = bsum[blockIdx.x] + total + wstart[n];
+  }
 }
 
 __global__ void k_scatter(int64_t n, const int32_t *__restrict__ cell_of,
@@ -177,9 +194,11 @@ __global__ void k_scatter(int64_t n, const int32_t *__restrict__ cell_of,
 }
 
 // Atomic ranks arrive in any order: sort each cell's run by storage index so
-// that the cell list, and every sum over it, is deterministic.
+// that the cell list, and every sum over it, is deterministic.  With idx_all
+// the sorted run is also written to the fluid part of the merged run.
 __global__ void k_sort_cells(int64_t ncell, const int32_t *__restrict__ start,
-                             int32_t *__restrict__ idx) {
+                             int32_t *__restrict__ idx, const int32_t *__restrict__ fluid_off,
+                             int32_t *__restrict__ idx_all) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncell) return;
   const int a = start[c], b = start[c + 1];
@@ -192,6 +211,37 @@ __global__ void k_sort_cells(int64_t ncell, const int32_t *__restrict__ start,
     }
     idx[j + 1] = v;
   }
+  if (idx_all) {
+    const int o = fluid_off[c];
+    for (int i = a; i < b; ++i) idx_all[o + (i - a)] = idx[i];
+  }
+}
+
+// Wall part of the merged runs: wall w (cell-sorted, cell wcell[w]) is index
+// nf + w of the position arrays.
+__global__ void k_fill_walls(int64_t nw, int64_t nf, const int32_t *__restrict__ wcell,
+                             const int32_t *__restrict__ wstart,
+                             const int32_t *__restrict__ start_all, int32_t *__restrict__ idx_all) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= nw) return;
+  const int c = wcell[w];
+  idx_all[start_all[c] + ((int)w - wstart[c])] = (int32_t)(nf + w);
+}
+
+// The pad entry after fluid and walls: a position far outside the box, so
+// that a batch past the end of a run never tests as a neighbour.
+__global__ void k_set_pad(float4 *pos4, float4 *vt4) {
+  *pos4 = make_float4(1e30f, 1e30f, 1e30f, __uint_as_float(0xFFFFFFFFu));
+  if (vt4) *vt4 = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+__global__ void k_cells(const KGeom G, int64_t n, const float4 *__restrict__ pos4,
+                        int32_t *__restrict__ cell) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const float4 x = pos4[p];
+  int cx, cy, cz;
+  cell[p] = cell_index(G, x.x, x.y, x.z, cx, cy, cz);
 }
 
 __global__ void k_permute(int64_t n, const int32_t *__restrict__ idx, const float4 *a_in,
@@ -366,19 +416,27 @@ __global__ __launch_bounds__(kBlock) void k_count_flagged(const KGeom G, int64_t
 // ---------------------------------------------------------------------------
 // Pair force (Eq. 3-10), body force, velocity update
 //
-// One thread per fluid particle i, in cell-sorted slot order.  The 27
-// neighbour cells are scanned for candidates (fluid run, then wall run of
-// each cell) with the FP32 cutoff decision; hits are appended to the
-// thread's column of an LDS list (slot-major, so a wavefront's appends touch
-// 64 different banks).  When the list is full or the scan is done, the
-// thread evaluates the listed pairs densely: the random number and force
-// arithmetic run only for pairs inside the cutoff, and a wavefront's lanes
-// stay converged for min(count) iterations instead of diverging on every
-// candidate.  Sums run in candidate order, so results are deterministic.
+// One thread per fluid particle i, in cell-sorted slot order; a wavefront is
+// 64 consecutive particles.  Phase A: each lane scans the merged runs (walls
+// then fluid) of its 27 neighbour cells with the FP32 cutoff decision, four
+// run entries at a time so that their loads overlap, and appends the hits to
+// its column of an LDS list (slot-major, so the wavefront's appends fall in
+// different banks).  Phase B: the lane evaluates its listed pairs; the
+// random-number and force arithmetic runs only for pairs inside the cutoff,
+// so the wavefront pays for max(hits) iterations instead of diverging on
+// every candidate.  Sums run in candidate order, so runs are deterministic.
+// If a list fills, phases A and B alternate until the scan is done.
 // ---------------------------------------------------------------------------
 constexpr int kForceBlock = 256;
 constexpr int kListCap = 24;
-constexpr uint32_t kWallBit = 0x80000000u;
+constexpr int kBatch = 4;
+
+// Ordering point for LDS traffic between lanes of one wavefront.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 struct Acc {
   float x, y, z;
@@ -405,29 +463,28 @@ __device__ __forceinline__ float min_image(float d, float L) {
   return d > 0.5f * L ? d - L : (d < -0.5f * L ? d + L : d);
 }
 
-// Scan state of one thread over its 27 neighbour cells.
-struct Scan {
-  int nbr;         // next neighbour cell code, 0..27
-  int t, t_end;    // current run [t, t_end)
-  bool wall;       // current run is the wall run of the cell
-  int c;           // current cell
+// Neighbour cell `code` (0..26) of (cx, cy, cz): wrapped index and the image
+// shift s L of its particles as seen from the home cell.
+struct NCell {
+  int c;
   float sx, sy, sz;
 };
 
-__device__ __forceinline__ void scan_cell(const KGeom &G, int cx, int cy, int cz, int code,
-                                          Scan &S) {
+__device__ __forceinline__ NCell neighbour_cell(const KGeom &G, int cx, int cy, int cz, int code) {
   const int ox = code % 3 - 1, oy = (code / 3) % 3 - 1, oz = code / 9 - 1;
   int qx = cx + ox, qy = cy + oy, qz = cz + oz;
-  S.sx = 0.f;
-  S.sy = 0.f;
-  S.sz = 0.f;
-  if (qx < 0) { qx += G.nc[0]; S.sx = -G.L[0]; }
-  else if (qx >= G.nc[0]) { qx -= G.nc[0]; S.sx = G.L[0]; }
-  if (qy < 0) { qy += G.nc[1]; S.sy = -G.L[1]; }
-  else if (qy >= G.nc[1]) { qy -= G.nc[1]; S.sy = G.L[1]; }
-  if (qz < 0) { qz += G.nc[2]; S.sz = -G.L[2]; }
-  else if (qz >= G.nc[2]) { qz -= G.nc[2]; S.sz = G.L[2]; }
-  S.c = (qz * G.nc[1] + qy) * G.nc[0] + qx;
+  NCell n;
+  n.sx = 0.f;
+  n.sy = 0.f;
+  n.sz = 0.f;
+  if (qx < 0) { qx += G.nc[0]; n.sx = -G.L[0]; }
+  else if (qx >= G.nc[0]) { qx -= G.nc[0]; n.sx = G.L[0]; }
+  if (qy < 0) { qy += G.nc[1]; n.sy = -G.L[1]; }
+  else if (qy >= G.nc[1]) { qy -= G.nc[1]; n.sy = G.L[1]; }
+  if (qz < 0) { qz += G.nc[2]; n.sz = -G.L[2]; }
+  else if (qz >= G.nc[2]) { qz -= G.nc[2]; n.sz = G.L[2]; }
+  n.c = (qz * G.nc[1] + qy) * G.nc[0] + qx;
+  return n;
 }
 
 template <bool INIT>
@@ -435,10 +492,9 @@ __global__ __launch_bounds__(kForceBlock) void k_force(
     const KGeom G, const KParams P, int64_t nf, const float4 *__restrict__ pos4,
     const float4 *__restrict__ vt4, const float4 *__restrict__ vel4,
     const float4 *__restrict__ frc4, const int32_t *__restrict__ idx,
-    const int32_t *__restrict__ cstart, const float4 *__restrict__ wpos4,
-    const int32_t *__restrict__ wcstart, float4 *__restrict__ pos_out,
-    float4 *__restrict__ vel_out, float4 *__restrict__ frc_out, uint32_t klo, uint32_t khi,
-    Status *st) {
+    const int32_t *__restrict__ idx_all, const int32_t *__restrict__ start_all, int32_t pad,
+    float4 *__restrict__ pos_out, float4 *__restrict__ vel_out, float4 *__restrict__ frc_out,
+    uint32_t klo, uint32_t khi, Status *st) {
   __shared__ uint32_t list[kListCap * kForceBlock];
   const int64_t s = (int64_t)xcd_block() * kForceBlock + threadIdx.x;
   if (s >= nf) return;
@@ -450,79 +506,57 @@ __global__ __launch_bounds__(kForceBlock) void k_force(
   cell_index(G, pi.x, pi.y, pi.z, cx, cy, cz);
   uint32_t *mine = list + threadIdx.x;
   Acc acc = {0.f, 0.f, 0.f};
-  Scan S;
-  S.nbr = 0;
-  S.t = 0;
-  S.t_end = 0;
-  S.wall = true;
-  S.c = 0;
-  S.sx = S.sy = S.sz = 0.f;
+  int code = 0, t = 0, t_end = 0;
+  float ax = pi.x, ay = pi.y, az = pi.z;   // i shifted to the current cell's image
   bool done = false;
   while (!done) {
+    // phase A: candidates into the list, kBatch run entries at a time (a
+    // batch past the run's end reads the far-away pad particle)
     int cnt = 0;
-    while (cnt < kListCap) {
-      if (S.t >= S.t_end) {
-        if (!S.wall) {
-          // fluid run of this cell done: its wall run next
-          S.wall = true;
-          S.t = wcstart[S.c];
-          S.t_end = wcstart[S.c + 1];
-          continue;
-        }
-        if (S.nbr == 27) {
+    while (cnt <= kListCap - kBatch) {
+      if (t >= t_end) {
+        if (code == 27) {
           done = true;
           break;
         }
-        scan_cell(G, cx, cy, cz, S.nbr, S);
-        ++S.nbr;
-        S.wall = false;
-        S.t = cstart[S.c];
-        S.t_end = cstart[S.c + 1];
+        const NCell nc = neighbour_cell(G, cx, cy, cz, code);
+        ++code;
+        ax = sub_nc(pi.x, nc.sx);
+        ay = sub_nc(pi.y, nc.sy);
+        az = sub_nc(pi.z, nc.sz);
+        t = start_all[nc.c];
+        t_end = start_all[nc.c + 1];
         continue;
       }
-      float4 pj;
-      uint32_t tag;
-      if (S.wall) {
-        pj = wpos4[S.t];
-        tag = (uint32_t)S.t | kWallBit;
-      } else {
-        const int j = idx[S.t];
-        pj = pos4[j];
-        tag = (uint32_t)j;
-        if (j == i) tag = 0xFFFFFFFFu;
+      int jb[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) jb[u] = t + u < t_end ? idx_all[t + u] : pad;
+      float4 pb[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) pb[u] = pos4[jb[u]];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const float r2 = pair_r2(sub_nc(ax, pb[u].x), sub_nc(ay, pb[u].y), sub_nc(az, pb[u].z));
+        // r2 > 0 drops i itself (and coincident particles, whose force is 0)
+        if (r2 < P.rc2 && r2 > 0.0f) {
+          mine[cnt * kForceBlock] = (uint32_t)jb[u];
+          ++cnt;
+        }
       }
-      ++S.t;
-      const float dx = sub_nc(pi.x, add_nc(pj.x, S.sx));
-      const float dy = sub_nc(pi.y, add_nc(pj.y, S.sy));
-      const float dz = sub_nc(pi.z, add_nc(pj.z, S.sz));
-      const float r2 = pair_r2(dx, dy, dz);
-      if (r2 < P.rc2 && r2 > 0.0f && tag != 0xFFFFFFFFu) {
-        mine[cnt * kForceBlock] = tag;
-        ++cnt;
-      }
+      t += kBatch;
     }
-    // dense evaluation of the listed pairs
+    // phase B: the listed pairs of this lane
     for (int q = 0; q < cnt; ++q) {
-      const uint32_t tag = mine[q * kForceBlock];
-      float4 pj;
-      float dvx = vti.x, dvy = vti.y, dvz = vti.z;
-      float a;
-      if (tag & kWallBit) {
-        pj = wpos4[tag & ~kWallBit];
-        a = P.a_fw;
-      } else {
-        pj = pos4[tag];
-        const float4 vtj = vt4[tag];
-        dvx -= vtj.x;
-        dvy -= vtj.y;
-        dvz -= vtj.z;
-        a = P.a_ff;
-      }
+      const uint32_t j = mine[q * kForceBlock];
+      const float4 pj = pos4[j];
+      const float4 vtj = vt4[j];
       const float dx = min_image(pi.x - pj.x, G.L[0]);
       const float dy = min_image(pi.y - pj.y, G.L[1]);
       const float dz = min_image(pi.z - pj.z, G.L[2]);
       const float r2 = dx * dx + dy * dy + dz * dz;
-      add_pair(acc, dx, dy, dz, r2, dvx, dvy, dvz, a, P, gi, __float_as_uint(pj.w), klo, khi);
+      const float a = (int64_t)j < nf ? P.a_ff : P.a_fw;
+      add_pair(acc, dx, dy, dz, r2, vti.x - vtj.x, vti.y - vtj.y, vti.z - vtj.z, a, P, gi,
+               __float_as_uint(pj.w), klo, khi);
     }
   }
   const float fx = acc.x + P.g[0], fy = acc.y + P.g[1], fz = acc.z + P.g[2];
@@ -551,38 +585,25 @@ __global__ __launch_bounds__(kForceBlock) void k_force(
 // pairs are written.
 __device__ __forceinline__ int pairs_of(const KGeom &G, const KParams &P, int i, float4 pi,
                                         int cx, int cy, int cz, const float4 *__restrict__ pos4,
-                                        const int32_t *__restrict__ idx,
-                                        const int32_t *__restrict__ cstart,
-                                        const float4 *__restrict__ wpos4,
-                                        const int32_t *__restrict__ wcstart, uint32_t *out,
+                                        const int32_t *__restrict__ idx_all,
+                                        const int32_t *__restrict__ start_all, uint32_t *out,
                                         int64_t base, int64_t cap) {
   int n = 0;
   const uint32_t gi = __float_as_uint(pi.w);
   for (int code = 0; code < 27; ++code) {
-    Scan S;
-    scan_cell(G, cx, cy, cz, code, S);
-    for (int pass = 0; pass < 2; ++pass) {
-      const int t0 = pass ? wcstart[S.c] : cstart[S.c];
-      const int t1 = pass ? wcstart[S.c + 1] : cstart[S.c + 1];
-      for (int t = t0; t < t1; ++t) {
-        float4 pj;
-        if (pass) {
-          pj = wpos4[t];
-        } else {
-          const int j = idx[t];
-          if (j == i) continue;
-          pj = pos4[j];
+    const NCell nc = neighbour_cell(G, cx, cy, cz, code);
+    const float ax = sub_nc(pi.x, nc.sx), ay = sub_nc(pi.y, nc.sy), az = sub_nc(pi.z, nc.sz);
+    const int t0 = start_all[nc.c], t1 = start_all[nc.c + 1];
+    for (int t = t0; t < t1; ++t) {
+      const int j = idx_all[t];
+      if (j == i) continue;
+      const float4 pj = pos4[j];
+      if (pair_r2(sub_nc(ax, pj.x), sub_nc(ay, pj.y), sub_nc(az, pj.z)) < P.rc2) {
+        if (out && base + n < cap) {
+          out[2 * (base + n)] = gi;
+          out[2 * (base + n) + 1] = __float_as_uint(pj.w);
         }
-        const float dx = sub_nc(pi.x, add_nc(pj.x, S.sx));
-        const float dy = sub_nc(pi.y, add_nc(pj.y, S.sy));
-        const float dz = sub_nc(pi.z, add_nc(pj.z, S.sz));
-        if (pair_r2(dx, dy, dz) < P.rc2) {
-          if (out && base + n < cap) {
-            out[2 * (base + n)] = gi;
-            out[2 * (base + n) + 1] = __float_as_uint(pj.w);
-          }
-          ++n;
-        }
+        ++n;
       }
     }
   }
@@ -591,9 +612,9 @@ __device__ __forceinline__ int pairs_of(const KGeom &G, const KParams &P, int i,
 
 __global__ __launch_bounds__(kBlock) void k_pairs(
     const KGeom G, const KParams P, int64_t nf, const float4 *__restrict__ pos4,
-    const int32_t *__restrict__ idx, const int32_t *__restrict__ cstart,
-    const float4 *__restrict__ wpos4, const int32_t *__restrict__ wcstart, uint32_t *pairs,
-    int64_t cap, unsigned long long *counter) {
+    const int32_t *__restrict__ idx, const int32_t *__restrict__ idx_all,
+    const int32_t *__restrict__ start_all, uint32_t *pairs, int64_t cap,
+    unsigned long long *counter) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool act = s < nf;
   int i = 0, cx = 0, cy = 0, cz = 0;
@@ -603,7 +624,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(
     i = idx[s];
     pi = pos4[i];
     cell_index(G, pi.x, pi.y, pi.z, cx, cy, cz);
-    n = pairs_of(G, P, i, pi, cx, cy, cz, pos4, idx, cstart, wpos4, wcstart, nullptr, 0, 0);
+    n = pairs_of(G, P, i, pi, cx, cy, cz, pos4, idx_all, start_all, nullptr, 0, 0);
   }
   // wavefront-inclusive prefix of n, one atomic per wavefront
   const int lane = (int)__lane_id();
@@ -617,7 +638,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(
   if (lane == 63 && total > 0) base = atomicAdd(counter, (unsigned long long)total);
   base = __shfl(base, 63, 64);
   if (act && pairs && n > 0)
-    pairs_of(G, P, i, pi, cx, cy, cz, pos4, idx, cstart, wpos4, wcstart, pairs,
+    pairs_of(G, P, i, pi, cx, cy, cz, pos4, idx_all, start_all, pairs,
              (int64_t)base + incl - n, cap);
 }
 
@@ -737,8 +758,10 @@ hipError_t launch_scan_top(hipStream_t s, int nblocks, int32_t *bsum) {
 }
 
 hipError_t launch_scan_down(hipStream_t s, int64_t ncell, int32_t *count, int32_t *start,
-                            const int32_t *bsum) {
-  k_scan_down<<<scan_blocks(ncell), kScanThreads, 0, s>>>(ncell, count, start, bsum);
+                            const int32_t *bsum, const int32_t *wstart, int32_t *start_all,
+                            int32_t *fluid_off) {
+  k_scan_down<<<scan_blocks(ncell), kScanThreads, 0, s>>>(ncell, count, start, bsum, wstart,
+                                                          start_all, fluid_off);
   return hipGetLastError();
 }
 
@@ -749,8 +772,28 @@ hipError_t launch_scatter(hipStream_t s, int64_t n, const int32_t *cell_of,
   return hipGetLastError();
 }
 
-hipError_t launch_sort_cells(hipStream_t s, int64_t ncell, const int32_t *start, int32_t *idx) {
-  k_sort_cells<<<grid_for(ncell), kBlock, 0, s>>>(ncell, start, idx);
+hipError_t launch_sort_cells(hipStream_t s, int64_t ncell, const int32_t *start, int32_t *idx,
+                             const int32_t *fluid_off, int32_t *idx_all) {
+  k_sort_cells<<<grid_for(ncell), kBlock, 0, s>>>(ncell, start, idx, fluid_off, idx_all);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_walls(hipStream_t s, int64_t nw, int64_t nf, const int32_t *wcell,
+                             const int32_t *wstart, const int32_t *start_all, int32_t *idx_all) {
+  if (nw <= 0) return hipSuccess;
+  k_fill_walls<<<grid_for(nw), kBlock, 0, s>>>(nw, nf, wcell, wstart, start_all, idx_all);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_pad(hipStream_t s, float4 *pos4, float4 *vt4) {
+  k_set_pad<<<1, 1, 0, s>>>(pos4, vt4);
+  return hipGetLastError();
+}
+
+hipError_t launch_cells(hipStream_t s, const KGeom &G, int64_t n, const float4 *pos4,
+                        int32_t *cell) {
+  if (n <= 0) return hipSuccess;
+  k_cells<<<grid_for(n), kBlock, 0, s>>>(G, n, pos4, cell);
   return hipGetLastError();
 }
 
@@ -826,31 +869,34 @@ hipError_t launch_integrate(hipStream_t s, const KGeom &G, const KParams &P, int
   return hipGetLastError();
 }
 
-hipError_t launch_force(hipStream_t s, const KGeom &G, const KParams &P, int64_t nf, int init,
-                        const float4 *pos4, const float4 *vt4, const float4 *vel4,
-                        const float4 *frc4, const int32_t *idx, const int32_t *cstart,
-                        const float4 *wpos4, const int32_t *wcstart, float4 *pos_out,
-                        float4 *vel_out, float4 *frc_out, uint64_t k, Status *st) {
+hipError_t launch_force(hipStream_t s, const KGeom &G, const KParams &P, int64_t nf, int64_t nw,
+                        int init, const float4 *pos4, const float4 *vt4, const float4 *vel4,
+                        const float4 *frc4, const int32_t *idx, const int32_t *idx_all,
+                        const int32_t *start_all, float4 *pos_out, float4 *vel_out,
+                        float4 *frc_out, uint64_t k, Status *st) {
+  const int32_t pad = (int32_t)(nf + nw);
   if (nf <= 0) return hipSuccess;
   const uint32_t klo = (uint32_t)k;
   const uint32_t khi = ((uint32_t)(k >> 32) & 0xFFFFu) | (P.replica << 16);
   const unsigned nb = xcd_grid(nf, kForceBlock);
   if (init)
-    k_force<true><<<nb, kForceBlock, 0, s>>>(G, P, nf, pos4, vt4, vel4, frc4, idx, cstart, wpos4,
-                                             wcstart, pos_out, vel_out, frc_out, klo, khi, st);
+    k_force<true><<<nb, kForceBlock, 0, s>>>(G, P, nf, pos4, vt4, vel4, frc4, idx, idx_all,
+                                             start_all, pad, pos_out, vel_out, frc_out, klo, khi,
+                                             st);
   else
-    k_force<false><<<nb, kForceBlock, 0, s>>>(G, P, nf, pos4, vt4, vel4, frc4, idx, cstart, wpos4,
-                                              wcstart, pos_out, vel_out, frc_out, klo, khi, st);
+    k_force<false><<<nb, kForceBlock, 0, s>>>(G, P, nf, pos4, vt4, vel4, frc4, idx, idx_all,
+                                              start_all, pad, pos_out, vel_out, frc_out, klo, khi,
+                                              st);
   return hipGetLastError();
 }
 
 hipError_t launch_pairs(hipStream_t s, const KGeom &G, const KParams &P, int64_t nf,
-                        const float4 *pos4, const int32_t *idx, const int32_t *cstart,
-                        const float4 *wpos4, const int32_t *wcstart, uint32_t *pairs,
-                        int64_t cap, unsigned long long *counter) {
+                        const float4 *pos4, const int32_t *idx, const int32_t *idx_all,
+                        const int32_t *start_all, uint32_t *pairs, int64_t cap,
+                        unsigned long long *counter) {
   if (nf <= 0) return hipSuccess;
-  k_pairs<<<grid_for(nf), kBlock, 0, s>>>(G, P, nf, pos4, idx, cstart, wpos4, wcstart, pairs,
-                                          cap, counter);
+  k_pairs<<<grid_for(nf), kBlock, 0, s>>>(G, P, nf, pos4, idx, idx_all, start_all, pairs, cap,
+                                          counter);
   return hipGetLastError();
 }
 

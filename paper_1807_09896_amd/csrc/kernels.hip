@@ -317,18 +317,24 @@ __global__ void k_check_phi(const KGeom G, const T *__restrict__ grid, int64_t n
 
 // ---------------------------------------------------------------------------
 // Integrate + reflect + bin (Groot-Warren drift, Sec. II.C bounce-back)
+//
+// Each thread advances two particles (p and p + kBlock of a 2 kBlock tile),
+// so that their loads and atomics are in flight together.  Ranks within a
+// cell come from one atomic per run of equal cells in a wavefront: the
+// particles arrive sorted by their previous cell and most keep it, so runs
+// are the common case.
 // ---------------------------------------------------------------------------
+struct Moved {
+  float4 pos;  // new position, gid bits in w
+  float4 vt;   // predicted velocity, event code bits in w
+  int cell;
+};
+
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_integrate(
-    const KGeom G, const KParams P, int64_t nf, float4 *__restrict__ pos4,
-    const float4 *__restrict__ vel4, const float4 *__restrict__ frc4, float4 *__restrict__ vt4,
-    int32_t *__restrict__ cell_of, int32_t *__restrict__ rank_of, int32_t *__restrict__ count,
-    const uint32_t *__restrict__ bits, int use_mask, const T *__restrict__ grid, Status *st) {
-  const int64_t p = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
-  if (p >= nf) return;
-  const float4 x = pos4[p];
-  const float4 v = vel4[p];
-  const float4 f = frc4[p];
+__device__ __forceinline__ Moved integrate_one(const KGeom &G, const KParams &P, float4 x,
+                                               float4 v, float4 f,
+                                               const uint32_t *__restrict__ bits, int use_mask,
+                                               const T *__restrict__ grid, Status *st) {
   float xs = drift1(x.x, v.x, f.x, P.hdt, P.dt, G.L[0]);
   float ys = drift1(x.y, v.y, f.y, P.hdt, P.dt, G.L[1]);
   float zs = drift1(x.z, v.z, f.z, P.hdt, P.dt, G.L[2]);
@@ -348,8 +354,6 @@ __global__ __launch_bounds__(kBlock) void k_integrate(
       if (!(zs >= 0.f && zs <= G.L[2])) zs = x.z;
     }
   }
-  int cx, cy, cz;
-  int c = cell_index(G, xs, ys, zs, cx, cy, cz);
   int event = 0;
   const GridLoc<T> loc = grid_locate<T>(G, xs, ys, zs);
   if (!use_mask || cube_flagged(bits, cube_index(G, loc))) {
@@ -380,14 +384,86 @@ __global__ __launch_bounds__(kBlock) void k_integrate(
       ys = by;
       zs = bz;
       vt = make_float4(-v.x, -v.y, -v.z, 0.f);
-      c = cell_index(G, xs, ys, zs, cx, cy, cz);
     }
   }
   vt.w = __int_as_float(event);
-  pos4[p] = make_float4(xs, ys, zs, x.w);
-  vt4[p] = vt;
-  cell_of[p] = c;
-  rank_of[p] = atomicAdd(&count[c], 1);
+  Moved m;
+  m.pos = make_float4(xs, ys, zs, x.w);
+  m.vt = vt;
+  int cx, cy, cz;
+  m.cell = cell_index(G, xs, ys, zs, cx, cy, cz);
+  return m;
+}
+
+// Run structure of equal cells across a wavefront (cell < 0: inactive lane).
+struct RunInfo {
+  unsigned long long heads;
+  int len;     // run length, for head lanes
+  bool head;
+};
+
+__device__ __forceinline__ RunInfo wave_runs(int cell) {
+  const int lane = (int)__lane_id();
+  const int prev = __shfl_up(cell, 1, 64);
+  RunInfo r;
+  r.head = lane == 0 || prev != cell;
+  r.heads = __ballot(r.head);
+  const unsigned long long after = lane == 63 ? 0ull : (r.heads >> (lane + 1));
+  r.len = after ? __ffsll((long long)after) : 64 - lane;
+  return r;
+}
+
+__device__ __forceinline__ int wave_rank(const RunInfo &r, int base) {
+  const int lane = (int)__lane_id();
+  const unsigned long long upto = lane == 63 ? r.heads : (r.heads & ((2ull << lane) - 1ull));
+  const int h = 63 - __clzll((long long)upto);
+  return __shfl(base, h, 64) + (lane - h);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_integrate(
+    const KGeom G, const KParams P, int64_t nf, float4 *__restrict__ pos4,
+    const float4 *__restrict__ vel4, const float4 *__restrict__ frc4, float4 *__restrict__ vt4,
+    int32_t *__restrict__ cell_of, int32_t *__restrict__ rank_of, int32_t *__restrict__ count,
+    const uint32_t *__restrict__ bits, int use_mask, const T *__restrict__ grid, Status *st) {
+  const int64_t p0 = (int64_t)xcd_block() * (2 * kBlock) + threadIdx.x;
+  const int64_t p1 = p0 + kBlock;
+  const bool a0 = p0 < nf, a1 = p1 < nf;
+  float4 x0 = make_float4(0.f, 0.f, 0.f, 0.f), v0 = x0, f0 = x0, x1 = x0, v1 = x0, f1 = x0;
+  if (a0) {
+    x0 = pos4[p0];
+    v0 = vel4[p0];
+    f0 = frc4[p0];
+  }
+  if (a1) {
+    x1 = pos4[p1];
+    v1 = vel4[p1];
+    f1 = frc4[p1];
+  }
+  Moved m0, m1;
+  m0.cell = -1;
+  m1.cell = -1;
+  if (a0) m0 = integrate_one<T>(G, P, x0, v0, f0, bits, use_mask, grid, st);
+  if (a1) m1 = integrate_one<T>(G, P, x1, v1, f1, bits, use_mask, grid, st);
+  const RunInfo r0 = wave_runs(m0.cell);
+  const RunInfo r1 = wave_runs(m1.cell);
+  int b0 = 0, b1 = 0;
+  if (r0.head && m0.cell >= 0) b0 = atomicAdd(&count[m0.cell], r0.len);
+  if (r1.head && m1.cell >= 0) b1 = atomicAdd(&count[m1.cell], r1.len);
+  const int k0 = wave_rank(r0, b0);
+  const int k1 = wave_rank(r1, b1);
+  if (a0) {
+    pos4[p0] = m0.pos;
+    vt4[p0] = m0.vt;
+    cell_of[p0] = m0.cell;
+    rank_of[p0] = k0;
+  }
+  if (a1) {
+    pos4[p1] = m1.pos;
+    vt4[p1] = m1.vt;
+    cell_of[p1] = m1.cell;
+    rank_of[p1] = k1;
+  }
 }
 
 // Number of fluid particles whose grid cube is flagged (the particles that
@@ -859,7 +935,7 @@ hipError_t launch_integrate(hipStream_t s, const KGeom &G, const KParams &P, int
                             const uint32_t *bits, int use_mask, const void *grid, int grid_f64,
                             Status *st) {
   if (nf <= 0) return hipSuccess;
-  const unsigned nb = xcd_grid(nf, kBlock);
+  const unsigned nb = xcd_grid(nf, 2 * kBlock);
   if (grid_f64)
     k_integrate<double><<<nb, kBlock, 0, s>>>(G, P, nf, pos4, vel4, frc4, vt4, cell_of, rank_of,
                                               count, bits, use_mask, (const double *)grid, st);

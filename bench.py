@@ -90,6 +90,10 @@ def main():
                     help="steps of the per-kernel HIP-event pass")
     ap.add_argument("--cpu-steps", type=int, default=2,
                     help="oracle steps of the CPU baseline (0 skips it)")
+    ap.add_argument("--batch-steps", type=int, default=100,
+                    help="steps of the 256-replica batch leg and of its sequential "
+                         "comparison (0 skips the leg)")
+    ap.add_argument("--replicas", type=int, default=256)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the run, copy this many MiB with the library's plain copy "
                          "kernel (the reference for hardware byte counters)")
@@ -167,6 +171,11 @@ def main():
         if tr.get("kernel_source_hash") == kernel_source_hash():
             traffic = tr.get("bytes_per_launch")
 
+    batch = None
+    if args.batch_steps > 0:
+        sim.close()
+        batch = batch_leg(dpd, args.replicas, args.batch_steps)
+
     cpu = None
     if args.cpu_steps > 0:
         import oracle
@@ -207,9 +216,64 @@ def main():
         "step_hbm": {"algorithmic_bytes": b_alg, "achieved_GBs": step_gbs,
                      "peak_GBs": HBM_PEAK_GBS, "frac": step_gbs / HBM_PEAK_GBS},
         "cpu_baseline": cpu,
+        "batch": batch,
     }
     print(json.dumps(out), flush=True)
     sim.close()
+
+
+def batch_leg(dpd, replicas, steps):
+    """Independent replica boxes of uneven size and geometry: one batch
+    context (one launch per kernel for all boxes, autotuned launch shapes,
+    step replayed as a HIP graph) against the same boxes as separate
+    graph-replayed plain contexts stepped back to back."""
+    import torch
+    import workloads
+    t0 = time.time()
+    boxes = workloads.replica_systems(count=replicas)
+    n_tot = sum(b.n for b in boxes)
+    log("batch leg: %d replicas, %d particles (%d..%d per box), generated in %.1fs"
+        % (replicas, n_tot, min(b.n for b in boxes), max(b.n for b in boxes), time.time() - t0))
+    bsim = dpd.Simulation(boxes, graph=True)
+    shape, trials = bsim.autotune(5)
+    log("autotuned shape (particles/thread, force block) = %s; trial ms/step %s"
+        % (shape, ["%.3f" % t for t in trials]))
+    bsim.step(10)
+    bsim.sync()
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    bsim.step(steps)
+    bsim.sync()
+    torch.cuda.synchronize()
+    tb_ = time.perf_counter() - ta
+    bsim.kernel_times(1)
+    bsim.step(5)
+    kt = bsim.kernel_times(0)
+    bsim.close()
+    batched = n_tot * steps / tb_
+    log("batched: %.4f ms/step, %.4e particle-steps/s" % (tb_ * 1e3 / steps, batched))
+    sims = [dpd.Simulation(b, graph=True) for b in boxes]
+    for s in sims:
+        s.step(2)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    for s in sims:
+        s.step(steps)
+    for s in sims:
+        s.sync()
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - ta
+    for s in sims:
+        s.close()
+    seq = n_tot * steps / ts
+    log("sequential plain contexts: %.4f ms per step of all boxes, %.4e particle-steps/s"
+        % (ts * 1e3 / steps, seq))
+    return {"replicas": replicas, "particles": n_tot, "steps": steps,
+            "value": batched, "unit": "particle-steps/s", "ms_per_step": tb_ * 1e3 / steps,
+            "sequential_value": seq, "sequential_ms_per_step": ts * 1e3 / steps,
+            "speedup_vs_sequential": batched / seq, "shape": list(shape),
+            "trial_ms_per_step": trials, "graph": True,
+            "kernel_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in kt.items() if v[1]}}
 
 
 def kernel_source_hash():

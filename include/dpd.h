@@ -205,6 +205,57 @@ int dpd_counters(dpd_ctx *ctx, int64_t *out);
 int dpd_kernel_times(dpd_ctx *ctx, int32_t enable, double *out_ms, int64_t *out_launches);
 const char *dpd_kernel_name(int32_t i);
 
+/* ---- Batches of independent boxes ----
+ * A batch context holds nbox independent systems ("replicas"), each one the
+ * whole problem of dpd_create (Sec. II) with its own box, particles, phase
+ * field and parameters; a step advances all of them with the same kernels
+ * (one launch per kernel for the whole batch).  Replica r of a batch gives
+ * bit-identical results to a plain context created from the same inputs.
+ * Every box shares the random-number index k; boxes that run the same
+ * geometry and seed should differ in params.replica, which enters the
+ * counter (Eq. 7).  All phi grids of a batch must have one dtype and all
+ * params one flags value.  The arrays boxes, particles, params, grids hold
+ * nbox entries each.  dpd_create is dpd_batch_create with nbox = 1. */
+int dpd_batch_create(int32_t nbox, const dpd_box *boxes, const dpd_particles *particles,
+                     const dpd_params *params, const dpd_phi_grid *grids,
+                     const dpd_allocator *alloc, void *hip_stream, dpd_ctx **out);
+
+/* Number of boxes of the context (>= 1), or DPD_E_INVAL for NULL. */
+int dpd_replica_count(const dpd_ctx *ctx);
+
+/* Per-box getters and setter: as dpd_forces, dpd_get_state, dpd_set_state,
+ * dpd_neighbor_pairs and dpd_profile, for box r (0 <= r < count) with that
+ * box's n and gid numbering.  The plain names act on box 0.  set_state sets
+ * the context-wide k. */
+int dpd_replica_forces(dpd_ctx *ctx, int32_t r, float *f_out);
+int dpd_replica_state(dpd_ctx *ctx, int32_t r, float *pos, float *vel, int32_t *events,
+                      int32_t *cell_of);
+int dpd_replica_set_state(dpd_ctx *ctx, int32_t r, const float *pos, const float *vel,
+                          const float *force, uint64_t k, int32_t on_device);
+int dpd_replica_pairs(dpd_ctx *ctx, int32_t r, uint32_t *pairs, int64_t cap, int64_t *count);
+int dpd_replica_profile(dpd_ctx *ctx, int32_t r, int32_t axis, int32_t nbins, double *out);
+
+/* enable != 0: dpd_step replays one captured HIP graph per step (the launch
+ * sequence of a step, captured on first use on a private stream and replayed
+ * on the context stream; the random-number index k lives on the device and is
+ * advanced inside the graph, so replays draw fresh numbers).  Results are
+ * bit-identical to direct launches.  Per-kernel timing, when enabled, uses
+ * direct launches.  A captured graph is dropped by set_state and autotune. */
+int dpd_use_graph(dpd_ctx *ctx, int32_t enable);
+
+/* Choose the launch shapes of the integrate kernel (particles per thread,
+ * 1 or 2) and of the pair-force kernel (work-group size, 128 or 256) by
+ * timing `steps` steps of each of the four combinations from the current
+ * state; the state, k and the step counter are restored after each trial, so
+ * the context is left as it was apart from the shapes (results do not depend
+ * on them).  If the environment variable DPD_TUNE_CACHE names a file, a
+ * choice recorded there for the same device and sizes is used without trials
+ * and new choices are appended.  shape_out (host int32[2], may be NULL)
+ * receives {particles per thread, work-group size}; ms_out (host double[4],
+ * may be NULL) the ms per step of {2/256, 1/256, 2/128, 1/128}, -1 when not
+ * timed.  Synchronises. */
+int dpd_autotune(dpd_ctx *ctx, int32_t steps, int32_t *shape_out, double *ms_out);
+
 /* Wait for the context stream and return any latched device error. */
 int dpd_sync(dpd_ctx *ctx);
 

@@ -13,33 +13,55 @@ from __future__ import annotations
 import numpy as np
 
 from . import binding
-from .binding import (DPDError, dpd_counters, dpd_create, dpd_destroy, dpd_forces,
-                      dpd_get_state, dpd_kernel_times, dpd_last_error, dpd_neighbor_pairs,
-                      dpd_profile, dpd_set_state, dpd_step, dpd_sync, load_library)
+from .binding import (DPDError, dpd_autotune, dpd_batch_create, dpd_counters, dpd_create,
+                      dpd_destroy, dpd_forces, dpd_get_state, dpd_kernel_times, dpd_last_error,
+                      dpd_neighbor_pairs, dpd_profile, dpd_replica_count, dpd_replica_forces,
+                      dpd_replica_pairs, dpd_replica_profile, dpd_replica_set_state,
+                      dpd_replica_state, dpd_set_state, dpd_step, dpd_sync, dpd_use_graph,
+                      load_library)
 
-__all__ = ["Simulation", "DPDError", "load_library", "dpd_create", "dpd_step", "dpd_forces",
-           "dpd_get_state", "dpd_set_state", "dpd_neighbor_pairs", "dpd_profile",
-           "dpd_counters", "dpd_kernel_times", "dpd_sync", "dpd_last_error", "dpd_destroy"]
+__all__ = ["Simulation", "DPDError", "load_library", "dpd_create", "dpd_batch_create",
+           "dpd_step", "dpd_forces", "dpd_get_state", "dpd_set_state", "dpd_neighbor_pairs",
+           "dpd_profile", "dpd_counters", "dpd_kernel_times", "dpd_sync", "dpd_last_error",
+           "dpd_destroy", "dpd_replica_count", "dpd_replica_forces", "dpd_replica_state",
+           "dpd_replica_set_state", "dpd_replica_pairs", "dpd_replica_profile",
+           "dpd_use_graph", "dpd_autotune"]
+
+
+def _box_args(system, params=None):
+    return (system.L, system.pos, system.vel, system.type, system.gid,
+            dict(system.params if params is None else params), system.phi, system.h)
 
 
 class Simulation:
-    """One box on the GPU.
+    """One box, or a batch of independent boxes, on the GPU.
 
     `system` is any object with L (3,), pos (N, 3) float32, vel (N, 3),
     type (N,) int32, gid (N,) uint32, phi (nz, ny, nx), h (3,) and params
     (dict: a, gamma, kBT, rc, dt, lam, g, seed, replica), such as the
-    systems built by the `workloads` package.
+    systems built by the `workloads` package, or a list of such objects for
+    a batch context (one launch per kernel advances every box).  Per-box
+    methods take the box index r (0 for a single box).
     """
 
-    def __init__(self, system, params=None, flags=0, stream=None):
+    def __init__(self, system, params=None, flags=0, stream=None, graph=False):
         import torch
         self.torch = torch
-        self.n = int(system.pos.shape[0])
-        self.params = dict(system.params if params is None else params)
-        self.ctx, self._keep = dpd_create(system.L, system.pos, system.vel, system.type,
-                                          system.gid, self.params, system.phi, system.h,
-                                          stream=stream, flags=flags)
+        if isinstance(system, (list, tuple)):
+            systems = list(system)
+            self.ctx, self._keep = dpd_batch_create([_box_args(s) for s in systems],
+                                                    stream=stream, flags=flags)
+        else:
+            systems = [system]
+            self.ctx, self._keep = dpd_create(*_box_args(system, params), stream=stream,
+                                              flags=flags)
+        self.ns = [int(s.pos.shape[0]) for s in systems]
+        self.n = self.ns[0]
+        self.replicas = len(systems)
+        self.params = dict(systems[0].params if params is None else params)
         self.device = torch.device("cuda", torch.cuda.current_device())
+        if graph:
+            self.use_graph(True)
 
     def close(self):
         if self.ctx is not None:
@@ -59,33 +81,40 @@ class Simulation:
     def sync(self):
         dpd_sync(self.ctx)
 
-    def forces(self):
-        f = self.torch.empty((self.n, 3), dtype=self.torch.float32, device=self.device)
-        dpd_forces(self.ctx, f)
+    def use_graph(self, enable=True):
+        dpd_use_graph(self.ctx, enable)
+
+    def autotune(self, steps=10):
+        return dpd_autotune(self.ctx, steps)
+
+    def forces(self, r=0):
+        f = self.torch.empty((self.ns[r], 3), dtype=self.torch.float32, device=self.device)
+        dpd_replica_forces(self.ctx, r, f)
         return f
 
-    def state(self):
+    def state(self, r=0):
         t = self.torch
-        pos = t.empty((self.n, 3), dtype=t.float32, device=self.device)
-        vel = t.empty((self.n, 3), dtype=t.float32, device=self.device)
-        ev = t.empty((self.n,), dtype=t.int32, device=self.device)
-        cell = t.empty((self.n,), dtype=t.int32, device=self.device)
-        dpd_get_state(self.ctx, pos, vel, ev, cell)
+        n = self.ns[r]
+        pos = t.empty((n, 3), dtype=t.float32, device=self.device)
+        vel = t.empty((n, 3), dtype=t.float32, device=self.device)
+        ev = t.empty((n,), dtype=t.int32, device=self.device)
+        cell = t.empty((n,), dtype=t.int32, device=self.device)
+        dpd_replica_state(self.ctx, r, pos, vel, ev, cell)
         return dict(pos=pos, vel=vel, events=ev, cell_of=cell)
 
-    def set_state(self, pos, vel, force, k):
-        dpd_set_state(self.ctx, pos, vel, force, k)
+    def set_state(self, pos, vel, force, k, r=0):
+        dpd_replica_set_state(self.ctx, r, pos, vel, force, k)
 
-    def pairs(self):
-        n = dpd_neighbor_pairs(self.ctx, None, 0)
+    def pairs(self, r=0):
+        n = dpd_replica_pairs(self.ctx, r, None, 0)
         buf = self.torch.empty((max(n, 1), 2), dtype=self.torch.int32, device=self.device)
-        n2 = dpd_neighbor_pairs(self.ctx, buf, n)
+        n2 = dpd_replica_pairs(self.ctx, r, buf, n)
         assert n2 == n
         return buf[:n].cpu().numpy().view(np.uint32)
 
-    def profile(self, axis=2, nbins=100):
+    def profile(self, axis=2, nbins=100, r=0):
         out = self.torch.empty((nbins, 5), dtype=self.torch.float64, device=self.device)
-        dpd_profile(self.ctx, axis, nbins, out)
+        dpd_replica_profile(self.ctx, r, axis, nbins, out)
         return out
 
     def counters(self):

@@ -34,7 +34,9 @@ _ERRNAMES = {DPD_E_INVAL: "DPD_E_INVAL", DPD_E_NOMEM: "DPD_E_NOMEM",
 EXPORTED = ["dpd_create", "dpd_step", "dpd_forces", "dpd_get_state", "dpd_set_state",
             "dpd_neighbor_pairs", "dpd_profile", "dpd_counters", "dpd_kernel_times",
             "dpd_kernel_name", "dpd_sync", "dpd_last_error", "dpd_destroy", "dpd_copy_probe",
-            "dpd_pair_random"]
+            "dpd_pair_random", "dpd_batch_create", "dpd_replica_count", "dpd_replica_forces",
+            "dpd_replica_state", "dpd_replica_set_state", "dpd_replica_pairs",
+            "dpd_replica_profile", "dpd_use_graph", "dpd_autotune"]
 
 
 class DPDError(RuntimeError):
@@ -115,6 +117,24 @@ def load_library(path: str = LIB_PATH):
     L.dpd_copy_probe.restype = C.c_int
     L.dpd_pair_random.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, P, P, C.c_int64, P, P, P]
     L.dpd_pair_random.restype = C.c_int
+    L.dpd_batch_create.argtypes = [C.c_int32, P, P, P, P, P, P, C.POINTER(P)]
+    L.dpd_batch_create.restype = C.c_int
+    L.dpd_replica_count.argtypes = [P]
+    L.dpd_replica_count.restype = C.c_int
+    L.dpd_replica_forces.argtypes = [P, C.c_int32, P]
+    L.dpd_replica_forces.restype = C.c_int
+    L.dpd_replica_state.argtypes = [P, C.c_int32, P, P, P, P]
+    L.dpd_replica_state.restype = C.c_int
+    L.dpd_replica_set_state.argtypes = [P, C.c_int32, P, P, P, C.c_uint64, C.c_int32]
+    L.dpd_replica_set_state.restype = C.c_int
+    L.dpd_replica_pairs.argtypes = [P, C.c_int32, P, C.c_int64, C.POINTER(C.c_int64)]
+    L.dpd_replica_pairs.restype = C.c_int
+    L.dpd_replica_profile.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P]
+    L.dpd_replica_profile.restype = C.c_int
+    L.dpd_use_graph.argtypes = [P, C.c_int32]
+    L.dpd_use_graph.restype = C.c_int
+    L.dpd_autotune.argtypes = [P, C.c_int32, P, P]
+    L.dpd_autotune.restype = C.c_int
     _lib = L
     return L
 
@@ -165,21 +185,10 @@ def _stream_handle(stream=None):
 # C-named entry points (thin marshalling)
 # ---------------------------------------------------------------------------
 
-def dpd_create(L, pos, vel, type_, gid, params, phi, h, stream=None, use_torch_allocator=True,
-               flags=0):
-    """Create a context from host numpy arrays (or device tensors).
-
-    params: dict with a (2x2), gamma, kBT, rc, dt, lam, g, seed, replica.
-    phi: (nz, ny, nx) float32/float64 array; h: grid spacing (3,).
-    Returns (ctx handle, keepalive) where keepalive must outlive the context.
-    """
-    import torch
-    lib = load_library()
-    if not torch.cuda.is_available():
-        raise DPDError(DPD_E_DEVICE, "no HIP device visible to torch")
+def _marshal_box(L, pos, vel, type_, gid, params, phi, h, flags, keep):
+    """ctypes structs of one box (host arrays are copied into `keep`)."""
     on_dev = int(hasattr(pos, "data_ptr"))
     n = int(pos.shape[0])
-    keep = []
 
     def host(a, dt):
         a = np.ascontiguousarray(a, dtype=dt)
@@ -209,6 +218,23 @@ def dpd_create(L, pos, vel, type_, gid, params, phi, h, stream=None, use_torch_a
                      (C.c_double * 3)(*params["g"]),
                      int(params["seed"]) & 0xFFFFFFFFFFFFFFFF, int(params["replica"]),
                      int(flags))
+    return box, parts, prm, grid
+
+
+def dpd_create(L, pos, vel, type_, gid, params, phi, h, stream=None, use_torch_allocator=True,
+               flags=0):
+    """Create a context from host numpy arrays (or device tensors).
+
+    params: dict with a (2x2), gamma, kBT, rc, dt, lam, g, seed, replica.
+    phi: (nz, ny, nx) float32/float64 array; h: grid spacing (3,).
+    Returns (ctx handle, keepalive) where keepalive must outlive the context.
+    """
+    import torch
+    lib = load_library()
+    if not torch.cuda.is_available():
+        raise DPDError(DPD_E_DEVICE, "no HIP device visible to torch")
+    keep = []
+    box, parts, prm, grid = _marshal_box(L, pos, vel, type_, gid, params, phi, h, flags, keep)
     alloc = None
     if use_torch_allocator:
         alloc = TorchAllocator(torch.device("cuda", torch.cuda.current_device()))
@@ -219,6 +245,83 @@ def dpd_create(L, pos, vel, type_, gid, params, phi, h, stream=None, use_torch_a
                         C.byref(ctx))
     _check(rc, None)
     return ctx, keep
+
+
+def dpd_batch_create(boxes, stream=None, use_torch_allocator=True, flags=0):
+    """Create a batch context from a list of boxes, each a tuple
+    (L, pos, vel, type, gid, params, phi, h) as taken by dpd_create.
+    Returns (ctx handle, keepalive)."""
+    import torch
+    lib = load_library()
+    if not torch.cuda.is_available():
+        raise DPDError(DPD_E_DEVICE, "no HIP device visible to torch")
+    nb = len(boxes)
+    keep = []
+    B = (dpd_box * nb)()
+    Pp = (dpd_particles * nb)()
+    Pr = (dpd_params * nb)()
+    G = (dpd_phi_grid * nb)()
+    for r, b in enumerate(boxes):
+        B[r], Pp[r], Pr[r], G[r] = _marshal_box(*b, flags, keep)
+    keep += [B, Pp, Pr, G]
+    alloc = None
+    if use_torch_allocator:
+        alloc = TorchAllocator(torch.device("cuda", torch.cuda.current_device()))
+        keep.append(alloc)
+    ctx = C.c_void_p()
+    rc = lib.dpd_batch_create(nb, B, Pp, Pr, G, C.byref(alloc.struct) if alloc else None,
+                              _stream_handle(stream), C.byref(ctx))
+    _check(rc, None)
+    return ctx, keep
+
+
+def dpd_replica_count(ctx):
+    rc = load_library().dpd_replica_count(ctx)
+    if rc < 0:
+        _check(rc, ctx)
+    return rc
+
+
+def dpd_replica_forces(ctx, r, f_out):
+    _check(load_library().dpd_replica_forces(ctx, int(r), _ptr(f_out)), ctx)
+
+
+def dpd_replica_state(ctx, r, pos=None, vel=None, events=None, cell_of=None):
+    _check(load_library().dpd_replica_state(ctx, int(r), _ptr(pos), _ptr(vel), _ptr(events),
+                                            _ptr(cell_of)), ctx)
+
+
+def dpd_replica_set_state(ctx, r, pos, vel, force, k):
+    on_dev = int(hasattr(pos, "data_ptr"))
+    if not on_dev:
+        pos = np.ascontiguousarray(pos, np.float32)
+        vel = np.ascontiguousarray(vel, np.float32)
+        force = np.ascontiguousarray(force, np.float32)
+    _check(load_library().dpd_replica_set_state(ctx, int(r), _ptr(pos), _ptr(vel), _ptr(force),
+                                                int(k), on_dev), ctx)
+
+
+def dpd_replica_pairs(ctx, r, pairs, cap):
+    cnt = C.c_int64(0)
+    _check(load_library().dpd_replica_pairs(ctx, int(r), _ptr(pairs), int(cap), C.byref(cnt)),
+           ctx)
+    return int(cnt.value)
+
+
+def dpd_replica_profile(ctx, r, axis, nbins, out):
+    _check(load_library().dpd_replica_profile(ctx, int(r), int(axis), int(nbins), _ptr(out)), ctx)
+
+
+def dpd_use_graph(ctx, enable):
+    _check(load_library().dpd_use_graph(ctx, int(enable)), ctx)
+
+
+def dpd_autotune(ctx, steps):
+    """Returns ((particles per thread, force block), ms per step of the four trials)."""
+    shape = np.zeros(2, np.int32)
+    ms = np.zeros(4, np.float64)
+    _check(load_library().dpd_autotune(ctx, int(steps), _ptr(shape), _ptr(ms)), ctx)
+    return (int(shape[0]), int(shape[1])), [float(x) for x in ms]
 
 
 def dpd_step(ctx, n):

@@ -1,10 +1,20 @@
 // C ABI of the DPD step library (declared in include/dpd.h): context set-up,
-// validation, buffer management, the per-step launch sequence and getters.
+// validation, buffer management, the per-step launch sequence, getters,
+// HIP-graph capture of the step and the launch-shape autotuner.
+//
+// A context holds R >= 1 independent boxes ("replicas") in concatenated
+// arrays; a single box is a batch of one.  Every step kernel covers all
+// boxes: integrate and pair-force read their box's descriptor per block, the
+// cell-list kernels work on one global cell index space.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -12,9 +22,11 @@
 #include "device.h"
 #include "kernels.h"
 
+using dpd::Box;
 using dpd::KGeom;
 using dpd::KParams;
 using dpd::Status;
+using dpd::Tile;
 
 namespace {
 
@@ -31,6 +43,17 @@ struct TimedLaunch {
   hipEvent_t a, b;
 };
 
+// Host view of one box.
+struct Replica {
+  int64_t n = 0, nf = 0, nw = 0;
+  int64_t fo = 0, wo = 0, co = 0, ncell = 0, go = 0, bo = 0, nwords = 0;
+  int nc[3] = {0, 0, 0}, ng[3] = {0, 0, 0};
+  double L[3] = {0, 0, 0}, h[3] = {0, 0, 0};
+  KGeom G{};
+  KParams P{};
+  int64_t flagged_cubes = 0;
+};
+
 }  // namespace
 
 struct dpd_ctx {
@@ -41,14 +64,17 @@ struct dpd_ctx {
   std::string err = "no error";
   std::vector<void *> owned;
 
-  int64_t n = 0, nf = 0, nw = 0, ncell = 0;
-  int nc[3] = {0, 0, 0};
-  int ng[3] = {0, 0, 0};
+  int R = 0;
+  std::vector<Replica> rep;
+  int64_t NF = 0, NW = 0, NCELL = 0, NGRID = 0, NWORDS = 0;
   int grid_f64 = 0;
-  double L[3] = {0, 0, 0}, h[3] = {0, 0, 0};
-  dpd_params params{};
-  KGeom G{};
-  KParams P{};
+  int use_mask = 1;
+
+  Box *boxes = nullptr;
+  int ppt = 2, fblock = 256;            // launch shapes (autotuned)
+  Tile *itiles = nullptr, *ftiles = nullptr;
+  int n_itiles = 0, n_ftiles = 0;
+  int itiles_cap = 0, ftiles_cap = 0;
 
   float4 *pos[2] = {nullptr, nullptr}, *vel[2] = {nullptr, nullptr}, *frc[2] = {nullptr, nullptr};
   float4 *vt = nullptr;
@@ -57,16 +83,14 @@ struct dpd_ctx {
           *idx = nullptr, *bsum = nullptr;
   int nscan = 0;
   int32_t *wcstart = nullptr;   // exclusive scan of wall counts per cell (static)
-  int32_t *wcell = nullptr;     // cell of each cell-sorted wall (static)
-  int32_t *idx_all = nullptr;   // merged per-cell runs: walls (nf + w), then fluid
+  int32_t *wcell = nullptr;     // global cell of each cell-sorted wall (static)
+  int32_t *idx_all = nullptr;   // merged per-cell runs: walls (NF + w), then fluid
   int32_t *start_all = nullptr; // start of each cell's merged run
   int32_t *fluid_off = nullptr; // start of each cell's fluid part in the merged run
   void *grid = nullptr;
-  uint32_t *bits = nullptr;   // near-interface grid cubes, one bit each
-  int64_t nwords = 0;
-  int use_mask = 1;
-  int64_t flagged_cubes = 0;
+  uint32_t *bits = nullptr;     // near-interface grid cubes, one bit each
   Status *status = nullptr;
+  unsigned long long *dk = nullptr;  // force evaluation index on the device
   unsigned long long *pair_counter = nullptr;
 
   uint64_t k = 0;
@@ -77,6 +101,10 @@ struct dpd_ctx {
   std::vector<hipEvent_t> free_events;
   double kernel_ms[DPD_NUM_KERNELS] = {0};
   int64_t kernel_launches[DPD_NUM_KERNELS] = {0};
+
+  bool use_graph = false;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -125,7 +153,20 @@ void dfree(dpd_ctx *c, void *p) {
   }
 }
 
+void drop_graphs(dpd_ctx *c) {
+  for (int g = 0; g < 2; ++g)
+    if (c->graph[g]) {
+      (void)hipGraphExecDestroy(c->graph[g]);
+      c->graph[g] = nullptr;
+    }
+}
+
 void release_all(dpd_ctx *c) {
+  drop_graphs(c);
+  if (c->cap_stream) {
+    (void)hipStreamDestroy(c->cap_stream);
+    c->cap_stream = nullptr;
+  }
   for (void *p : c->owned) {
     if (c->has_al)
       c->al.free(p, (void *)c->stream, c->al.user);
@@ -169,8 +210,8 @@ void harvest_timings(dpd_ctx *c) {
 
 // Launch helper: brackets a launch with events when timing is on.
 template <typename F>
-hipError_t timed(dpd_ctx *c, int kernel, F &&launch) {
-  if (!c->timing) return launch();
+hipError_t timed(dpd_ctx *c, hipStream_t s, int kernel, F &&launch) {
+  if (!c->timing || s != c->stream) return launch();
   if (c->pending.size() > 4096) {
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return e;
@@ -216,167 +257,319 @@ bool finite3(const float *p) {
   return std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]);
 }
 
-// Cell list of the current fluid positions in pos[cur]: bin, scan, scatter, sort.
-int build_cells_from_pos(dpd_ctx *c) {
-  HIP_TRY(c, timed(c, K_OTHER, [&] {
-            return dpd::launch_bin(c->stream, c->G, c->nf, c->pos[c->cur], c->cell_of,
-                                   c->rank_of, c->count);
-          }));
+// Tile tables: runs of consecutive particles of one box, `size` per tile.
+int build_tiles(dpd_ctx *c, int size, Tile **dst, int *n, int *cap) {
+  std::vector<Tile> t;
+  for (int r = 0; r < c->R; ++r) {
+    const Replica &p = c->rep[r];
+    for (int64_t f = 0; f < p.nf; f += size) {
+      Tile x;
+      x.box = r;
+      x.first = (int32_t)(p.fo + f);
+      x.count = (int32_t)std::min<int64_t>(size, p.nf - f);
+      x.pad = 0;
+      t.push_back(x);
+    }
+  }
+  if ((int)t.size() > *cap) {
+    if (*dst) dfree(c, *dst);
+    *dst = (Tile *)dalloc(c, sizeof(Tile) * std::max<size_t>(t.size(), 1));
+    if (!*dst) return fail(c, DPD_E_NOMEM, "tile table allocation failed");
+    *cap = (int)t.size();
+  }
+  *n = (int)t.size();
+  if (!t.empty())
+    HIP_TRY(c, hipMemcpyAsync(*dst, t.data(), sizeof(Tile) * t.size(), hipMemcpyHostToDevice,
+                              c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
   return DPD_OK;
 }
 
-int scan_scatter_sort(dpd_ctx *c) {
-  HIP_TRY(c, timed(c, K_SCAN_REDUCE, [&] {
-            return dpd::launch_scan_reduce(c->stream, c->ncell, c->count, c->bsum);
+int set_shapes(dpd_ctx *c, int ppt, int fblock) {
+  c->ppt = ppt;
+  c->fblock = fblock;
+  drop_graphs(c);
+  int rc = build_tiles(c, 256 * ppt, &c->itiles, &c->n_itiles, &c->itiles_cap);
+  if (!rc) rc = build_tiles(c, fblock, &c->ftiles, &c->n_ftiles, &c->ftiles_cap);
+  return rc;
+}
+
+// Bin the current fluid positions of every box (counting-sort pass 1).
+int bin_all(dpd_ctx *c, hipStream_t s) {
+  for (int r = 0; r < c->R; ++r) {
+    const Replica &p = c->rep[r];
+    HIP_TRY(c, timed(c, s, K_OTHER, [&] {
+              return dpd::launch_bin(s, p.G, p.co, p.nf, c->pos[c->cur] + p.fo,
+                                     c->cell_of + p.fo, c->rank_of + p.fo, c->count);
+            }));
+  }
+  return DPD_OK;
+}
+
+int scan_scatter_sort(dpd_ctx *c, hipStream_t s) {
+  HIP_TRY(c, timed(c, s, K_SCAN_REDUCE, [&] {
+            return dpd::launch_scan_reduce(s, c->NCELL, c->count, c->bsum);
           }));
-  HIP_TRY(c, timed(c, K_SCAN_TOP, [&] { return dpd::launch_scan_top(c->stream, c->nscan, c->bsum); }));
-  HIP_TRY(c, timed(c, K_SCAN_DOWN, [&] {
-            return dpd::launch_scan_down(c->stream, c->ncell, c->count, c->cstart, c->bsum,
-                                         c->wcstart, c->start_all, c->fluid_off);
+  HIP_TRY(c, timed(c, s, K_SCAN_TOP, [&] { return dpd::launch_scan_top(s, c->nscan, c->bsum); }));
+  HIP_TRY(c, timed(c, s, K_SCAN_DOWN, [&] {
+            return dpd::launch_scan_down(s, c->NCELL, c->count, c->cstart, c->bsum, c->wcstart,
+                                         c->start_all, c->fluid_off);
           }));
-  HIP_TRY(c, timed(c, K_SCATTER, [&] {
-            return dpd::launch_scatter(c->stream, c->nf, c->cell_of, c->rank_of, c->cstart,
-                                       c->idx);
+  HIP_TRY(c, timed(c, s, K_SCATTER, [&] {
+            return dpd::launch_scatter(s, c->NF, c->cell_of, c->rank_of, c->cstart, c->idx);
           }));
-  HIP_TRY(c, timed(c, K_SORT, [&] {
-            return dpd::launch_sort_cells(c->stream, c->ncell, c->cstart, c->idx, c->fluid_off,
+  HIP_TRY(c, timed(c, s, K_SORT, [&] {
+            return dpd::launch_sort_cells(s, c->NCELL, c->cstart, c->idx, c->fluid_off,
                                           c->idx_all);
           }));
-  HIP_TRY(c, timed(c, K_OTHER, [&] {
-            return dpd::launch_fill_walls(c->stream, c->nw, c->nf, c->wcell, c->wcstart,
-                                          c->start_all, c->idx_all);
+  HIP_TRY(c, timed(c, s, K_OTHER, [&] {
+            return dpd::launch_fill_walls(s, c->NW, c->NF, c->wcell, c->wcstart, c->start_all,
+                                          c->idx_all);
           }));
   return DPD_OK;
 }
 
 // Forces at the current state in sorted order; init = 1 keeps velocities.
-int force_pass(dpd_ctx *c, int init) {
+int force_pass(dpd_ctx *c, hipStream_t s, int init) {
   const int a = c->cur, b = 1 - c->cur;
-  HIP_TRY(c, timed(c, K_FORCE, [&] {
-            return dpd::launch_force(c->stream, c->G, c->P, c->nf, c->nw, init, c->pos[a], c->vt,
-                                     c->vel[a], c->frc[a], c->idx, c->idx_all, c->start_all,
-                                     c->pos[b], c->vel[b], c->frc[b], c->k,
-                                     c->status);
+  HIP_TRY(c, timed(c, s, K_FORCE, [&] {
+            return dpd::launch_force(s, c->fblock, c->boxes, c->ftiles, c->n_ftiles, c->NF,
+                                     (int32_t)(c->NF + c->NW), init, c->pos[a], c->vt, c->vel[a],
+                                     c->frc[a], c->idx, c->idx_all, c->start_all, c->pos[b],
+                                     c->vel[b], c->frc[b], c->dk, c->status);
           }));
   c->cur = b;
   return DPD_OK;
 }
 
-int one_step(dpd_ctx *c) {
+// The launches of one step on stream s (swaps cur).
+int enqueue_step(dpd_ctx *c, hipStream_t s) {
   const int a = c->cur;
-  HIP_TRY(c, timed(c, K_INTEGRATE, [&] {
-            return dpd::launch_integrate(c->stream, c->G, c->P, c->nf, c->pos[a], c->vel[a],
-                                         c->frc[a], c->vt, c->cell_of, c->rank_of, c->count,
-                                         c->bits, c->use_mask, c->grid, c->grid_f64, c->status);
+  HIP_TRY(c, timed(c, s, K_INTEGRATE, [&] {
+            return dpd::launch_integrate(s, c->ppt, c->boxes, c->itiles, c->n_itiles, c->pos[a],
+                                         c->vel[a], c->frc[a], c->vt, c->cell_of, c->rank_of,
+                                         c->count, c->bits, c->use_mask, c->grid, c->grid_f64,
+                                         c->status);
           }));
-  int rc = scan_scatter_sort(c);
+  int rc = scan_scatter_sort(c, s);
   if (rc) return rc;
+  HIP_TRY(c, timed(c, s, K_OTHER, [&] { return dpd::launch_bump_k(s, c->dk); }));
+  return force_pass(c, s, 0);
+}
+
+// Capture the step from buffer set `from` into an executable graph.
+int capture_step(dpd_ctx *c, int from) {
+  if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  const int saved = c->cur;
+  c->cur = from;
+  hipGraph_t g = nullptr;
+  HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  int rc = enqueue_step(c, c->cap_stream);
+  hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+  c->cur = saved;
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&c->graph[from], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
+  return DPD_OK;
+}
+
+int one_step(dpd_ctx *c) {
+  if (c->use_graph && !c->timing) {
+    const int a = c->cur;
+    if (!c->graph[a]) {
+      int rc = capture_step(c, a);
+      if (rc) return rc;
+    }
+    HIP_TRY(c, hipGraphLaunch(c->graph[a], c->stream));
+    c->cur = 1 - a;
+  } else {
+    int rc = enqueue_step(c, c->stream);
+    if (rc) return rc;
+  }
   c->k += 1;
-  rc = force_pass(c, 0);
-  if (rc) return rc;
   c->steps += 1;
   return DPD_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-const char *dpd_last_error(const dpd_ctx *ctx) {
-  return ctx ? ctx->err.c_str() : g_create_error.c_str();
+// Re-sort the fluid state into cell order after positions changed outside a
+// step (set_state): bin, scan, scatter, sort, permute into the other buffers.
+int resort(dpd_ctx *c) {
+  int rc = bin_all(c, c->stream);
+  if (!rc) rc = scan_scatter_sort(c, c->stream);
+  if (rc) return rc;
+  const int a = c->cur, b = 1 - a;
+  HIP_TRY(c, dpd::launch_permute(c->stream, c->NF, c->idx, c->pos[a], c->pos[b], c->vel[a],
+                                 c->vel[b], c->frc[a], c->frc[b]));
+  c->cur = b;
+  return DPD_OK;
 }
 
-const char *dpd_kernel_name(int32_t i) {
-  if (i < 0 || i >= DPD_NUM_KERNELS) return "";
-  return kKernelNames[i];
-}
+// Host-side checks and splitting of one box's inputs.
+struct HostBox {
+  std::vector<float> pos, vel;
+  std::vector<int32_t> type;
+  std::vector<uint32_t> gid;
+  std::vector<int64_t> rows_f, rows_w;
+};
 
-int dpd_create(const dpd_box *box, const dpd_particles *pp, const dpd_params *prm,
-               const dpd_phi_grid *phi, const dpd_allocator *alloc, void *hip_stream,
-               dpd_ctx **out) {
-  if (!out) return fail(nullptr, DPD_E_INVAL, "out is NULL");
-  *out = nullptr;
-  if (!box || !pp || !prm || !phi) return fail(nullptr, DPD_E_INVAL, "NULL argument");
-  // ---- validate scalar inputs ----
+int check_box(int r, const dpd_box *box, const dpd_particles *pp, const dpd_params *prm,
+              const dpd_phi_grid *phi, Replica &R, HostBox &H) {
+  const std::string pre = "box " + std::to_string(r) + ": ";
+  if (!box || !pp || !prm || !phi) return fail(nullptr, DPD_E_INVAL, pre + "NULL argument");
   const dpd_params &P = *prm;
   for (int a = 0; a < 3; ++a)
     if (!(std::isfinite(box->L[a]) && box->L[a] > 0))
-      return fail(nullptr, DPD_E_INVAL, "box edges must be finite and positive");
-  if (!(std::isfinite(P.rc) && P.rc > 0)) return fail(nullptr, DPD_E_INVAL, "rc must be > 0");
-  if (!(std::isfinite(P.dt) && P.dt > 0)) return fail(nullptr, DPD_E_INVAL, "dt must be > 0");
+      return fail(nullptr, DPD_E_INVAL, pre + "box edges must be finite and positive");
+  if (!(std::isfinite(P.rc) && P.rc > 0)) return fail(nullptr, DPD_E_INVAL, pre + "rc must be > 0");
+  if (!(std::isfinite(P.dt) && P.dt > 0)) return fail(nullptr, DPD_E_INVAL, pre + "dt must be > 0");
   if (!(std::isfinite(P.gamma) && P.gamma >= 0) || !(std::isfinite(P.kBT) && P.kBT >= 0))
-    return fail(nullptr, DPD_E_INVAL, "gamma and kBT must be finite and >= 0");
-  if (!std::isfinite(P.lambda)) return fail(nullptr, DPD_E_INVAL, "lambda must be finite");
+    return fail(nullptr, DPD_E_INVAL, pre + "gamma and kBT must be finite and >= 0");
+  if (!std::isfinite(P.lambda)) return fail(nullptr, DPD_E_INVAL, pre + "lambda must be finite");
   for (int a = 0; a < 4; ++a)
-    if (!std::isfinite(P.a[a])) return fail(nullptr, DPD_E_INVAL, "a_ij must be finite");
-  if (P.a[1] != P.a[2]) return fail(nullptr, DPD_E_INVAL, "a_ij must be symmetric");
+    if (!std::isfinite(P.a[a])) return fail(nullptr, DPD_E_INVAL, pre + "a_ij must be finite");
+  if (P.a[1] != P.a[2]) return fail(nullptr, DPD_E_INVAL, pre + "a_ij must be symmetric");
   for (int a = 0; a < 3; ++a)
-    if (!std::isfinite(P.g[a])) return fail(nullptr, DPD_E_INVAL, "g must be finite");
-  if (P.replica >= 65536u) return fail(nullptr, DPD_E_INVAL, "replica must be < 65536");
-  int nc[3];
+    if (!std::isfinite(P.g[a])) return fail(nullptr, DPD_E_INVAL, pre + "g must be finite");
+  if (P.replica >= 65536u) return fail(nullptr, DPD_E_INVAL, pre + "replica must be < 65536");
   for (int a = 0; a < 3; ++a) {
-    nc[a] = (int)std::floor(box->L[a] / P.rc);
-    if (nc[a] < 3) return fail(nullptr, DPD_E_INVAL, "box must hold at least 3 cells per axis");
+    R.nc[a] = (int)std::floor(box->L[a] / P.rc);
+    if (R.nc[a] < 3)
+      return fail(nullptr, DPD_E_INVAL, pre + "box must hold at least 3 cells per axis");
   }
-  const int64_t ncell = (int64_t)nc[0] * nc[1] * nc[2];
-  if (ncell > (int64_t)1 << 30) return fail(nullptr, DPD_E_INVAL, "too many cells");
+  R.ncell = (int64_t)R.nc[0] * R.nc[1] * R.nc[2];
+  if (R.ncell > (int64_t)1 << 30) return fail(nullptr, DPD_E_INVAL, pre + "too many cells");
   if (!(phi->dtype == 4 || phi->dtype == 8))
-    return fail(nullptr, DPD_E_INVAL, "phi dtype must be 4 or 8");
-  if (!phi->data) return fail(nullptr, DPD_E_INVAL, "phi data is NULL");
+    return fail(nullptr, DPD_E_INVAL, pre + "phi dtype must be 4 or 8");
+  if (!phi->data) return fail(nullptr, DPD_E_INVAL, pre + "phi data is NULL");
   for (int a = 0; a < 3; ++a) {
     if (phi->n[a] < 2 || !(phi->h[a] > 0))
-      return fail(nullptr, DPD_E_INVAL, "phi grid needs >= 2 nodes and h > 0 per axis");
+      return fail(nullptr, DPD_E_INVAL, pre + "phi grid needs >= 2 nodes and h > 0 per axis");
     if (std::fabs(phi->n[a] * phi->h[a] - box->L[a]) > 1e-9 * box->L[a])
-      return fail(nullptr, DPD_E_INVAL, "phi grid n*h must equal the box edge");
+      return fail(nullptr, DPD_E_INVAL, pre + "phi grid n*h must equal the box edge");
   }
   const int64_t n = pp->n;
   if (n < 0 || n >= ((int64_t)1 << 31))
-    return fail(nullptr, DPD_E_INVAL, "particle count out of range");
+    return fail(nullptr, DPD_E_INVAL, pre + "particle count out of range");
   if (n > 0 && (!pp->pos || !pp->vel || !pp->type))
-    return fail(nullptr, DPD_E_INVAL, "particle arrays are NULL");
-
-  // ---- bring particle arrays to the host for validation and splitting ----
-  std::vector<float> hpos(3 * (size_t)n), hvel(3 * (size_t)n);
-  std::vector<int32_t> htype((size_t)n);
-  std::vector<uint32_t> hgid((size_t)n);
+    return fail(nullptr, DPD_E_INVAL, pre + "particle arrays are NULL");
+  H.pos.resize(3 * (size_t)n);
+  H.vel.resize(3 * (size_t)n);
+  H.type.resize((size_t)n);
+  H.gid.resize((size_t)n);
   if (n > 0) {
     if (pp->on_device) {
-      if (hipMemcpy(hpos.data(), pp->pos, 12 * (size_t)n, hipMemcpyDeviceToHost) != hipSuccess ||
-          hipMemcpy(hvel.data(), pp->vel, 12 * (size_t)n, hipMemcpyDeviceToHost) != hipSuccess ||
-          hipMemcpy(htype.data(), pp->type, 4 * (size_t)n, hipMemcpyDeviceToHost) != hipSuccess ||
-          (pp->gid && hipMemcpy(hgid.data(), pp->gid, 4 * (size_t)n, hipMemcpyDeviceToHost) !=
+      if (hipMemcpy(H.pos.data(), pp->pos, 12 * (size_t)n, hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(H.vel.data(), pp->vel, 12 * (size_t)n, hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(H.type.data(), pp->type, 4 * (size_t)n, hipMemcpyDeviceToHost) != hipSuccess ||
+          (pp->gid && hipMemcpy(H.gid.data(), pp->gid, 4 * (size_t)n, hipMemcpyDeviceToHost) !=
                           hipSuccess))
-        return fail(nullptr, DPD_E_DEVICE, "copying particle arrays failed");
+        return fail(nullptr, DPD_E_DEVICE, pre + "copying particle arrays failed");
     } else {
-      std::memcpy(hpos.data(), pp->pos, 12 * (size_t)n);
-      std::memcpy(hvel.data(), pp->vel, 12 * (size_t)n);
-      std::memcpy(htype.data(), pp->type, 4 * (size_t)n);
-      if (pp->gid) std::memcpy(hgid.data(), pp->gid, 4 * (size_t)n);
+      std::memcpy(H.pos.data(), pp->pos, 12 * (size_t)n);
+      std::memcpy(H.vel.data(), pp->vel, 12 * (size_t)n);
+      std::memcpy(H.type.data(), pp->type, 4 * (size_t)n);
+      if (pp->gid) std::memcpy(H.gid.data(), pp->gid, 4 * (size_t)n);
     }
   }
   if (!pp->gid)
-    for (int64_t i = 0; i < n; ++i) hgid[i] = (uint32_t)i;
+    for (int64_t i = 0; i < n; ++i) H.gid[i] = (uint32_t)i;
   {
     std::vector<uint8_t> seen((size_t)n, 0);
     for (int64_t i = 0; i < n; ++i) {
-      if (hgid[i] >= (uint64_t)n || seen[hgid[i]])
-        return fail(nullptr, DPD_E_INVAL, "gid must be a permutation of 0..n-1");
-      seen[hgid[i]] = 1;
+      if (H.gid[i] >= (uint64_t)n || seen[H.gid[i]])
+        return fail(nullptr, DPD_E_INVAL, pre + "gid must be a permutation of 0..n-1");
+      seen[H.gid[i]] = 1;
     }
   }
-  std::vector<int64_t> rows_f, rows_w;
   for (int64_t i = 0; i < n; ++i) {
-    if (htype[i] != DPD_TYPE_FLUID && htype[i] != DPD_TYPE_WALL)
-      return fail(nullptr, DPD_E_INVAL, "type must be 0 (fluid) or 1 (wall)");
-    if (!finite3(&hpos[3 * i]) || (htype[i] == DPD_TYPE_FLUID && !finite3(&hvel[3 * i])))
-      return fail(nullptr, DPD_E_INVAL, "non-finite particle position or velocity");
+    if (H.type[i] != DPD_TYPE_FLUID && H.type[i] != DPD_TYPE_WALL)
+      return fail(nullptr, DPD_E_INVAL, pre + "type must be 0 (fluid) or 1 (wall)");
+    if (!finite3(&H.pos[3 * i]) || (H.type[i] == DPD_TYPE_FLUID && !finite3(&H.vel[3 * i])))
+      return fail(nullptr, DPD_E_INVAL, pre + "non-finite particle position or velocity");
     for (int a = 0; a < 3; ++a)
-      if (!(hpos[3 * i + a] >= 0.0f && hpos[3 * i + a] < (float)box->L[a]))
-        return fail(nullptr, DPD_E_INVAL, "particle position outside [0, L)");
-    (htype[i] == DPD_TYPE_FLUID ? rows_f : rows_w).push_back(i);
+      if (!(H.pos[3 * i + a] >= 0.0f && H.pos[3 * i + a] < (float)box->L[a]))
+        return fail(nullptr, DPD_E_INVAL, pre + "particle position outside [0, L)");
+    (H.type[i] == DPD_TYPE_FLUID ? H.rows_f : H.rows_w).push_back(i);
   }
+  R.n = n;
+  R.nf = (int64_t)H.rows_f.size();
+  R.nw = (int64_t)H.rows_w.size();
+  for (int a = 0; a < 3; ++a) {
+    R.ng[a] = phi->n[a];
+    R.L[a] = box->L[a];
+    R.h[a] = phi->h[a];
+    R.G.L[a] = (float)box->L[a];
+    R.G.invw[a] = (float)((double)R.nc[a] / box->L[a]);
+    R.G.nc[a] = R.nc[a];
+    R.G.ng[a] = phi->n[a];
+    R.G.inv_h[a] = (float)(1.0 / phi->h[a]);
+    R.G.inv_h64[a] = 1.0 / phi->h[a];
+    R.G.h[a] = (float)phi->h[a];
+  }
+  KParams &K = R.P;
+  K.a_ff = (float)P.a[0];
+  K.a_fw = (float)P.a[1];
+  K.gamma = (float)P.gamma;
+  K.sigma_rdt = (float)(std::sqrt(2.0 * P.gamma * P.kBT) / std::sqrt(P.dt));
+  K.rc2 = (float)(P.rc * P.rc);
+  K.inv_rc = (float)(1.0 / P.rc);
+  K.dt = (float)P.dt;
+  K.hdt = (float)(0.5 * P.dt);
+  K.lamdt = (float)(P.lambda * P.dt);
+  for (int a = 0; a < 3; ++a) K.g[a] = (float)P.g[a];
+  double wmin = box->L[0] / R.nc[0];
+  for (int a = 1; a < 3; ++a) wmin = std::fmin(wmin, box->L[a] / R.nc[a]);
+  K.max_disp2 = (float)(0.25 * wmin * wmin);
+  K.key0 = (uint32_t)P.seed;
+  K.key1 = (uint32_t)(P.seed >> 32);
+  K.replica = P.replica;
+  return DPD_OK;
+}
 
-  // ---- device (after the host-side checks, which need none) ----
+int create_impl(int32_t nbox, const dpd_box *boxes, const dpd_particles *parts,
+                const dpd_params *params, const dpd_phi_grid *grids,
+                const dpd_allocator *alloc, void *hip_stream, dpd_ctx **out) {
+  if (!out) return fail(nullptr, DPD_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (nbox < 1) return fail(nullptr, DPD_E_INVAL, "need at least one box");
+  if (!boxes || !parts || !params || !grids) return fail(nullptr, DPD_E_INVAL, "NULL argument");
+
+  // ---- host-side checks, which need no device ----
+  std::vector<Replica> rep((size_t)nbox);
+  std::vector<HostBox> host((size_t)nbox);
+  for (int r = 0; r < nbox; ++r) {
+    int rc = check_box(r, &boxes[r], &parts[r], &params[r], &grids[r], rep[r], host[r]);
+    if (rc) return rc;
+    if (grids[r].dtype != grids[0].dtype)
+      return fail(nullptr, DPD_E_INVAL, "all phi grids of a batch must have the same dtype");
+    if ((params[r].flags & DPD_FLAG_NO_MASK) != (params[0].flags & DPD_FLAG_NO_MASK))
+      return fail(nullptr, DPD_E_INVAL, "all boxes of a batch must use the same flags");
+  }
+  int64_t NF = 0, NW = 0, NCELL = 0, NGRID = 0, NWORDS = 0;
+  for (int r = 0; r < nbox; ++r) {
+    Replica &p = rep[r];
+    p.fo = NF;
+    p.wo = NW;
+    p.co = NCELL;
+    p.go = NGRID;
+    p.bo = NWORDS;
+    const int64_t nodes = (int64_t)p.ng[0] * p.ng[1] * p.ng[2];
+    p.nwords = (nodes + 31) / 32;
+    NF += p.nf;
+    NW += p.nw;
+    NCELL += p.ncell;
+    NGRID += nodes;
+    NWORDS += p.nwords;
+  }
+  if (NF + NW + 1 >= ((int64_t)1 << 31) || NCELL >= ((int64_t)1 << 31))
+    return fail(nullptr, DPD_E_INVAL, "too many particles or cells in total");
+
+  // ---- device (after the host-side checks) ----
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
     return fail(nullptr, DPD_E_DEVICE, "no HIP device");
@@ -400,161 +593,153 @@ int dpd_create(const dpd_box *box, const dpd_particles *pp, const dpd_params *pr
     c->al = *alloc;
     c->has_al = true;
   }
-  c->params = P;
-  c->n = n;
-  c->nf = (int64_t)rows_f.size();
-  c->nw = (int64_t)rows_w.size();
-  c->ncell = ncell;
-  c->grid_f64 = phi->dtype == 8;
-  for (int a = 0; a < 3; ++a) {
-    c->nc[a] = nc[a];
-    c->ng[a] = phi->n[a];
-    c->L[a] = box->L[a];
-    c->h[a] = phi->h[a];
-    c->G.L[a] = (float)box->L[a];
-    c->G.invw[a] = (float)((double)nc[a] / box->L[a]);
-    c->G.nc[a] = nc[a];
-    c->G.ng[a] = phi->n[a];
-    c->G.inv_h[a] = (float)(1.0 / phi->h[a]);
-    c->G.inv_h64[a] = 1.0 / phi->h[a];
-    c->G.h[a] = (float)phi->h[a];
-  }
-  {
-    KParams &K = c->P;
-    K.a_ff = (float)P.a[0];
-    K.a_fw = (float)P.a[1];
-    K.gamma = (float)P.gamma;
-    K.sigma_rdt = (float)(std::sqrt(2.0 * P.gamma * P.kBT) / std::sqrt(P.dt));
-    K.rc2 = (float)(P.rc * P.rc);
-    K.inv_rc = (float)(1.0 / P.rc);
-    K.dt = (float)P.dt;
-    K.hdt = (float)(0.5 * P.dt);
-    K.lamdt = (float)(P.lambda * P.dt);
-    for (int a = 0; a < 3; ++a) K.g[a] = (float)P.g[a];
-    double wmin = box->L[0] / nc[0];
-    for (int a = 1; a < 3; ++a) wmin = std::fmin(wmin, box->L[a] / nc[a]);
-    K.max_disp2 = (float)(0.25 * wmin * wmin);
-    K.key0 = (uint32_t)P.seed;
-    K.key1 = (uint32_t)(P.seed >> 32);
-    K.replica = P.replica;
-  }
-  c->use_mask = (P.flags & DPD_FLAG_NO_MASK) ? 0 : 1;
-
+  c->R = nbox;
+  c->rep = rep;
+  c->NF = NF;
+  c->NW = NW;
+  c->NCELL = NCELL;
+  c->NGRID = NGRID;
+  c->NWORDS = NWORDS;
+  c->grid_f64 = grids[0].dtype == 8;
+  c->use_mask = (params[0].flags & DPD_FLAG_NO_MASK) ? 0 : 1;
   auto bail = [c](int code) { return abandon_create(c, code); };
 
   // ---- device buffers ----
-  const size_t nf = (size_t)c->nf, nw = (size_t)c->nw;
-  const size_t gbytes = (size_t)phi->n[0] * phi->n[1] * phi->n[2] * (size_t)phi->dtype;
+  const size_t nf = (size_t)NF, nw = (size_t)NW, ncell = (size_t)NCELL;
   for (int b = 0; b < 2; ++b) {
     c->pos[b] = (float4 *)dalloc(c, 16 * (nf + nw + 1));
     c->vel[b] = (float4 *)dalloc(c, 16 * nf);
     c->frc[b] = (float4 *)dalloc(c, 16 * nf);
   }
   c->vt = (float4 *)dalloc(c, 16 * (nf + nw + 1));
-  c->cell_of = (int32_t *)dalloc(c, 4 * (nf > nw ? nf : nw));
-  c->rank_of = (int32_t *)dalloc(c, 4 * (nf > nw ? nf : nw));
-  c->idx = (int32_t *)dalloc(c, 4 * (nf > nw ? nf : nw));
-  c->count = (int32_t *)dalloc(c, 4 * (size_t)ncell);
-  c->cstart = (int32_t *)dalloc(c, 4 * ((size_t)ncell + 1));
-  c->nscan = dpd::scan_blocks(ncell);
+  c->cell_of = (int32_t *)dalloc(c, 4 * std::max(nf, nw));
+  c->rank_of = (int32_t *)dalloc(c, 4 * std::max(nf, nw));
+  c->idx = (int32_t *)dalloc(c, 4 * std::max(nf, nw));
+  c->count = (int32_t *)dalloc(c, 4 * ncell);
+  c->cstart = (int32_t *)dalloc(c, 4 * (ncell + 1));
+  c->nscan = dpd::scan_blocks(NCELL);
   c->bsum = (int32_t *)dalloc(c, 4 * (size_t)c->nscan);
-  c->wcstart = (int32_t *)dalloc(c, 4 * ((size_t)ncell + 1));
+  c->wcstart = (int32_t *)dalloc(c, 4 * (ncell + 1));
   c->wcell = (int32_t *)dalloc(c, 4 * nw);
   c->idx_all = (int32_t *)dalloc(c, 4 * (nf + nw));
-  c->start_all = (int32_t *)dalloc(c, 4 * ((size_t)ncell + 1));
-  c->fluid_off = (int32_t *)dalloc(c, 4 * (size_t)ncell);
-  c->grid = dalloc(c, gbytes);
-  c->nwords = ((int64_t)phi->n[0] * phi->n[1] * phi->n[2] + 31) / 32;
-  c->bits = (uint32_t *)dalloc(c, 4 * (size_t)c->nwords);
+  c->start_all = (int32_t *)dalloc(c, 4 * (ncell + 1));
+  c->fluid_off = (int32_t *)dalloc(c, 4 * ncell);
+  c->grid = dalloc(c, (size_t)NGRID * (size_t)grids[0].dtype);
+  c->bits = (uint32_t *)dalloc(c, 4 * (size_t)NWORDS);
+  c->boxes = (Box *)dalloc(c, sizeof(Box) * (size_t)nbox);
   c->status = (Status *)dalloc(c, sizeof(Status));
+  c->dk = (unsigned long long *)dalloc(c, 8);
   c->pair_counter = (unsigned long long *)dalloc(c, 8);
   for (int b = 0; b < 2; ++b)
-    if (!c->pos[b] || !c->vel[b] || !c->frc[b]) return bail(fail(c, DPD_E_NOMEM, "device allocation failed"));
+    if (!c->pos[b] || !c->vel[b] || !c->frc[b])
+      return bail(fail(c, DPD_E_NOMEM, "device allocation failed"));
   if (!c->vt || !c->cell_of || !c->rank_of || !c->idx || !c->count || !c->cstart || !c->bsum ||
-      !c->wcell || !c->idx_all || !c->start_all || !c->fluid_off || !c->wcstart || !c->grid || !c->bits || !c->status || !c->pair_counter)
+      !c->wcstart || !c->wcell || !c->idx_all || !c->start_all || !c->fluid_off || !c->grid ||
+      !c->bits || !c->boxes || !c->status || !c->dk || !c->pair_counter)
     return bail(fail(c, DPD_E_NOMEM, "device allocation failed"));
 
-  // ---- upload ----
   int rc = DPD_OK;
   auto chk = [&](hipError_t e, const char *w) {
     if (e != hipSuccess && rc == DPD_OK) rc = hip_fail(c, e, w);
   };
-  chk(hipMemcpyAsync(c->grid, phi->data, gbytes,
-                     phi->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream),
-      "upload phi");
   chk(dpd::launch_fill_zero(c->stream, c->status, sizeof(Status)), "zero status");
-  chk(dpd::launch_fill_zero(c->stream, c->count, 4 * (size_t)ncell), "zero counts");
+  chk(dpd::launch_fill_zero(c->stream, c->count, 4 * ncell), "zero counts");
   chk(dpd::launch_fill_zero(c->stream, c->pair_counter, 8), "zero counter");
+  chk(dpd::launch_fill_zero(c->stream, c->dk, 8), "zero k");
+  for (int r = 0; r < nbox; ++r) {
+    const Replica &p = c->rep[r];
+    const size_t gb = (size_t)p.ng[0] * p.ng[1] * p.ng[2] * (size_t)grids[0].dtype;
+    chk(hipMemcpyAsync((char *)c->grid + (size_t)p.go * grids[0].dtype, grids[r].data, gb,
+                       grids[r].on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                       c->stream),
+        "upload phi");
+  }
   if (rc) return bail(rc);
+
+  // ---- particles: fluid into its slots, walls sorted by cell (once) ----
   {
-    // staging of all input rows on the device, released before returning
-    const size_t nn = (size_t)(n > 0 ? n : 1);
-    float *dpos = (float *)dalloc(c, 12 * nn);
-    float *dvel = (float *)dalloc(c, 12 * nn);
-    uint32_t *dgid = (uint32_t *)dalloc(c, 4 * nn);
-    int64_t *drows_f = (int64_t *)dalloc(c, 8 * (nf > 0 ? nf : 1));
-    int64_t *drows_w = (int64_t *)dalloc(c, 8 * (nw > 0 ? nw : 1));
-    float4 *wtmp = (float4 *)dalloc(c, 16 * (nw > 0 ? nw : 1));
-    if (!dpos || !dvel || !dgid || !drows_f || !drows_w || !wtmp)
-      return bail(fail(c, DPD_E_NOMEM, "staging allocation failed"));
-    if (n > 0) {
-      chk(hipMemcpyAsync(dpos, hpos.data(), 12 * (size_t)n, hipMemcpyHostToDevice, c->stream), "upload pos");
-      chk(hipMemcpyAsync(dvel, hvel.data(), 12 * (size_t)n, hipMemcpyHostToDevice, c->stream), "upload vel");
-      chk(hipMemcpyAsync(dgid, hgid.data(), 4 * (size_t)n, hipMemcpyHostToDevice, c->stream), "upload gid");
+    float4 *wtmp = (float4 *)dalloc(c, 16 * std::max<size_t>(nw, 1));
+    if (!wtmp) return bail(fail(c, DPD_E_NOMEM, "staging allocation failed"));
+    for (int r = 0; r < nbox && !rc; ++r) {
+      const Replica &p = c->rep[r];
+      const HostBox &H = host[r];
+      const size_t nn = (size_t)std::max<int64_t>(p.n, 1);
+      float *dpos = (float *)dalloc(c, 12 * nn);
+      float *dvel = (float *)dalloc(c, 12 * nn);
+      uint32_t *dgid = (uint32_t *)dalloc(c, 4 * nn);
+      int64_t *drows = (int64_t *)dalloc(c, 8 * nn);
+      if (!dpos || !dvel || !dgid || !drows)
+        return bail(fail(c, DPD_E_NOMEM, "staging allocation failed"));
+      if (p.n > 0) {
+        chk(hipMemcpyAsync(dpos, H.pos.data(), 12 * (size_t)p.n, hipMemcpyHostToDevice, c->stream), "upload pos");
+        chk(hipMemcpyAsync(dvel, H.vel.data(), 12 * (size_t)p.n, hipMemcpyHostToDevice, c->stream), "upload vel");
+        chk(hipMemcpyAsync(dgid, H.gid.data(), 4 * (size_t)p.n, hipMemcpyHostToDevice, c->stream), "upload gid");
+      }
+      if (p.nf > 0) {
+        chk(hipMemcpyAsync(drows, H.rows_f.data(), 8 * (size_t)p.nf, hipMemcpyHostToDevice, c->stream), "rows");
+        chk(dpd::launch_pack(c->stream, p.nf, dpos, dvel, dgid, drows, c->pos[0] + p.fo,
+                             c->vel[0] + p.fo, c->vt + p.fo, c->frc[0] + p.fo),
+            "pack fluid");
+      }
+      if (p.nw > 0) {
+        chk(hipStreamSynchronize(c->stream), "sync");
+        chk(hipMemcpyAsync(drows, H.rows_w.data(), 8 * (size_t)p.nw, hipMemcpyHostToDevice, c->stream), "rows");
+        chk(dpd::launch_pack(c->stream, p.nw, dpos, nullptr, dgid, drows, wtmp + p.wo, nullptr,
+                             nullptr, nullptr),
+            "pack walls");
+        chk(dpd::launch_bin(c->stream, p.G, p.co, p.nw, wtmp + p.wo, c->cell_of + p.wo,
+                            c->rank_of + p.wo, c->count),
+            "bin walls");
+      }
+      chk(hipStreamSynchronize(c->stream), "sync");
+      for (void *q : {(void *)dpos, (void *)dvel, (void *)dgid, (void *)drows}) dfree(c, q);
     }
-    if (nf > 0) {
-      chk(hipMemcpyAsync(drows_f, rows_f.data(), 8 * nf, hipMemcpyHostToDevice, c->stream), "rows");
-      chk(dpd::launch_pack(c->stream, (int64_t)nf, dpos, dvel, dgid, drows_f, c->pos[0],
-                           c->vel[0], c->vt, c->frc[0]),
-          "pack fluid");
-    }
-    // frozen walls: pack, bin, scan, scatter, sort each cell, permute (once)
-    if (nw > 0) {
-      chk(hipMemcpyAsync(drows_w, rows_w.data(), 8 * nw, hipMemcpyHostToDevice, c->stream), "rows");
-      chk(dpd::launch_pack(c->stream, (int64_t)nw, dpos, nullptr, dgid, drows_w, wtmp, nullptr,
-                           nullptr, nullptr),
-          "pack walls");
-      chk(dpd::launch_bin(c->stream, c->G, (int64_t)nw, wtmp, c->cell_of, c->rank_of, c->count),
-          "bin walls");
-    }
-    chk(dpd::launch_scan_reduce(c->stream, ncell, c->count, c->bsum), "scan");
+    chk(dpd::launch_scan_reduce(c->stream, NCELL, c->count, c->bsum), "scan");
     chk(dpd::launch_scan_top(c->stream, c->nscan, c->bsum), "scan");
-    chk(dpd::launch_scan_down(c->stream, ncell, c->count, c->wcstart, c->bsum, nullptr, nullptr,
+    chk(dpd::launch_scan_down(c->stream, NCELL, c->count, c->wcstart, c->bsum, nullptr, nullptr,
                               nullptr),
         "scan");
     if (nw > 0) {
-      // walls sorted by cell into the tail of both position buffers (static),
-      // with zero predicted velocity
-      chk(dpd::launch_scatter(c->stream, (int64_t)nw, c->cell_of, c->rank_of, c->wcstart, c->idx),
+      // walls sorted by global cell (so each box's walls stay contiguous)
+      // into the tail of both position buffers, with zero predicted velocity
+      chk(dpd::launch_scatter(c->stream, NW, c->cell_of, c->rank_of, c->wcstart, c->idx),
           "scatter walls");
-      chk(dpd::launch_sort_cells(c->stream, ncell, c->wcstart, c->idx, nullptr, nullptr),
+      chk(dpd::launch_sort_cells(c->stream, NCELL, c->wcstart, c->idx, nullptr, nullptr),
           "sort walls");
-      chk(dpd::launch_permute(c->stream, (int64_t)nw, c->idx, wtmp, c->pos[0] + nf, nullptr,
-                              nullptr, nullptr, nullptr),
+      chk(dpd::launch_permute(c->stream, NW, c->idx, wtmp, c->pos[0] + nf, nullptr, nullptr,
+                              nullptr, nullptr),
           "permute walls");
       chk(hipMemcpyAsync(c->pos[1] + nf, c->pos[0] + nf, 16 * nw, hipMemcpyDeviceToDevice,
                          c->stream),
           "copy walls");
       chk(dpd::launch_fill_zero(c->stream, c->vt + nf, 16 * nw), "zero wall velocities");
-      chk(dpd::launch_cells(c->stream, c->G, (int64_t)nw, c->pos[0] + nf, c->wcell), "wall cells");
+      for (int r = 0; r < nbox; ++r) {
+        const Replica &p = c->rep[r];
+        chk(dpd::launch_cells(c->stream, p.G, p.co, p.nw, c->pos[0] + nf + p.wo, c->wcell + p.wo),
+            "wall cells");
+      }
     }
     chk(dpd::launch_set_pad(c->stream, c->pos[0] + nf + nw, c->vt + nf + nw), "pad");
     chk(dpd::launch_set_pad(c->stream, c->pos[1] + nf + nw, nullptr), "pad");
     chk(hipStreamSynchronize(c->stream), "sync");
-    for (void *q : {(void *)dpos, (void *)dvel, (void *)dgid, (void *)drows_f, (void *)drows_w,
-                    (void *)wtmp})
-      dfree(c, q);
+    dfree(c, wtmp);
     if (rc) return bail(rc);
   }
-  // near-interface mask and create-time phi check
-  {
-    chk(dpd::launch_cube_mask(c->stream, c->G, c->grid, c->grid_f64, c->nwords, c->bits), "mask");
-    chk(dpd::launch_check_grid(c->stream, c->grid, c->grid_f64,
-                               (int64_t)phi->n[0] * phi->n[1] * phi->n[2], c->status),
+
+  // ---- phase field: cube masks and create-time checks ----
+  for (int r = 0; r < nbox; ++r) {
+    const Replica &p = c->rep[r];
+    const size_t es = (size_t)grids[0].dtype;
+    const void *g = (const char *)c->grid + (size_t)p.go * es;
+    chk(dpd::launch_cube_mask(c->stream, p.G, g, c->grid_f64, p.nwords, c->bits + p.bo), "mask");
+    chk(dpd::launch_check_grid(c->stream, g, c->grid_f64, (int64_t)p.ng[0] * p.ng[1] * p.ng[2],
+                               c->status),
         "check grid");
-    chk(dpd::launch_check_phi(c->stream, c->G, c->grid, c->grid_f64, c->nf, c->pos[0], c->status),
+    chk(dpd::launch_check_phi(c->stream, p.G, g, c->grid_f64, p.nf, c->pos[0] + p.fo, c->status),
         "check phi");
-    if (rc) return bail(rc);
+  }
+  if (rc) return bail(rc);
+  {
     Status st;
     int r2 = read_status(c, st);
     if (r2) return bail(r2);
@@ -563,20 +748,43 @@ int dpd_create(const dpd_box *box, const dpd_particles *pp, const dpd_params *pr
     if (st.bad_phi)
       return bail(fail(c, DPD_E_INVAL,
                        std::to_string(st.bad_phi) + " fluid particles start at phi < 0"));
-    std::vector<uint32_t> hb((size_t)c->nwords);
-    chk(hipMemcpy(hb.data(), c->bits, 4 * (size_t)c->nwords, hipMemcpyDeviceToHost),
-        "mask readback");
+    std::vector<uint32_t> hb((size_t)NWORDS);
+    chk(hipMemcpy(hb.data(), c->bits, 4 * (size_t)NWORDS, hipMemcpyDeviceToHost), "mask readback");
     if (rc) return bail(rc);
-    int64_t m = 0;
-    for (uint32_t v : hb) m += __builtin_popcount(v);
-    c->flagged_cubes = m;
+    for (int r = 0; r < nbox; ++r) {
+      int64_t m = 0;
+      for (int64_t w = 0; w < c->rep[r].nwords; ++w) m += __builtin_popcount(hb[c->rep[r].bo + w]);
+      c->rep[r].flagged_cubes = m;
+    }
   }
-  // initial cell list and forces f(0) with k = 0
+
+  // ---- descriptors, tiles, initial cell list and forces f(0) with k = 0 ----
+  {
+    std::vector<Box> hb((size_t)nbox);
+    for (int r = 0; r < nbox; ++r) {
+      const Replica &p = c->rep[r];
+      hb[r].G = p.G;
+      hb[r].P = p.P;
+      hb[r].fo = p.fo;
+      hb[r].nf = p.nf;
+      hb[r].wo = p.wo;
+      hb[r].nw = p.nw;
+      hb[r].co = p.co;
+      hb[r].ncell = p.ncell;
+      hb[r].go = p.go;
+      hb[r].bo = p.bo;
+    }
+    chk(hipMemcpy(c->boxes, hb.data(), sizeof(Box) * (size_t)nbox, hipMemcpyHostToDevice),
+        "upload boxes");
+    if (rc) return bail(rc);
+  }
+  rc = set_shapes(c, 2, 256);
+  if (rc) return bail(rc);
   c->cur = 0;
   c->k = 0;
-  rc = build_cells_from_pos(c);
-  if (!rc) rc = scan_scatter_sort(c);
-  if (!rc) rc = force_pass(c, 1);
+  rc = bin_all(c, c->stream);
+  if (!rc) rc = scan_scatter_sort(c, c->stream);
+  if (!rc) rc = force_pass(c, c->stream, 1);
   if (!rc) {
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) rc = hip_fail(c, e, "initial forces");
@@ -586,6 +794,69 @@ int dpd_create(const dpd_box *box, const dpd_particles *pp, const dpd_params *pr
   *out = c;
   return DPD_OK;
 }
+
+int check_replica(dpd_ctx *c, int32_t r) {
+  if (r < 0 || r >= c->R) return fail(c, DPD_E_INVAL, "replica index out of range");
+  return DPD_OK;
+}
+
+// Time `steps` steps of the current shapes from the saved state; returns ms.
+int trial(dpd_ctx *c, int steps, float *ms) {
+  hipEvent_t a = get_event(c), b = get_event(c);
+  int rc = one_step(c);  // warm-up (and graph capture)
+  if (!rc) (void)hipEventRecord(a, c->stream);
+  for (int s = 0; s < steps && !rc; ++s) rc = one_step(c);
+  if (!rc) (void)hipEventRecord(b, c->stream);
+  if (!rc) {
+    hipError_t e = hipEventSynchronize(b);
+    if (e != hipSuccess)
+      rc = hip_fail(c, e, "autotune");
+    else if (hipEventElapsedTime(ms, a, b) != hipSuccess)
+      rc = fail(c, DPD_E_DEVICE, "timing");
+  }
+  c->free_events.push_back(a);
+  c->free_events.push_back(b);
+  return rc;
+}
+
+std::string tune_signature(dpd_ctx *c) {
+  hipDeviceProp_t prop;
+  std::string dev = "unknown";
+  if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) dev = prop.gcnArchName;
+  for (auto &ch : dev)
+    if (ch == ' ') ch = '_';
+  std::ostringstream s;
+  s << dev << ":R" << c->R << ":F" << c->NF << ":W" << c->NW << ":C" << c->NCELL << ":g"
+    << (c->use_graph ? 1 : 0);
+  return s.str();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *dpd_last_error(const dpd_ctx *ctx) {
+  return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+const char *dpd_kernel_name(int32_t i) {
+  if (i < 0 || i >= DPD_NUM_KERNELS) return "";
+  return kKernelNames[i];
+}
+
+int dpd_create(const dpd_box *box, const dpd_particles *pp, const dpd_params *prm,
+               const dpd_phi_grid *phi, const dpd_allocator *alloc, void *hip_stream,
+               dpd_ctx **out) {
+  return create_impl(1, box, pp, prm, phi, alloc, hip_stream, out);
+}
+
+int dpd_batch_create(int32_t nbox, const dpd_box *boxes, const dpd_particles *particles,
+                     const dpd_params *params, const dpd_phi_grid *grids,
+                     const dpd_allocator *alloc, void *hip_stream, dpd_ctx **out) {
+  return create_impl(nbox, boxes, particles, params, grids, alloc, hip_stream, out);
+}
+
+int dpd_replica_count(const dpd_ctx *c) { return c ? c->R : DPD_E_INVAL; }
 
 int dpd_step(dpd_ctx *c, int64_t nsteps) {
   if (!c) return DPD_E_INVAL;
@@ -597,58 +868,76 @@ int dpd_step(dpd_ctx *c, int64_t nsteps) {
   return DPD_OK;
 }
 
-int dpd_forces(dpd_ctx *c, float *f_out) {
+int dpd_use_graph(dpd_ctx *c, int32_t enable) {
   if (!c) return DPD_E_INVAL;
+  if ((enable != 0) != c->use_graph) drop_graphs(c);
+  c->use_graph = enable != 0;
+  return DPD_OK;
+}
+
+int dpd_replica_forces(dpd_ctx *c, int32_t r, float *f_out) {
+  if (!c) return DPD_E_INVAL;
+  if (check_replica(c, r)) return DPD_E_INVAL;
   if (!f_out) return fail(c, DPD_E_INVAL, "f_out is NULL");
-  HIP_TRY(c, dpd::launch_fill_zero(c->stream, f_out, 12 * (size_t)c->n));
-  HIP_TRY(c, dpd::launch_export(c->stream, c->G, c->nf, c->pos[c->cur], c->vel[c->cur],
-                                c->frc[c->cur], 0, nullptr, nullptr, f_out, nullptr, nullptr));
+  const Replica &p = c->rep[r];
+  HIP_TRY(c, dpd::launch_fill_zero(c->stream, f_out, 12 * (size_t)p.n));
+  HIP_TRY(c, dpd::launch_export(c->stream, p.G, p.nf, c->pos[c->cur] + p.fo,
+                                c->vel[c->cur] + p.fo, c->frc[c->cur] + p.fo, 0, nullptr,
+                                nullptr, f_out, nullptr, nullptr));
+  return latched_error(c);
+}
+
+int dpd_forces(dpd_ctx *c, float *f_out) { return dpd_replica_forces(c, 0, f_out); }
+
+int dpd_replica_state(dpd_ctx *c, int32_t r, float *pos, float *vel, int32_t *events,
+                      int32_t *cell_of) {
+  if (!c) return DPD_E_INVAL;
+  if (check_replica(c, r)) return DPD_E_INVAL;
+  const Replica &p = c->rep[r];
+  HIP_TRY(c, dpd::launch_export(c->stream, p.G, p.nf, c->pos[c->cur] + p.fo,
+                                c->vel[c->cur] + p.fo, c->frc[c->cur] + p.fo, 0, pos, vel,
+                                nullptr, events, cell_of));
+  HIP_TRY(c, dpd::launch_export(c->stream, p.G, p.nw, c->pos[c->cur] + c->NF + p.wo, nullptr,
+                                nullptr, 1, pos, vel, nullptr, events, cell_of));
   return latched_error(c);
 }
 
 int dpd_get_state(dpd_ctx *c, float *pos, float *vel, int32_t *events, int32_t *cell_of) {
-  if (!c) return DPD_E_INVAL;
-  HIP_TRY(c, dpd::launch_export(c->stream, c->G, c->nf, c->pos[c->cur], c->vel[c->cur],
-                                c->frc[c->cur], 0, pos, vel, nullptr, events, cell_of));
-  HIP_TRY(c, dpd::launch_export(c->stream, c->G, c->nw, c->pos[c->cur] + c->nf, nullptr, nullptr,
-                                1, pos, vel,
-                                nullptr, events, cell_of));
-  return latched_error(c);
+  return dpd_replica_state(c, 0, pos, vel, events, cell_of);
 }
 
-int dpd_set_state(dpd_ctx *c, const float *pos, const float *vel, const float *force,
-                  uint64_t k, int32_t on_device) {
+int dpd_replica_set_state(dpd_ctx *c, int32_t r, const float *pos, const float *vel,
+                          const float *force, uint64_t k, int32_t on_device) {
   if (!c) return DPD_E_INVAL;
+  if (check_replica(c, r)) return DPD_E_INVAL;
   if (!pos || !vel || !force) return fail(c, DPD_E_INVAL, "NULL state array");
-  const size_t bytes = 12 * (size_t)c->n;
+  const Replica &p = c->rep[r];
+  const size_t bytes = 12 * (size_t)p.n;
   const float *dp = pos, *dv = vel, *df = force;
   float *stage = nullptr;
   if (!on_device) {
-    stage = (float *)dalloc(c, 3 * bytes);
+    stage = (float *)dalloc(c, 3 * std::max<size_t>(bytes, 4));
     if (!stage) return fail(c, DPD_E_NOMEM, "staging allocation failed");
     HIP_TRY(c, hipMemcpyAsync(stage, pos, bytes, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(stage + 3 * c->n, vel, bytes, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(stage + 6 * c->n, force, bytes, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(stage + 3 * p.n, vel, bytes, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(stage + 6 * p.n, force, bytes, hipMemcpyHostToDevice, c->stream));
     dp = stage;
-    dv = stage + 3 * c->n;
-    df = stage + 6 * c->n;
+    dv = stage + 3 * p.n;
+    df = stage + 6 * p.n;
   }
   const int a = c->cur;
-  HIP_TRY(c, dpd::launch_import(c->stream, c->nf, c->pos[a], c->vel[a], c->frc[a], dp, dv, df));
-  // re-sort: cell list of the new positions, permute into slot order
-  HIP_TRY(c, dpd::launch_bin(c->stream, c->G, c->nf, c->pos[a], c->cell_of, c->rank_of, c->count));
-  int rc = scan_scatter_sort(c);
+  HIP_TRY(c, dpd::launch_import(c->stream, p.nf, c->pos[a] + p.fo, c->vel[a] + p.fo,
+                                c->frc[a] + p.fo, dp, dv, df));
+  drop_graphs(c);
+  int rc = resort(c);
   if (rc) return rc;
-  const int b = 1 - a;
-  HIP_TRY(c, dpd::launch_permute(c->stream, c->nf, c->idx, c->pos[a], c->pos[b], c->vel[a],
-                                 c->vel[b], c->frc[a], c->frc[b]));
-  c->cur = b;
   c->k = k;
-  // validate positions: in box and phi >= 0
+  HIP_TRY(c, hipMemcpyAsync(c->dk, &c->k, 8, hipMemcpyHostToDevice, c->stream));
   Status before;
   rc = read_status(c, before);
   if (rc) return rc;
-  HIP_TRY(c, dpd::launch_check_phi(c->stream, c->G, c->grid, c->grid_f64, c->nf, c->pos[c->cur],
+  const void *g = (const char *)c->grid + (size_t)p.go * (c->grid_f64 ? 8 : 4);
+  HIP_TRY(c, dpd::launch_check_phi(c->stream, p.G, g, c->grid_f64, p.nf, c->pos[c->cur] + p.fo,
                                    c->status));
   Status after;
   rc = read_status(c, after);
@@ -659,18 +948,23 @@ int dpd_set_state(dpd_ctx *c, const float *pos, const float *vel, const float *f
   return DPD_OK;
 }
 
-int dpd_neighbor_pairs(dpd_ctx *c, uint32_t *pairs, int64_t cap, int64_t *count) {
+int dpd_set_state(dpd_ctx *c, const float *pos, const float *vel, const float *force,
+                  uint64_t k, int32_t on_device) {
+  return dpd_replica_set_state(c, 0, pos, vel, force, k, on_device);
+}
+
+int dpd_replica_pairs(dpd_ctx *c, int32_t r, uint32_t *pairs, int64_t cap, int64_t *count) {
   if (!c || !count) return DPD_E_INVAL;
+  if (check_replica(c, r)) return DPD_E_INVAL;
   if (cap < 0 || (cap > 0 && !pairs)) return fail(c, DPD_E_INVAL, "bad pair buffer");
-  // cell list of the current positions (state is in slot order already; the
-  // list is rebuilt so that it matches the positions exactly)
+  const Replica &p = c->rep[r];
+  // rebuild the cell list so that it matches the current positions exactly
   HIP_TRY(c, dpd::launch_fill_zero(c->stream, c->pair_counter, 8));
-  HIP_TRY(c, dpd::launch_bin(c->stream, c->G, c->nf, c->pos[c->cur], c->cell_of, c->rank_of,
-                             c->count));
-  int rc = scan_scatter_sort(c);
+  int rc = bin_all(c, c->stream);
+  if (!rc) rc = scan_scatter_sort(c, c->stream);
   if (rc) return rc;
-  HIP_TRY(c, dpd::launch_pairs(c->stream, c->G, c->P, c->nf, c->pos[c->cur], c->idx, c->idx_all,
-                               c->start_all, pairs, cap, c->pair_counter));
+  HIP_TRY(c, dpd::launch_pairs(c->stream, p.G, p.P, p.co, p.fo, p.nf, c->pos[c->cur], c->idx,
+                               c->idx_all, c->start_all, pairs, cap, c->pair_counter));
   unsigned long long cnt = 0;
   HIP_TRY(c, hipMemcpyAsync(&cnt, c->pair_counter, 8, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -678,13 +972,24 @@ int dpd_neighbor_pairs(dpd_ctx *c, uint32_t *pairs, int64_t cap, int64_t *count)
   return latched_error(c);
 }
 
-int dpd_profile(dpd_ctx *c, int32_t axis, int32_t nbins, double *out) {
+int dpd_neighbor_pairs(dpd_ctx *c, uint32_t *pairs, int64_t cap, int64_t *count) {
+  return dpd_replica_pairs(c, 0, pairs, cap, count);
+}
+
+int dpd_replica_profile(dpd_ctx *c, int32_t r, int32_t axis, int32_t nbins, double *out) {
   if (!c) return DPD_E_INVAL;
-  if (axis < 0 || axis > 2 || nbins <= 0 || !out) return fail(c, DPD_E_INVAL, "bad profile arguments");
+  if (check_replica(c, r)) return DPD_E_INVAL;
+  if (axis < 0 || axis > 2 || nbins <= 0 || !out)
+    return fail(c, DPD_E_INVAL, "bad profile arguments");
+  const Replica &p = c->rep[r];
   HIP_TRY(c, dpd::launch_fill_zero(c->stream, out, 5 * 8 * (size_t)nbins));
-  HIP_TRY(c, dpd::launch_profile(c->stream, c->G, c->nf, c->pos[c->cur], c->vel[c->cur], axis,
-                                 nbins, out));
+  HIP_TRY(c, dpd::launch_profile(c->stream, p.G, p.nf, c->pos[c->cur] + p.fo,
+                                 c->vel[c->cur] + p.fo, axis, nbins, out));
   return DPD_OK;
+}
+
+int dpd_profile(dpd_ctx *c, int32_t axis, int32_t nbins, double *out) {
+  return dpd_replica_profile(c, 0, axis, nbins, out);
 }
 
 int dpd_counters(dpd_ctx *c, int64_t *out) {
@@ -692,19 +997,23 @@ int dpd_counters(dpd_ctx *c, int64_t *out) {
   Status st;
   int rc = read_status(c, st);
   if (rc) return rc;
+  int64_t flagged = 0;
+  for (auto &p : c->rep) flagged += p.flagged_cubes;
   out[0] = c->steps;
   out[1] = (int64_t)c->k;
   out[2] = (int64_t)st.bounce;
   out[3] = (int64_t)st.fallback;
-  out[4] = c->nf;
-  out[5] = c->nw;
-  out[6] = c->ncell;
-  out[7] = c->flagged_cubes;
+  out[4] = c->NF;
+  out[5] = c->NW;
+  out[6] = c->NCELL;
+  out[7] = flagged;
   out[9] = (int64_t)st.unstable;
   // fluid particles now in flagged cubes (those that interpolate phi)
   HIP_TRY(c, dpd::launch_fill_zero(c->stream, &c->status->lookups, 8));
-  HIP_TRY(c, dpd::launch_count_flagged(c->stream, c->G, c->grid_f64, c->nf, c->pos[c->cur],
-                                       c->bits, &c->status->lookups));
+  for (auto &p : c->rep)
+    HIP_TRY(c, dpd::launch_count_flagged(c->stream, p.G, c->grid_f64, p.nf,
+                                         c->pos[c->cur] + p.fo, c->bits + p.bo,
+                                         &c->status->lookups));
   rc = read_status(c, st);
   if (rc) return rc;
   out[8] = (int64_t)st.lookups;
@@ -726,6 +1035,80 @@ int dpd_kernel_times(dpd_ctx *c, int32_t enable, double *out_ms, int64_t *out_la
     }
   }
   c->timing = enable != 0;
+  return DPD_OK;
+}
+
+int dpd_autotune(dpd_ctx *c, int32_t steps, int32_t *shape_out, double *ms_out) {
+  if (!c) return DPD_E_INVAL;
+  if (steps < 1) return fail(c, DPD_E_INVAL, "autotune needs at least one step per trial");
+  const int shapes[4][2] = {{2, 256}, {1, 256}, {2, 128}, {1, 128}};
+  const std::string sig = tune_signature(c);
+  const char *cache = std::getenv("DPD_TUNE_CACHE");
+  int best = -1;
+  double times[4] = {-1, -1, -1, -1};
+  if (cache) {
+    std::ifstream in(cache);
+    std::string s;
+    int ppt, blk;
+    while (in >> s >> ppt >> blk) {
+      if (s != sig) continue;
+      for (int i = 0; i < 4; ++i)
+        if (shapes[i][0] == ppt && shapes[i][1] == blk) best = i;
+    }
+  }
+  if (best < 0) {
+    // trials start from a saved copy of the state and leave it unchanged
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const int cur0 = c->cur;
+    const uint64_t k0 = c->k;
+    const int64_t steps0 = c->steps;
+    const size_t np = 16 * (size_t)(c->NF + c->NW + 1), nv = 16 * (size_t)c->NF;
+    char *save = (char *)dalloc(c, np + 2 * nv + sizeof(Status));
+    if (!save) return fail(c, DPD_E_NOMEM, "autotune snapshot allocation failed");
+    HIP_TRY(c, hipMemcpyAsync(save, c->pos[cur0], np, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(save + np, c->vel[cur0], nv, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(save + np + nv, c->frc[cur0], nv, hipMemcpyDeviceToDevice,
+                              c->stream));
+    HIP_TRY(c, hipMemcpyAsync(save + np + 2 * nv, c->status, sizeof(Status),
+                              hipMemcpyDeviceToDevice, c->stream));
+    const bool timing = c->timing;
+    c->timing = false;
+    int rc = DPD_OK;
+    for (int i = 0; i < 4 && !rc; ++i) {
+      rc = set_shapes(c, shapes[i][0], shapes[i][1]);
+      float ms = 0.f;
+      if (!rc) rc = trial(c, steps, &ms);
+      times[i] = ms / steps;
+      // restore the saved state
+      c->cur = cur0;
+      c->k = k0;
+      c->steps = steps0;
+      HIP_TRY(c, hipMemcpyAsync(c->pos[cur0], save, np, hipMemcpyDeviceToDevice, c->stream));
+      HIP_TRY(c, hipMemcpyAsync(c->vel[cur0], save + np, nv, hipMemcpyDeviceToDevice, c->stream));
+      HIP_TRY(c, hipMemcpyAsync(c->frc[cur0], save + np + nv, nv, hipMemcpyDeviceToDevice,
+                                c->stream));
+      HIP_TRY(c, hipMemcpyAsync(c->status, save + np + 2 * nv, sizeof(Status),
+                                hipMemcpyDeviceToDevice, c->stream));
+      HIP_TRY(c, hipMemcpyAsync(c->dk, &c->k, 8, hipMemcpyHostToDevice, c->stream));
+      if (!rc && (best < 0 || times[i] < times[best])) best = i;
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    dfree(c, save);
+    c->timing = timing;
+    if (rc) return rc;
+    if (cache) {
+      std::ofstream o(cache, std::ios::app);
+      o << sig << " " << shapes[best][0] << " " << shapes[best][1] << "\n";
+    }
+  }
+  int rc = set_shapes(c, shapes[best][0], shapes[best][1]);
+  if (rc) return rc;
+  if (shape_out) {
+    shape_out[0] = c->ppt;
+    shape_out[1] = c->fblock;
+  }
+  if (ms_out)
+    for (int i = 0; i < 4; ++i) ms_out[i] = times[i];
   return DPD_OK;
 }
 

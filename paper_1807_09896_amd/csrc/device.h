@@ -38,6 +38,26 @@ struct KParams {
   uint32_t replica;
 };
 
+// One box of a batch: its geometry and parameters, and where its slices lie
+// in the concatenated arrays (a single box is a batch of one).
+struct Box {
+  KGeom G;
+  KParams P;
+  int64_t fo, nf;     // fluid slots [fo, fo + nf)
+  int64_t wo, nw;     // walls at position index NF + [wo, wo + nw)
+  int64_t co, ncell;  // global cells [co, co + ncell)
+  int64_t go;         // first element of the box's phi grid
+  int64_t bo;         // first word of the box's cube mask
+};
+
+// A run of consecutive particles of one box, the work of one block.
+struct Tile {
+  int32_t box;
+  int32_t first;
+  int32_t count;
+  int32_t pad;
+};
+
 // Device status counters, read back by the host at sync points.
 struct Status {
   unsigned long long bounce;     // bounce-backs by Eq. 17 (code 1)

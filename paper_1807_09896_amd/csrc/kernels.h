@@ -22,8 +22,8 @@ hipError_t launch_pack(hipStream_t s, int64_t n, const float *pos, const float *
 
 // Cell of each position (float4 x,y,z) and its rank within the cell by an
 // atomic counter: counting-sort pass 1.
-hipError_t launch_bin(hipStream_t s, const KGeom &G, int64_t n, const float4 *pos4,
-                      int32_t *cell_of, int32_t *rank_of, int32_t *count);
+hipError_t launch_bin(hipStream_t s, const KGeom &G, int64_t cell_off, int64_t n,
+                      const float4 *pos4, int32_t *cell_of, int32_t *rank_of, int32_t *count);
 
 // Exclusive scan of count[0..ncell) into start[0..ncell] (start[ncell] =
 // total), count reset to 0, in three launches: per-block sums, a scan of
@@ -49,8 +49,8 @@ hipError_t launch_fill_walls(hipStream_t s, int64_t nw, int64_t nf, const int32_
 hipError_t launch_set_pad(hipStream_t s, float4 *pos4, float4 *vt4);
 
 // Cell index of each position.
-hipError_t launch_cells(hipStream_t s, const KGeom &G, int64_t n, const float4 *pos4,
-                        int32_t *cell);
+hipError_t launch_cells(hipStream_t s, const KGeom &G, int64_t cell_off, int64_t n,
+                        const float4 *pos4, int32_t *cell);
 
 // out[s] = in[idx[s]] for up to three float4 arrays (NULL skipped).
 hipError_t launch_permute(hipStream_t s, int64_t n, const int32_t *idx, const float4 *a_in,
@@ -75,28 +75,35 @@ hipError_t launch_check_grid(hipStream_t s, const void *grid, int grid_f64, int6
 hipError_t launch_check_phi(hipStream_t s, const KGeom &G, const void *grid, int grid_f64,
                             int64_t n, const float4 *pos4, Status *st);
 
-// Fused drift + predicted velocity + phi test + bounce-back + binning.
-hipError_t launch_integrate(hipStream_t s, const KGeom &G, const KParams &P, int64_t nf,
-                            float4 *pos4, const float4 *vel4, const float4 *frc4, float4 *vt4,
-                            int32_t *cell_of, int32_t *rank_of, int32_t *count,
+// Fused drift + predicted velocity + phi test + bounce-back + binning, over
+// tiles of up to ppt x 256 particles (ppt 1 or 2); grid is the base of the
+// concatenated phi grids, bits of the concatenated cube masks.
+hipError_t launch_integrate(hipStream_t s, int ppt, const Box *boxes, const Tile *tiles,
+                            int ntiles, float4 *pos4, const float4 *vel4, const float4 *frc4,
+                            float4 *vt4, int32_t *cell_of, int32_t *rank_of, int32_t *count,
                             const uint32_t *bits, int use_mask, const void *grid, int grid_f64,
                             Status *st);
 
-// Pair forces (Eq. 3-10) + body force + velocity update, writing the state
-// in cell-sorted slot order.  init = 1: forces only (velocities unchanged).
-// pos4 and vt4 hold nf fluid entries, the nw walls and one pad entry.
-hipError_t launch_force(hipStream_t s, const KGeom &G, const KParams &P, int64_t nf, int64_t nw,
-                        int init,
-                        const float4 *pos4, const float4 *vt4, const float4 *vel4,
-                        const float4 *frc4, const int32_t *idx, const int32_t *idx_all,
-                        const int32_t *start_all, float4 *pos_out, float4 *vel_out,
-                        float4 *frc_out, uint64_t k, Status *st);
+// Pair forces (Eq. 3-10) + body force + velocity update over tiles of up to
+// `block` (128 or 256) fluid slots, writing the state in cell-sorted slot
+// order.  pos4 and vt4 hold NF fluid entries, the walls and the pad entry
+// (index pad).  init = 1: forces only (velocities unchanged).
+hipError_t launch_force(hipStream_t s, int block, const Box *boxes, const Tile *tiles,
+                        int ntiles, int64_t NF, int32_t pad, int init, const float4 *pos4,
+                        const float4 *vt4, const float4 *vel4, const float4 *frc4,
+                        const int32_t *idx, const int32_t *idx_all, const int32_t *start_all,
+                        float4 *pos_out, float4 *vel_out, float4 *frc_out,
+                        const unsigned long long *dk, Status *st);
 
-// Interacting pairs (gid_i, gid_j) from each fluid particle.
-hipError_t launch_pairs(hipStream_t s, const KGeom &G, const KParams &P, int64_t nf,
-                        const float4 *pos4, const int32_t *idx, const int32_t *idx_all,
-                        const int32_t *start_all, uint32_t *pairs, int64_t cap,
-                        unsigned long long *counter);
+// *dk += 1 (the force evaluation index, on the device).
+hipError_t launch_bump_k(hipStream_t s, unsigned long long *dk);
+
+// Interacting pairs (gid_i, gid_j) from each fluid particle of one box
+// (slots [first, first + nf), cells from cell_off).
+hipError_t launch_pairs(hipStream_t s, const KGeom &G, const KParams &P, int64_t cell_off,
+                        int64_t first, int64_t nf, const float4 *pos4, const int32_t *idx,
+                        const int32_t *idx_all, const int32_t *start_all, uint32_t *pairs,
+                        int64_t cap, unsigned long long *counter);
 
 // Random numbers of given pairs: Philox words (n x 4) and xi (n), either NULL.
 hipError_t launch_pair_random(hipStream_t s, uint64_t seed, uint64_t k, uint32_t replica,

@@ -67,14 +67,14 @@ __global__ void k_copy1(uint8_t *__restrict__ dst, const uint8_t *__restrict__ s
 // ---------------------------------------------------------------------------
 // Counting sort into cells
 // ---------------------------------------------------------------------------
-__global__ void k_bin(const KGeom G, int64_t n, const float4 *__restrict__ pos4,
+__global__ void k_bin(const KGeom G, int64_t cell_off, int64_t n, const float4 *__restrict__ pos4,
                       int32_t *__restrict__ cell_of, int32_t *__restrict__ rank_of,
                       int32_t *__restrict__ count) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   const float4 x = pos4[p];
   int cx, cy, cz;
-  const int c = cell_index(G, x.x, x.y, x.z, cx, cy, cz);
+  const int c = (int)cell_off + cell_index(G, x.x, x.y, x.z, cx, cy, cz);
   cell_of[p] = c;
   rank_of[p] = atomicAdd(&count[c], 1);
 }
@@ -228,6 +228,9 @@ __global__ void k_fill_walls(int64_t nw, int64_t nf, const int32_t *__restrict__
   idx_all[start_all[c] + ((int)w - wstart[c])] = (int32_t)(nf + w);
 }
 
+// k += 1: the force evaluation index of the next force pass.
+__global__ void k_bump(unsigned long long *dk) { *dk += 1ull; }
+
 // The pad entry after fluid and walls: a position far outside the box, so
 // that a batch past the end of a run never tests as a neighbour.
 __global__ void k_set_pad(float4 *pos4, float4 *vt4) {
@@ -235,13 +238,13 @@ __global__ void k_set_pad(float4 *pos4, float4 *vt4) {
   if (vt4) *vt4 = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
-__global__ void k_cells(const KGeom G, int64_t n, const float4 *__restrict__ pos4,
-                        int32_t *__restrict__ cell) {
+__global__ void k_cells(const KGeom G, int64_t cell_off, int64_t n,
+                        const float4 *__restrict__ pos4, int32_t *__restrict__ cell) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   const float4 x = pos4[p];
   int cx, cy, cz;
-  cell[p] = cell_index(G, x.x, x.y, x.z, cx, cy, cz);
+  cell[p] = (int)cell_off + cell_index(G, x.x, x.y, x.z, cx, cy, cz);
 }
 
 __global__ void k_permute(int64_t n, const int32_t *__restrict__ idx, const float4 *a_in,
@@ -420,49 +423,64 @@ __device__ __forceinline__ int wave_rank(const RunInfo &r, int base) {
   return __shfl(base, h, 64) + (lane - h);
 }
 
-template <typename T>
+// One block per tile of up to PPT x kBlock particles of one box; each thread
+// advances PPT particles.
+template <typename T, int PPT>
 __global__ __launch_bounds__(kBlock) void k_integrate(
-    const KGeom G, const KParams P, int64_t nf, float4 *__restrict__ pos4,
-    const float4 *__restrict__ vel4, const float4 *__restrict__ frc4, float4 *__restrict__ vt4,
-    int32_t *__restrict__ cell_of, int32_t *__restrict__ rank_of, int32_t *__restrict__ count,
-    const uint32_t *__restrict__ bits, int use_mask, const T *__restrict__ grid, Status *st) {
-  const int64_t p0 = (int64_t)xcd_block() * (2 * kBlock) + threadIdx.x;
-  const int64_t p1 = p0 + kBlock;
-  const bool a0 = p0 < nf, a1 = p1 < nf;
-  float4 x0 = make_float4(0.f, 0.f, 0.f, 0.f), v0 = x0, f0 = x0, x1 = x0, v1 = x0, f1 = x0;
-  if (a0) {
-    x0 = pos4[p0];
-    v0 = vel4[p0];
-    f0 = frc4[p0];
+    const Box *__restrict__ boxes, const Tile *__restrict__ tiles, int ntiles,
+    float4 *__restrict__ pos4, const float4 *__restrict__ vel4, const float4 *__restrict__ frc4,
+    float4 *__restrict__ vt4, int32_t *__restrict__ cell_of, int32_t *__restrict__ rank_of,
+    int32_t *__restrict__ count, const uint32_t *__restrict__ bits_base, int use_mask,
+    const T *__restrict__ grid_base, Status *st) {
+  const int tid = xcd_block();
+  if (tid >= ntiles) return;
+  const Tile tile = tiles[tid];
+  const Box &B = boxes[tile.box];
+  const KGeom G = B.G;
+  const KParams P = B.P;
+  const T *grid = grid_base + B.go;
+  const uint32_t *bits = bits_base + B.bo;
+  const int co = (int)B.co;
+  int64_t p[PPT];
+  bool a[PPT];
+  float4 x[PPT], v[PPT], f[PPT];
+#pragma unroll
+  for (int u = 0; u < PPT; ++u) {
+    const int local = u * kBlock + (int)threadIdx.x;
+    a[u] = local < tile.count;
+    p[u] = (int64_t)tile.first + local;
+    x[u] = v[u] = f[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (a[u]) {
+      x[u] = pos4[p[u]];
+      v[u] = vel4[p[u]];
+      f[u] = frc4[p[u]];
+    }
   }
-  if (a1) {
-    x1 = pos4[p1];
-    v1 = vel4[p1];
-    f1 = frc4[p1];
+  Moved m[PPT];
+  RunInfo r[PPT];
+  int b[PPT];
+#pragma unroll
+  for (int u = 0; u < PPT; ++u) {
+    m[u].cell = -1;
+    if (a[u]) {
+      m[u] = integrate_one<T>(G, P, x[u], v[u], f[u], bits, use_mask, grid, st);
+      m[u].cell += co;
+    }
+    r[u] = wave_runs(m[u].cell);
+    b[u] = 0;
   }
-  Moved m0, m1;
-  m0.cell = -1;
-  m1.cell = -1;
-  if (a0) m0 = integrate_one<T>(G, P, x0, v0, f0, bits, use_mask, grid, st);
-  if (a1) m1 = integrate_one<T>(G, P, x1, v1, f1, bits, use_mask, grid, st);
-  const RunInfo r0 = wave_runs(m0.cell);
-  const RunInfo r1 = wave_runs(m1.cell);
-  int b0 = 0, b1 = 0;
-  if (r0.head && m0.cell >= 0) b0 = atomicAdd(&count[m0.cell], r0.len);
-  if (r1.head && m1.cell >= 0) b1 = atomicAdd(&count[m1.cell], r1.len);
-  const int k0 = wave_rank(r0, b0);
-  const int k1 = wave_rank(r1, b1);
-  if (a0) {
-    pos4[p0] = m0.pos;
-    vt4[p0] = m0.vt;
-    cell_of[p0] = m0.cell;
-    rank_of[p0] = k0;
-  }
-  if (a1) {
-    pos4[p1] = m1.pos;
-    vt4[p1] = m1.vt;
-    cell_of[p1] = m1.cell;
-    rank_of[p1] = k1;
+#pragma unroll
+  for (int u = 0; u < PPT; ++u)
+    if (r[u].head && m[u].cell >= 0) b[u] = atomicAdd(&count[m[u].cell], r[u].len);
+#pragma unroll
+  for (int u = 0; u < PPT; ++u) {
+    const int k = wave_rank(r[u], b[u]);
+    if (a[u]) {
+      pos4[p[u]] = m[u].pos;
+      vt4[p[u]] = m[u].vt;
+      cell_of[p[u]] = m[u].cell;
+      rank_of[p[u]] = k;
+    }
   }
 }
 
@@ -503,7 +521,6 @@ __global__ __launch_bounds__(kBlock) void k_count_flagged(const KGeom G, int64_t
 // every candidate.  Sums run in candidate order, so runs are deterministic.
 // If a list fills, phases A and B alternate until the scan is done.
 // ---------------------------------------------------------------------------
-constexpr int kForceBlock = 256;
 constexpr int kListCap = 24;
 constexpr int kBatch = 4;
 
@@ -563,17 +580,30 @@ __device__ __forceinline__ NCell neighbour_cell(const KGeom &G, int cx, int cy, 
   return n;
 }
 
-template <bool INIT>
-__global__ __launch_bounds__(kForceBlock) void k_force(
-    const KGeom G, const KParams P, int64_t nf, const float4 *__restrict__ pos4,
-    const float4 *__restrict__ vt4, const float4 *__restrict__ vel4,
-    const float4 *__restrict__ frc4, const int32_t *__restrict__ idx,
-    const int32_t *__restrict__ idx_all, const int32_t *__restrict__ start_all, int32_t pad,
-    float4 *__restrict__ pos_out, float4 *__restrict__ vel_out, float4 *__restrict__ frc_out,
-    uint32_t klo, uint32_t khi, Status *st) {
-  __shared__ uint32_t list[kListCap * kForceBlock];
-  const int64_t s = (int64_t)xcd_block() * kForceBlock + threadIdx.x;
-  if (s >= nf) return;
+template <bool INIT, int BS>
+__global__ __launch_bounds__(BS) void k_force(
+    const Box *__restrict__ boxes, const Tile *__restrict__ tiles, int ntiles, int64_t NF,
+    int32_t pad, const float4 *__restrict__ pos4, const float4 *__restrict__ vt4,
+    const float4 *__restrict__ vel4, const float4 *__restrict__ frc4,
+    const int32_t *__restrict__ idx, const int32_t *__restrict__ idx_all,
+    const int32_t *__restrict__ start_all, float4 *__restrict__ pos_out,
+    float4 *__restrict__ vel_out, float4 *__restrict__ frc_out,
+    const unsigned long long *__restrict__ dk, Status *st) {
+  __shared__ uint32_t list[kListCap * BS];
+  const int tid = xcd_block();
+  if (tid >= ntiles) return;
+  const Tile tile = tiles[tid];
+  if ((int)threadIdx.x >= tile.count) return;
+  const Box &B = boxes[tile.box];
+  const KGeom G = B.G;
+  const KParams P = B.P;
+  const int co = (int)B.co;
+  // force evaluation index k, kept on the device so that a captured step
+  // draws new random numbers on every replay
+  const unsigned long long kk = *dk;
+  const uint32_t klo = (uint32_t)kk;
+  const uint32_t khi = ((uint32_t)(kk >> 32) & 0xFFFFu) | (P.replica << 16);
+  const int64_t s = (int64_t)tile.first + threadIdx.x;
   const int i = idx[s];
   const float4 pi = pos4[i];
   const float4 vti = vt4[i];
@@ -600,8 +630,8 @@ __global__ __launch_bounds__(kForceBlock) void k_force(
         ax = sub_nc(pi.x, nc.sx);
         ay = sub_nc(pi.y, nc.sy);
         az = sub_nc(pi.z, nc.sz);
-        t = start_all[nc.c];
-        t_end = start_all[nc.c + 1];
+        t = start_all[co + nc.c];
+        t_end = start_all[co + nc.c + 1];
         continue;
       }
       int jb[kBatch];
@@ -615,7 +645,7 @@ __global__ __launch_bounds__(kForceBlock) void k_force(
         const float r2 = pair_r2(sub_nc(ax, pb[u].x), sub_nc(ay, pb[u].y), sub_nc(az, pb[u].z));
         // r2 > 0 drops i itself (and coincident particles, whose force is 0)
         if (r2 < P.rc2 && r2 > 0.0f) {
-          mine[cnt * kForceBlock] = (uint32_t)jb[u];
+          mine[cnt * BS] = (uint32_t)jb[u];
           ++cnt;
         }
       }
@@ -623,14 +653,14 @@ __global__ __launch_bounds__(kForceBlock) void k_force(
     }
     // phase B: the listed pairs of this lane
     for (int q = 0; q < cnt; ++q) {
-      const uint32_t j = mine[q * kForceBlock];
+      const uint32_t j = mine[q * BS];
       const float4 pj = pos4[j];
       const float4 vtj = vt4[j];
       const float dx = min_image(pi.x - pj.x, G.L[0]);
       const float dy = min_image(pi.y - pj.y, G.L[1]);
       const float dz = min_image(pi.z - pj.z, G.L[2]);
       const float r2 = dx * dx + dy * dy + dz * dz;
-      const float a = (int64_t)j < nf ? P.a_ff : P.a_fw;
+      const float a = (int64_t)j < NF ? P.a_ff : P.a_fw;
       add_pair(acc, dx, dy, dz, r2, vti.x - vtj.x, vti.y - vtj.y, vti.z - vtj.z, a, P, gi,
                __float_as_uint(pj.w), klo, khi);
     }
@@ -659,8 +689,9 @@ __global__ __launch_bounds__(kForceBlock) void k_force(
 // Interacting pairs with the same decision as the force kernel.  Each thread
 // counts its pairs, a wavefront reserves room with one atomic, then the
 // pairs are written.
-__device__ __forceinline__ int pairs_of(const KGeom &G, const KParams &P, int i, float4 pi,
-                                        int cx, int cy, int cz, const float4 *__restrict__ pos4,
+__device__ __forceinline__ int pairs_of(const KGeom &G, const KParams &P, int co, int i,
+                                        float4 pi, int cx, int cy, int cz,
+                                        const float4 *__restrict__ pos4,
                                         const int32_t *__restrict__ idx_all,
                                         const int32_t *__restrict__ start_all, uint32_t *out,
                                         int64_t base, int64_t cap) {
@@ -669,7 +700,7 @@ __device__ __forceinline__ int pairs_of(const KGeom &G, const KParams &P, int i,
   for (int code = 0; code < 27; ++code) {
     const NCell nc = neighbour_cell(G, cx, cy, cz, code);
     const float ax = sub_nc(pi.x, nc.sx), ay = sub_nc(pi.y, nc.sy), az = sub_nc(pi.z, nc.sz);
-    const int t0 = start_all[nc.c], t1 = start_all[nc.c + 1];
+    const int t0 = start_all[co + nc.c], t1 = start_all[co + nc.c + 1];
     for (int t = t0; t < t1; ++t) {
       const int j = idx_all[t];
       if (j == i) continue;
@@ -687,12 +718,12 @@ __device__ __forceinline__ int pairs_of(const KGeom &G, const KParams &P, int i,
 }
 
 __global__ __launch_bounds__(kBlock) void k_pairs(
-    const KGeom G, const KParams P, int64_t nf, const float4 *__restrict__ pos4,
-    const int32_t *__restrict__ idx, const int32_t *__restrict__ idx_all,
-    const int32_t *__restrict__ start_all, uint32_t *pairs, int64_t cap,
-    unsigned long long *counter) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool act = s < nf;
+    const KGeom G, const KParams P, int co, int64_t first, int64_t nf,
+    const float4 *__restrict__ pos4, const int32_t *__restrict__ idx,
+    const int32_t *__restrict__ idx_all, const int32_t *__restrict__ start_all, uint32_t *pairs,
+    int64_t cap, unsigned long long *counter) {
+  const int64_t s = first + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool act = s < first + nf;
   int i = 0, cx = 0, cy = 0, cz = 0;
   float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
   int n = 0;
@@ -700,7 +731,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(
     i = idx[s];
     pi = pos4[i];
     cell_index(G, pi.x, pi.y, pi.z, cx, cy, cz);
-    n = pairs_of(G, P, i, pi, cx, cy, cz, pos4, idx_all, start_all, nullptr, 0, 0);
+    n = pairs_of(G, P, co, i, pi, cx, cy, cz, pos4, idx_all, start_all, nullptr, 0, 0);
   }
   // wavefront-inclusive prefix of n, one atomic per wavefront
   const int lane = (int)__lane_id();
@@ -714,7 +745,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(
   if (lane == 63 && total > 0) base = atomicAdd(counter, (unsigned long long)total);
   base = __shfl(base, 63, 64);
   if (act && pairs && n > 0)
-    pairs_of(G, P, i, pi, cx, cy, cz, pos4, idx_all, start_all, pairs,
+    pairs_of(G, P, co, i, pi, cx, cy, cz, pos4, idx_all, start_all, pairs,
              (int64_t)base + incl - n, cap);
 }
 
@@ -816,10 +847,10 @@ hipError_t launch_pack(hipStream_t s, int64_t n, const float *pos, const float *
   return hipGetLastError();
 }
 
-hipError_t launch_bin(hipStream_t s, const KGeom &G, int64_t n, const float4 *pos4,
-                      int32_t *cell_of, int32_t *rank_of, int32_t *count) {
+hipError_t launch_bin(hipStream_t s, const KGeom &G, int64_t cell_off, int64_t n,
+                      const float4 *pos4, int32_t *cell_of, int32_t *rank_of, int32_t *count) {
   if (n <= 0) return hipSuccess;
-  k_bin<<<grid_for(n), kBlock, 0, s>>>(G, n, pos4, cell_of, rank_of, count);
+  k_bin<<<grid_for(n), kBlock, 0, s>>>(G, cell_off, n, pos4, cell_of, rank_of, count);
   return hipGetLastError();
 }
 
@@ -861,15 +892,20 @@ hipError_t launch_fill_walls(hipStream_t s, int64_t nw, int64_t nf, const int32_
   return hipGetLastError();
 }
 
+hipError_t launch_bump_k(hipStream_t s, unsigned long long *dk) {
+  k_bump<<<1, 1, 0, s>>>(dk);
+  return hipGetLastError();
+}
+
 hipError_t launch_set_pad(hipStream_t s, float4 *pos4, float4 *vt4) {
   k_set_pad<<<1, 1, 0, s>>>(pos4, vt4);
   return hipGetLastError();
 }
 
-hipError_t launch_cells(hipStream_t s, const KGeom &G, int64_t n, const float4 *pos4,
-                        int32_t *cell) {
+hipError_t launch_cells(hipStream_t s, const KGeom &G, int64_t cell_off, int64_t n,
+                        const float4 *pos4, int32_t *cell) {
   if (n <= 0) return hipSuccess;
-  k_cells<<<grid_for(n), kBlock, 0, s>>>(G, n, pos4, cell);
+  k_cells<<<grid_for(n), kBlock, 0, s>>>(G, cell_off, n, pos4, cell);
   return hipGetLastError();
 }
 
@@ -929,50 +965,52 @@ inline unsigned xcd_grid(int64_t n, int block) {
   return (unsigned)(((nb + 7) / 8) * 8);
 }
 
-hipError_t launch_integrate(hipStream_t s, const KGeom &G, const KParams &P, int64_t nf,
-                            float4 *pos4, const float4 *vel4, const float4 *frc4, float4 *vt4,
-                            int32_t *cell_of, int32_t *rank_of, int32_t *count,
+hipError_t launch_integrate(hipStream_t s, int ppt, const Box *boxes, const Tile *tiles,
+                            int ntiles, float4 *pos4, const float4 *vel4, const float4 *frc4,
+                            float4 *vt4, int32_t *cell_of, int32_t *rank_of, int32_t *count,
                             const uint32_t *bits, int use_mask, const void *grid, int grid_f64,
                             Status *st) {
-  if (nf <= 0) return hipSuccess;
-  const unsigned nb = xcd_grid(nf, 2 * kBlock);
-  if (grid_f64)
-    k_integrate<double><<<nb, kBlock, 0, s>>>(G, P, nf, pos4, vel4, frc4, vt4, cell_of, rank_of,
-                                              count, bits, use_mask, (const double *)grid, st);
-  else
-    k_integrate<float><<<nb, kBlock, 0, s>>>(G, P, nf, pos4, vel4, frc4, vt4, cell_of, rank_of,
-                                             count, bits, use_mask, (const float *)grid, st);
+  if (ntiles <= 0) return hipSuccess;
+  const unsigned nb = (unsigned)(((ntiles + 7) / 8) * 8);
+#define DPD_INTEGRATE(T, K)                                                                     \
+  k_integrate<T, K><<<nb, kBlock, 0, s>>>(boxes, tiles, ntiles, pos4, vel4, frc4, vt4, cell_of, \
+                                          rank_of, count, bits, use_mask, (const T *)grid, st)
+  if (grid_f64) {
+    if (ppt == 1) DPD_INTEGRATE(double, 1); else DPD_INTEGRATE(double, 2);
+  } else {
+    if (ppt == 1) DPD_INTEGRATE(float, 1); else DPD_INTEGRATE(float, 2);
+  }
+#undef DPD_INTEGRATE
   return hipGetLastError();
 }
 
-hipError_t launch_force(hipStream_t s, const KGeom &G, const KParams &P, int64_t nf, int64_t nw,
-                        int init, const float4 *pos4, const float4 *vt4, const float4 *vel4,
-                        const float4 *frc4, const int32_t *idx, const int32_t *idx_all,
-                        const int32_t *start_all, float4 *pos_out, float4 *vel_out,
-                        float4 *frc_out, uint64_t k, Status *st) {
-  const int32_t pad = (int32_t)(nf + nw);
-  if (nf <= 0) return hipSuccess;
-  const uint32_t klo = (uint32_t)k;
-  const uint32_t khi = ((uint32_t)(k >> 32) & 0xFFFFu) | (P.replica << 16);
-  const unsigned nb = xcd_grid(nf, kForceBlock);
-  if (init)
-    k_force<true><<<nb, kForceBlock, 0, s>>>(G, P, nf, pos4, vt4, vel4, frc4, idx, idx_all,
-                                             start_all, pad, pos_out, vel_out, frc_out, klo, khi,
-                                             st);
-  else
-    k_force<false><<<nb, kForceBlock, 0, s>>>(G, P, nf, pos4, vt4, vel4, frc4, idx, idx_all,
-                                              start_all, pad, pos_out, vel_out, frc_out, klo, khi,
-                                              st);
+hipError_t launch_force(hipStream_t s, int block, const Box *boxes, const Tile *tiles,
+                        int ntiles, int64_t NF, int32_t pad, int init, const float4 *pos4,
+                        const float4 *vt4, const float4 *vel4, const float4 *frc4,
+                        const int32_t *idx, const int32_t *idx_all, const int32_t *start_all,
+                        float4 *pos_out, float4 *vel_out, float4 *frc_out,
+                        const unsigned long long *dk, Status *st) {
+  if (ntiles <= 0) return hipSuccess;
+  const unsigned nb = (unsigned)(((ntiles + 7) / 8) * 8);
+#define DPD_FORCE(I, BS)                                                                        \
+  k_force<I, BS><<<nb, BS, 0, s>>>(boxes, tiles, ntiles, NF, pad, pos4, vt4, vel4, frc4, idx,   \
+                                   idx_all, start_all, pos_out, vel_out, frc_out, dk, st)
+  if (block == 128) {
+    if (init) DPD_FORCE(true, 128); else DPD_FORCE(false, 128);
+  } else {
+    if (init) DPD_FORCE(true, 256); else DPD_FORCE(false, 256);
+  }
+#undef DPD_FORCE
   return hipGetLastError();
 }
 
-hipError_t launch_pairs(hipStream_t s, const KGeom &G, const KParams &P, int64_t nf,
-                        const float4 *pos4, const int32_t *idx, const int32_t *idx_all,
-                        const int32_t *start_all, uint32_t *pairs, int64_t cap,
-                        unsigned long long *counter) {
+hipError_t launch_pairs(hipStream_t s, const KGeom &G, const KParams &P, int64_t cell_off,
+                        int64_t first, int64_t nf, const float4 *pos4, const int32_t *idx,
+                        const int32_t *idx_all, const int32_t *start_all, uint32_t *pairs,
+                        int64_t cap, unsigned long long *counter) {
   if (nf <= 0) return hipSuccess;
-  k_pairs<<<grid_for(nf), kBlock, 0, s>>>(G, P, nf, pos4, idx, idx_all, start_all, pairs, cap,
-                                          counter);
+  k_pairs<<<grid_for(nf), kBlock, 0, s>>>(G, P, (int)cell_off, first, nf, pos4, idx, idx_all,
+                                          start_all, pairs, cap, counter);
   return hipGetLastError();
 }
 

@@ -98,7 +98,11 @@ def test_initial_forces_cells_pairs(dpd, oracle_lib, name):
     sim.close()
 
 
-def _one_step_compare(dpd, oracle_lib, s, nsteps_before=0):
+def _one_step_compare(dpd, oracle_lib, s, nsteps_before=0, sim=None, r=0):
+    """One step of the GPU path from a common FP32 snapshot against the
+    oracle.  With `sim` (a batch context holding s as box r) the snapshot is
+    set into box r and the whole batch steps once."""
+    own = sim is None
     o = oracle_lib.Oracle(s)
     if nsteps_before:
         o.step(nsteps_before)
@@ -111,12 +115,13 @@ def _one_step_compare(dpd, oracle_lib, s, nsteps_before=0):
         col[col < 0] += np.float32(s.L[a])
         col[col >= np.float32(s.L[a])] = np.float32(0.0)
     o.set_state(pos32, vel32, f32, o.k)
-    sim = dpd.Simulation(s)
-    sim.set_state(by_gid(o, pos32), by_gid(o, vel32), by_gid(o, f32), o.k)
+    if own:
+        sim = dpd.Simulation(s)
+    sim.set_state(by_gid(o, pos32), by_gid(o, vel32), by_gid(o, f32), o.k, r=r)
     ev_or = o.step(1)
     sim.step(1)
-    st = {k: v.cpu().numpy() for k, v in sim.state().items()}
-    f_gpu = sim.forces().cpu().numpy().astype(np.float64)
+    st = {k: v.cpu().numpy() for k, v in sim.state(r).items()}
+    f_gpu = sim.forces(r).cpu().numpy().astype(np.float64)
     fluid_g = by_gid(o, s.type) == 0
     ev_or_g = by_gid(o, ev_or)
     # events: bounce or not, bit-exact; the code (1 vs 2) outside the band
@@ -153,10 +158,10 @@ def _one_step_compare(dpd, oracle_lib, s, nsteps_before=0):
     if bounced.any():
         # particles that bounced, and their partners, see a reflected
         # position computed in FP32 vs FP64 (Eq. 17): checked at 1e-4
-        bset = set(np.nonzero(bounced)[0].tolist())
-        for a, b in o.pairs():
-            if a in bset or b in bset:
-                near[a] = near[b] = True
+        pr = o.pairs().astype(np.int64)
+        hit = bounced[pr[:, 0]] | bounced[pr[:, 1]]
+        near[pr[hit, 0]] = True
+        near[pr[hit, 1]] = True
         near |= bounced
     strict = fluid_g & ~near
     assert err[strict].max() <= FORCE_TOL * scale, (err[strict].max(), scale)
@@ -166,17 +171,18 @@ def _one_step_compare(dpd, oracle_lib, s, nsteps_before=0):
     assert np.abs(f_gpu - f_or)[fluid_g].max() <= 2e-4 * scale
     # interacting pairs after the step, except pairs of a particle whose
     # bounced position differs from the oracle's by rounding
-    gp = sim.pairs()
+    gp = sim.pairs(r)
     op = o.pairs()
     if not bounced.any():
         assert np.array_equal(sorted_pairs(gp), sorted_pairs(op))
     else:
-        bad = set(np.nonzero(bounced)[0].tolist())
-        keep_g = np.array([a not in bad and b not in bad for a, b in gp])
-        keep_o = np.array([a not in bad and b not in bad for a, b in op])
+        gpi, opi = gp.astype(np.int64), op.astype(np.int64)
+        keep_g = ~(bounced[gpi[:, 0]] | bounced[gpi[:, 1]])
+        keep_o = ~(bounced[opi[:, 0]] | bounced[opi[:, 1]])
         assert np.array_equal(sorted_pairs(gp[keep_g]), sorted_pairs(op[keep_o]))
     n_events = int((ev_or_g > 0).sum())
-    sim.close()
+    if own:
+        sim.close()
     return n_events
 
 

@@ -389,7 +389,7 @@ def porous_system(Lbox=128.0, rho=4.0, h=0.25, width=0.5, corr_len=6.0,
 
 
 def replica_systems(count=256, seed=30, rho=3.0, h=0.25, width=0.5,
-                    edge_range=(8.0, 24.0)):
+                    edge_range=(8.0, 24.0), threads=8):
     """Independent replica boxes of uneven size and geometry.
 
     Edges are drawn per axis uniformly in edge_range and rounded to the grid
@@ -397,10 +397,13 @@ def replica_systems(count=256, seed=30, rho=3.0, h=0.25, width=0.5,
     radius 3-10 (clipped to fit), or a pack of overlapping spheres of radius
     1.5-3 added until the porosity drawn from [0.4, 0.6] is reached.  Each
     replica has its own a in [15, 35], gamma in [3, 6] and g_x in
-    [0.005, 0.03]; walls fill phi < 0.
+    [0.005, 0.03]; walls fill phi < 0.  The per-replica draws come from
+    generator `seed` in replica order; replica r's geometry and particles
+    from generator seed + 1 + r (also its force seed), so replicas are built
+    independently (in `threads` threads).
     """
     rng = np.random.default_rng(seed)
-    out = []
+    specs = []
     for r in range(count):
         L = np.round(rng.uniform(*edge_range, size=3) / h) * h
         kind = int(rng.integers(0, 3))
@@ -409,8 +412,12 @@ def replica_systems(count=256, seed=30, rho=3.0, h=0.25, width=0.5,
         gx = float(rng.uniform(0.005, 0.03))
         p = default_params(a_ff=a, a_fs=a, gamma=gamma, g=(gx, 0, 0),
                            seed=seed + 1 + r, replica=r)
-        out.append(_replica(r, L, kind, rng, rho, h, width, p))
-    return out
+        specs.append((r, L, kind, np.random.default_rng(seed + 1 + r), rho, h, width, p))
+    if threads and threads > 1 and count > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            return list(ex.map(lambda sp: _replica(*sp), specs))
+    return [_replica(*sp) for sp in specs]
 
 
 def _replica(r, L, kind, rng, rho, h, width, params):
@@ -431,15 +438,16 @@ def _replica(r, L, kind, rng, rho, h, width, params):
             return np.hypot(dx, dz) - rad
         meta = dict(kind="cylinder", radius=rad)
     else:
+        # spheres are added until the solid fraction, estimated on 20k
+        # random sample points, reaches 1 - porosity
         target = float(rng.uniform(0.4, 0.6))
+        samp = rng.random((20000, 3)) * L
+        solid = np.zeros(samp.shape[0], dtype=bool)
         centres, radii = [], []
-        Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
-        nodes = np.stack([X, Y, Z], axis=-1)
-        solid = np.zeros(X.shape, dtype=bool)
         while True:
             c = rng.random(3) * L
             rr = float(rng.uniform(1.5, 3.0))
-            dd = np.mod(nodes - c + L / 2, L) - L / 2
+            dd = np.mod(samp - c + L / 2, L) - L / 2
             solid |= (dd * dd).sum(-1) < rr * rr
             centres.append(c)
             radii.append(rr)
@@ -447,14 +455,19 @@ def _replica(r, L, kind, rng, rho, h, width, params):
                 break
         centres_a = np.array(centres)
         radii_a = np.array(radii)
+        from scipy.spatial import cKDTree
+        tree = cKDTree(np.mod(centres_a, L), boxsize=L)
+        kq = min(16, len(centres))
 
-        def dfun(p, C=centres_a, R=radii_a):
-            flat = p.reshape(-1, 3)
-            best = np.full(flat.shape[0], np.inf)
-            for c, rr in zip(C, R):
-                dd = np.mod(flat - c + L / 2, L) - L / 2
-                best = np.minimum(best, np.sqrt((dd * dd).sum(-1)) - rr)
-            return best.reshape(p.shape[:-1])
+        def dfun(p, R=radii_a):
+            # signed distance to the union: min over the kq nearest centres
+            # of |p - c| - r (radii differ by at most 1.5, so a farther
+            # centre only matters beyond the 16th neighbour)
+            flat = np.mod(p.reshape(-1, 3), L)
+            dist, ind = tree.query(flat, k=kq)
+            if kq == 1:
+                dist, ind = dist[:, None], ind[:, None]
+            return (dist - R[ind]).min(axis=1).reshape(p.shape[:-1])
         meta = dict(kind="spheres", porosity_target=target, n_spheres=len(centres))
     Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
     d = dfun(np.stack([X, Y, Z], axis=-1))

@@ -83,6 +83,9 @@ def lib():
         L.orc_potential.restype = C.c_double
         L.orc_profile.argtypes = [P, C.c_int64, P, P, P, C.c_int, C.c_int, P, P, P, P]
         L.orc_num_threads.restype = C.c_int
+        L.orc_window.argtypes = [P, P, C.c_int64, P, P, P, P, C.c_uint64, C.c_int, C.c_int,
+                                 C.c_int, C.c_int, P, P, P, P, P, P, P]
+        L.orc_window.restype = C.c_int
         _lib = L
     return _lib
 
@@ -237,6 +240,47 @@ class Oracle:
                 raise MemoryError("oracle step allocation failed")
             self.k = int(k.value)
         return self.events.copy()
+
+    def set_phi(self, phi):
+        """Replace the phase-field values (same shape); the FP64 copy drives the
+        physics (Eq. 17 and its gradient), the FP32 copy the decisions of an
+        FP32 grid."""
+        phi = np.asarray(phi)
+        assert phi.shape == self.phi64.shape
+        self.phi64 = np.ascontiguousarray(phi, dtype=np.float64)
+        self.geom.phi64 = self.phi64.ctypes.data
+        if self.phi32 is not None:
+            self.phi32 = np.ascontiguousarray(phi, dtype=np.float32)
+            self.geom.phi32 = self.phi32.ctypes.data
+
+    def window(self, T, axis=2, nbins=40, logs=None, k0=None):
+        """Window of T steps from the current (r, v) at force index k0 (default
+        the current k), the carried force refreshed first; the state itself is
+        left unchanged.  Without `logs` every decision is taken and logged; with
+        the logs of an earlier call they are replayed (frozen-event form).
+        Returns dict(profile, sums, counts, logs, r, v): profile[b] =
+        sums[b] / counts[b] is the window mean of v_x in bin b along `axis`."""
+        n, T = self.n, int(T)
+        record = logs is None
+        if record:
+            logs = dict(ev=np.zeros((T, n), np.int32), xs=np.zeros((T, n, 3), np.float32),
+                        bin=np.zeros((T, n), np.int32), T=T, axis=axis, nbins=nbins)
+        else:
+            assert logs["T"] == T and logs["axis"] == axis and logs["nbins"] == nbins
+        sums = np.zeros(nbins, np.float64)
+        counts = np.zeros(nbins, np.float64)
+        r_out = np.zeros((n, 3), np.float64)
+        v_out = np.zeros((n, 3), np.float64)
+        k0 = self.k if k0 is None else int(k0)
+        rc = lib().orc_window(C.byref(self.geom), C.byref(self.cparams), n,
+                              _p(np.ascontiguousarray(self.r)), _p(np.ascontiguousarray(self.v)),
+                              _p(self.type), _p(self.gid), k0, T, int(axis), int(nbins),
+                              int(record), _p(logs["ev"]), _p(logs["xs"]), _p(logs["bin"]),
+                              _p(sums), _p(counts), _p(r_out), _p(v_out))
+        if rc != 0:
+            raise MemoryError("oracle window allocation failed")
+        prof = sums / np.maximum(counts, 1.0)
+        return dict(profile=prof, sums=sums, counts=counts, logs=logs, r=r_out, v=v_out)
 
     def cells(self, xs=None):
         xs = self.xs if xs is None else np.ascontiguousarray(xs, dtype=np.float32)

@@ -290,11 +290,11 @@ double orc_phi64(const orc_geom *G, const double x[3], double grad[3])
  * ---------------------------------------------------------------------- */
 static void pair_force(const orc_params *P, double sigma, double inv_sqrt_dt,
                        const double d[3], const double dv[3], int ti, int tj,
-                       uint32_t gi, uint32_t gj, uint64_t k, double out[3])
+                       uint32_t gi, uint32_t gj, uint64_t k, int noclamp, double out[3])
 {
     double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
     double w = 1.0 - r / P->rc;
-    if (r == 0.0 || w <= 0.0) {
+    if (r == 0.0 || (!noclamp && w <= 0.0)) {
         out[0] = out[1] = out[2] = 0.0;
         return;
     }
@@ -378,10 +378,10 @@ static int cell_shift(int c, int o, int n, int *wrapped)
  * so wall-wall pairs are skipped; with all_particles = 0 only fluid forces
  * are computed (wall rows left zero), with 1 walls get their forces too.
  */
-int orc_forces(const orc_geom *G, const orc_params *P, int64_t n,
-               const double *r, const double *vt, const float *xs,
-               const int32_t *type, const uint32_t *gid, uint64_t k,
-               int mode, int all_particles, double *f)
+static int forces_impl(const orc_geom *G, const orc_params *P, int64_t n,
+                       const double *r, const double *vt, const float *xs,
+                       const int32_t *type, const uint32_t *gid, uint64_t k,
+                       int mode, int all_particles, int noclamp, double *f)
 {
     const double sigma = sqrt(2.0 * P->gamma * P->kBT);
     const double inv_sqrt_dt = 1.0 / sqrt(P->dt);
@@ -420,7 +420,7 @@ int orc_forces(const orc_geom *G, const orc_params *P, int64_t n,
                         dv[a] = vt[3 * i + a] - vt[3 * j + a];
                     }
                     pair_force(P, sigma, inv_sqrt_dt, d, dv, type[i], type[j],
-                               gid[i], gid[j], k, F);
+                               gid[i], gid[j], k, noclamp, F);
                     acc[0] += F[0]; acc[1] += F[1]; acc[2] += F[2];
                 }
             }
@@ -454,7 +454,7 @@ int orc_forces(const orc_geom *G, const orc_params *P, int64_t n,
                 }
                 for (int a = 0; a < 3; ++a) dv[a] = vt[3 * i + a] - vt[3 * j + a];
                 pair_force(P, sigma, inv_sqrt_dt, d, dv, type[i], type[j],
-                           gid[i], gid[j], k, F);
+                           gid[i], gid[j], k, 0, F);
                 acc[0] += F[0]; acc[1] += F[1]; acc[2] += F[2];
             }
         }
@@ -465,6 +465,14 @@ int orc_forces(const orc_geom *G, const orc_params *P, int64_t n,
     }
     if (mode != 0) free_cells(&C);
     return 0;
+}
+
+int orc_forces(const orc_geom *G, const orc_params *P, int64_t n,
+               const double *r, const double *vt, const float *xs,
+               const int32_t *type, const uint32_t *gid, uint64_t k,
+               int mode, int all_particles, double *f)
+{
+    return forces_impl(G, P, n, r, vt, xs, type, gid, k, mode, all_particles, 0, f);
 }
 
 /* Cells of the shadow positions (decision form). */
@@ -702,4 +710,162 @@ int orc_num_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* ------------------------------------------------------------------------
+ * Window of T steps for the gradient checks of the adjoint form.
+ *
+ * The step of orc_step iterated from (r0, v0) at force index k0, with the
+ * carried force refreshed first, f0 = F(r0, v0; k0) + g (pairs decided at
+ * fl32(r0)), and the binned profile of v_x over the states after steps
+ * 1..T: sums[b] = sum over steps t and fluid particles i in bin b after
+ * step t of v_x,i, counts[b] the number of terms.  The bin of a particle is
+ * the FP32 decision b = clamp(floor(fl(x_axis * fl32(nbins / L_axis))),
+ * 0, nbins - 1) on its FP32 decision position.
+ *
+ * record = 1: every discrete decision (bounce-back event and its code, the
+ * pair set of each force evaluation, the bins) is taken as in orc_step and
+ * logged: ev[t n + i], xs_log[3 (t n + i) + a] (the FP32 positions on which
+ * step t's pair set and bins are decided) and bin[t n + i].
+ * record = 0: the same steps with every decision replayed from the logs, so
+ * the profile is a smooth function of a_ij, gamma, g and the phi values
+ * near the events (the frozen-event form whose derivative the adjoint
+ * computes).  The FP64 positions are kept in the periodic image of the
+ * logged decision positions.
+ * Pair forces of a decided pair use w = 1 - r/rc without clamping at rc in
+ * both modes (replay stays differentiable; record mode differs from
+ * orc_step only for pairs within rounding of the cutoff).
+ * r_out, v_out (n x 3, may be NULL) receive the final state.  Returns 0, or
+ * -1 when an allocation fails.
+ * ---------------------------------------------------------------------- */
+static int bin_of32(float x, float scale, int nbins)
+{
+    int b = (int)floorf(x * scale);
+    if (b < 0) b = 0;
+    if (b >= nbins) b = nbins - 1;
+    return b;
+}
+
+int orc_window(const orc_geom *G, const orc_params *P, int64_t n,
+               const double *r0, const double *v0, const int32_t *type,
+               const uint32_t *gid, uint64_t k0, int T, int axis, int nbins,
+               int record, int32_t *ev, float *xs_log, int32_t *bin,
+               double *sums, double *counts, double *r_out, double *v_out)
+{
+    const double dt = P->dt;
+    const double delta = 0x1p-20;
+    const float scale = (float)((double)nbins / G->L[axis]);
+    const size_t n3 = 3 * (size_t)(n > 0 ? n : 1);
+    double *r = malloc(sizeof(double) * n3), *v = malloc(sizeof(double) * n3);
+    double *f = malloc(sizeof(double) * n3), *fn = malloc(sizeof(double) * n3);
+    double *vt = malloc(sizeof(double) * n3), *vold = malloc(sizeof(double) * n3);
+    float *xs = malloc(sizeof(float) * n3);
+    int32_t *code = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int rc = -1;
+    if (!r || !v || !f || !fn || !vt || !vold || !xs || !code) goto out;
+    for (int b = 0; b < nbins; ++b) sums[b] = counts[b] = 0.0;
+    for (int64_t q = 0; q < 3 * n; ++q) {
+        r[q] = r0[q];
+        v[q] = type[q / 3] == 0 ? v0[q] : 0.0;
+        xs[q] = (float)r0[q];
+    }
+    if (forces_impl(G, P, n, r, v, xs, type, gid, k0, 2, 0, 1, f) != 0) goto out;
+
+    for (int t = 0; t < T; ++t) {
+        float *xl = xs_log + 3 * (size_t)t * (size_t)n;
+        for (int64_t i = 0; i < n; ++i) {
+            double *ri = r + 3 * i, *vi = v + 3 * i, *fi = f + 3 * i;
+            for (int a = 0; a < 3; ++a) vold[3 * i + a] = vi[a];
+            code[i] = 0;
+            if (type[i] != 0) {
+                for (int a = 0; a < 3; ++a) {
+                    vt[3 * i + a] = 0.0;
+                    xs[3 * i + a] = (float)ri[a];
+                }
+                continue;
+            }
+            /* drift and prediction (Groot-Warren) */
+            float x32[3], v32[3], f32[3], y32[3];
+            int sh[3];
+            for (int a = 0; a < 3; ++a) {
+                x32[a] = (float)ri[a];
+                v32[a] = (float)vi[a];
+                f32[a] = (float)fi[a];
+            }
+            drift32(G, P, x32, v32, f32, y32, sh);
+            double rs[3], rt[3];
+            for (int a = 0; a < 3; ++a) {
+                rt[a] = ri[a];
+                rs[a] = ri[a] + dt * vi[a] + 0.5 * dt * dt * fi[a] + sh[a] * G->L[a];
+                vt[3 * i + a] = vi[a] + P->lambda * dt * fi[a];
+            }
+            int c = record ? (phi_negative(G, y32) ? 1 : 0) : ev[(size_t)t * n + i];
+            float d32[3] = {y32[0], y32[1], y32[2]};
+            if (c == 0) {
+                for (int a = 0; a < 3; ++a) ri[a] = rs[a];
+            } else {
+                /* bounce-back, Eq. 16-17 */
+                double a1 = -orc_phi64(G, rs, NULL), a0 = orc_phi64(G, rt, NULL);
+                if (a1 < 0.0) a1 = 0.0;
+                if (a1 > 1.0 - delta) a1 = 1.0 - delta;
+                if (a0 < 0.0) a0 = 0.0;
+                if (a0 > 1.0 - delta) a0 = 1.0 - delta;
+                double c1 = atanh(a1), c0 = atanh(a0);
+                double sfrac = c1 > 0.0 ? c1 / (c0 + c1) : 0.0;
+                double rbb[3];
+                for (int a = 0; a < 3; ++a) {
+                    rbb[a] = rs[a] - 2.0 * sfrac * dt * vi[a];
+                    d32[a] = (float)rbb[a];
+                    rbb[a] += wrap32(&d32[a], G->L32[a]) * G->L[a];
+                }
+                if (record) c = phi_negative(G, d32) ? 2 : 1;
+                for (int a = 0; a < 3; ++a) {
+                    ri[a] = c == 2 ? rt[a] : rbb[a];
+                    if (c == 2) d32[a] = (float)rt[a];
+                    vt[3 * i + a] = -vi[a];
+                    vi[a] = -vi[a];
+                }
+            }
+            code[i] = c;
+            for (int a = 0; a < 3; ++a) xs[3 * i + a] = d32[a];
+        }
+        if (record) {
+            for (int64_t i = 0; i < n; ++i) {
+                ev[(size_t)t * n + i] = code[i];
+                for (int a = 0; a < 3; ++a) xl[3 * i + a] = xs[3 * i + a];
+            }
+        } else {
+            /* decisions from the log; positions in the logged image */
+            for (int64_t q = 0; q < 3 * n; ++q) {
+                const int a = (int)(q % 3);
+                xs[q] = xl[q];
+                r[q] -= G->L[a] * nearbyint((r[q] - (double)xl[q]) / G->L[a]);
+            }
+        }
+        if (forces_impl(G, P, n, r, vt, xs, type, gid, k0 + (uint64_t)t + 1, 2, 0, 1, fn) != 0)
+            goto out;
+        for (int64_t i = 0; i < n; ++i) {
+            if (type[i] != 0) continue;
+            for (int a = 0; a < 3; ++a) {
+                if (code[i] == 0)
+                    v[3 * i + a] = vold[3 * i + a] + 0.5 * dt * (f[3 * i + a] + fn[3 * i + a]);
+                f[3 * i + a] = fn[3 * i + a];
+            }
+            int b;
+            if (record) {
+                b = bin_of32(xs[3 * i + axis], scale, nbins);
+                bin[(size_t)t * n + i] = b;
+            } else {
+                b = bin[(size_t)t * n + i];
+            }
+            sums[b] += v[3 * i];
+            counts[b] += 1.0;
+        }
+    }
+    if (r_out) memcpy(r_out, r, sizeof(double) * 3 * (size_t)n);
+    if (v_out) memcpy(v_out, v, sizeof(double) * 3 * (size_t)n);
+    rc = 0;
+out:
+    free(r); free(v); free(f); free(fn); free(vt); free(vold); free(xs); free(code);
+    return rc;
 }

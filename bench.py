@@ -94,6 +94,8 @@ def main():
                     help="steps of the 256-replica batch leg and of its sequential "
                          "comparison (0 skips the leg)")
     ap.add_argument("--replicas", type=int, default=256)
+    ap.add_argument("--adjoint-reps", type=int, default=0,
+                    help="timed repetitions of the 200-step adjoint window (0 skips the leg)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the run, copy this many MiB with the library's plain copy "
                          "kernel (the reference for hardware byte counters)")
@@ -176,6 +178,11 @@ def main():
         sim.close()
         batch = batch_leg(dpd, args.replicas, args.batch_steps)
 
+    adjoint = None
+    if args.adjoint_reps > 0:
+        sim.close()
+        adjoint = adjoint_leg(dpd, args.adjoint_reps)
+
     cpu = None
     if args.cpu_steps > 0:
         import oracle
@@ -217,6 +224,7 @@ def main():
                      "peak_GBs": HBM_PEAK_GBS, "frac": step_gbs / HBM_PEAK_GBS},
         "cpu_baseline": cpu,
         "batch": batch,
+        "adjoint": adjoint,
     }
     print(json.dumps(out), flush=True)
     sim.close()
@@ -274,6 +282,49 @@ def batch_leg(dpd, replicas, steps):
             "speedup_vs_sequential": batched / seq, "shape": list(shape),
             "trial_ms_per_step": trials, "graph": True,
             "kernel_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in kt.items() if v[1]}}
+
+
+def adjoint_leg(dpd, reps, steps=200, ckpt=20, nbins=40):
+    """The differentiation workload: 20^3 slit with sinusoidal walls, a
+    200-step window with a checkpoint every 20 steps, 40 bins along z.
+    Times the recorded forward window and the backward sweep (segment
+    recompute included) of the same window."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_1807_09896_amd import binding
+    from paper_1807_09896_amd.adjoint import Window
+    s = workloads.sinusoid_slit_system()
+    sim = dpd.Simulation(s, graph=True)
+    shape, _ = sim.autotune(5)
+    win = Window(sim, steps=steps, ckpt=ckpt, axis=2, nbins=nbins)
+    prof = win.run()
+    dldp = (2.0 * (prof - 0.5 * prof) / nbins).contiguous()
+    win.backward(dldp)
+    tf, tb = [], []
+    for _ in range(reps):
+        binding.dpd_set_state(sim.ctx, win.pos, win.vel, win.force, win.k0)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        binding.dpd_window_forward(sim.ctx, steps, ckpt, 2, nbins, prof, None)
+        torch.cuda.synchronize()
+        tf.append(time.perf_counter() - ta)
+        ta = time.perf_counter()
+        g = binding.dpd_backward(sim.ctx, dldp, None)
+        torch.cuda.synchronize()
+        tb.append(time.perf_counter() - ta)
+    sim.kernel_times(1)
+    sim.step(20)
+    kt = sim.kernel_times(0)
+    sim.close()
+    f_ms, b_ms = 1e3 * float(np.median(tf)), 1e3 * float(np.median(tb))
+    log("adjoint window: %d particles, forward %.3f ms, backward %.3f ms (%d steps, ckpt %d), "
+        "ratio %.2f" % (s.n, f_ms, b_ms, steps, ckpt, b_ms / f_ms))
+    return {"workload": s.name, "particles": s.n, "fluid": s.n_fluid, "steps": steps,
+            "ckpt": ckpt, "nbins": nbins, "forward_ms": f_ms, "backward_ms": b_ms,
+            "ratio_backward_over_forward": b_ms / f_ms, "shape": list(shape),
+            "grads": [float(x) for x in g],
+            "step_kernel_ms": {k: v[0] / max(v[1], 1) for k, v in kt.items() if v[1]}}
 
 
 def kernel_source_hash():

@@ -256,6 +256,51 @@ int dpd_use_graph(dpd_ctx *ctx, int32_t enable);
  * timed.  Synchronises. */
 int dpd_autotune(dpd_ctx *ctx, int32_t steps, int32_t *shape_out, double *ms_out);
 
+/* Replace the parameters of box r (every field of dpd_params; rc and flags
+ * must keep their create-time values, since rc fixes the cell grid).  The
+ * carried force is not recomputed: the next step uses the new parameters
+ * from its force evaluation on.  Invalidates a recorded window. */
+int dpd_set_params(dpd_ctx *ctx, int32_t r, const dpd_params *params);
+
+/* Replace the phase-field values of box r (same node count and dtype as at
+ * create; host or device memory per on_device) and rebuild the mask of grid
+ * cubes next to the interface.  DPD_E_INVAL, with the old grid kept, when a
+ * value is not finite or a fluid particle would sit at phi < 0.
+ * Invalidates a recorded window. */
+int dpd_set_phi(dpd_ctx *ctx, int32_t r, const void *data, int32_t on_device);
+
+/* ---- Adjoint form (single-box contexts) ----
+ * A window of `steps` steps from the current positions and velocities, with
+ * the carried force first recomputed at them with the current parameters
+ * and force index k0 = k: f0 = F(r0, v0; k0) + g (as at create).  The
+ * observable is the window-mean stream velocity along x per bin of `axis`
+ * (Sec. III.A's velocity profile): profile[b] = (sum over steps t = 1..steps
+ * and fluid particles i in bin b after step t of v_x,i) / N_b, with N_b the
+ * number of such terms and the bin the FP32 decision
+ * clamp(floor(fl(x_axis * fl32(nbins / L_axis))), 0, nbins - 1).
+ * profile (device, nbins float64) and counts (device, nbins int64: N_b) may
+ * be NULL.  A checkpoint of the fluid state is stored every ckpt steps
+ * (1 <= ckpt <= steps, nbins <= 1024); the context ends at the window's last
+ * state.  DPD_E_STATE for a batch context.
+ *
+ * dpd_backward: gradients of a loss L(profile) from dL_dprofile (device,
+ * nbins float64) by the hand-written adjoint of every step of the window
+ * (pair force of Eq. 3-10, the Groot-Warren update and the bounce-back of
+ * Eq. 16-17 with the recorded events held fixed, and the starting force),
+ * recomputing each ckpt-step segment from its checkpoint.  The bins, pair
+ * sets and events are those of the forward window.  grads (host, 6 float64)
+ * receives dL/d{a_ff, a_fw, gamma, g_x, g_y, g_z} (gamma through both the
+ * dissipative amplitude and sigma = sqrt(2 gamma kBT); the sigma path is
+ * omitted where sigma = 0); dL_dphi (device, grid nodes float64 in the
+ * grid's layout, may be NULL) receives dL/d(phi node values), nonzero only
+ * at the nodes of cubes where a bounce-back of code 1 started or ended.
+ * The context's state, k and counters are unchanged.  DPD_E_STATE without a
+ * recorded window or after dpd_set_params / dpd_set_phi / dpd_set_state. */
+int dpd_window_forward(dpd_ctx *ctx, int32_t steps, int32_t ckpt, int32_t axis,
+                       int32_t nbins, double *profile, int64_t *counts);
+int dpd_backward(dpd_ctx *ctx, const double *dL_dprofile, double *grads,
+                 double *dL_dphi);
+
 /* Wait for the context stream and return any latched device error. */
 int dpd_sync(dpd_ctx *ctx);
 

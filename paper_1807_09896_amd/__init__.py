@@ -55,6 +55,8 @@ class Simulation:
             systems = [system]
             self.ctx, self._keep = dpd_create(*_box_args(system, params), stream=stream,
                                               flags=flags)
+        self.flags = flags
+        self._phi_shape = tuple(systems[0].phi.shape)
         self.ns = [int(s.pos.shape[0]) for s in systems]
         self.n = self.ns[0]
         self.replicas = len(systems)
@@ -119,6 +121,14 @@ class Simulation:
 
     def counters(self):
         return dpd_counters(self.ctx)
+
+    def set_params(self, params, r=0):
+        binding.dpd_set_params(self.ctx, r, params, self.flags)
+        if r == 0:
+            self.params = dict(params)
+
+    def set_phi(self, phi, r=0):
+        binding.dpd_set_phi(self.ctx, r, phi)
 
     def kernel_times(self, enable):
         return dpd_kernel_times(self.ctx, enable)

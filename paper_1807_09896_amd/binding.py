@@ -36,7 +36,8 @@ EXPORTED = ["dpd_create", "dpd_step", "dpd_forces", "dpd_get_state", "dpd_set_st
             "dpd_kernel_name", "dpd_sync", "dpd_last_error", "dpd_destroy", "dpd_copy_probe",
             "dpd_pair_random", "dpd_batch_create", "dpd_replica_count", "dpd_replica_forces",
             "dpd_replica_state", "dpd_replica_set_state", "dpd_replica_pairs",
-            "dpd_replica_profile", "dpd_use_graph", "dpd_autotune"]
+            "dpd_replica_profile", "dpd_use_graph", "dpd_autotune", "dpd_set_params",
+            "dpd_set_phi", "dpd_window_forward", "dpd_backward"]
 
 
 class DPDError(RuntimeError):
@@ -135,6 +136,14 @@ def load_library(path: str = LIB_PATH):
     L.dpd_use_graph.restype = C.c_int
     L.dpd_autotune.argtypes = [P, C.c_int32, P, P]
     L.dpd_autotune.restype = C.c_int
+    L.dpd_set_params.argtypes = [P, C.c_int32, P]
+    L.dpd_set_params.restype = C.c_int
+    L.dpd_set_phi.argtypes = [P, C.c_int32, P, C.c_int32]
+    L.dpd_set_phi.restype = C.c_int
+    L.dpd_window_forward.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P]
+    L.dpd_window_forward.restype = C.c_int
+    L.dpd_backward.argtypes = [P, P, P, P]
+    L.dpd_backward.restype = C.c_int
     _lib = L
     return L
 
@@ -212,13 +221,16 @@ def _marshal_box(L, pos, vel, type_, gid, params, phi, h, flags, keep):
     nz, ny, nx = (int(x) for x in phi_a.shape)
     grid = dpd_phi_grid((C.c_int32 * 3)(nx, ny, nz), (C.c_double * 3)(*[float(x) for x in h]),
                         dt, _ptr(phi_a), int(hasattr(phi, "data_ptr")))
+    return box, parts, _params_struct(params, flags), grid
+
+
+def _params_struct(params, flags=0):
     a = params["a"]
-    prm = dpd_params((C.c_double * 4)(a[0][0], a[0][1], a[1][0], a[1][1]), params["gamma"],
-                     params["kBT"], params["rc"], params["dt"], params["lam"],
-                     (C.c_double * 3)(*params["g"]),
-                     int(params["seed"]) & 0xFFFFFFFFFFFFFFFF, int(params["replica"]),
-                     int(flags))
-    return box, parts, prm, grid
+    return dpd_params((C.c_double * 4)(a[0][0], a[0][1], a[1][0], a[1][1]), params["gamma"],
+                      params["kBT"], params["rc"], params["dt"], params["lam"],
+                      (C.c_double * 3)(*params["g"]),
+                      int(params["seed"]) & 0xFFFFFFFFFFFFFFFF, int(params["replica"]),
+                      int(flags))
 
 
 def dpd_create(L, pos, vel, type_, gid, params, phi, h, stream=None, use_torch_allocator=True,
@@ -393,3 +405,28 @@ def dpd_pair_random(seed, k, replica, gi, gj, words=None, xi=None, stream=None):
     _check(load_library().dpd_pair_random(int(seed) & 0xFFFFFFFFFFFFFFFF, int(k), int(replica),
                                           _ptr(gi), _ptr(gj), n, _ptr(words), _ptr(xi),
                                           _stream_handle(stream)))
+
+
+def dpd_set_params(ctx, r, params, flags=0):
+    prm = _params_struct(params, flags)
+    _check(load_library().dpd_set_params(ctx, int(r), C.byref(prm)), ctx)
+
+
+def dpd_set_phi(ctx, r, phi):
+    """phi: device tensor or host array of the create-time shape and dtype."""
+    on_dev = int(hasattr(phi, "data_ptr"))
+    if not on_dev:
+        phi = np.ascontiguousarray(phi)
+    _check(load_library().dpd_set_phi(ctx, int(r), _ptr(phi), on_dev), ctx)
+
+
+def dpd_window_forward(ctx, steps, ckpt, axis, nbins, profile=None, counts=None):
+    _check(load_library().dpd_window_forward(ctx, int(steps), int(ckpt), int(axis), int(nbins),
+                                             _ptr(profile), _ptr(counts)), ctx)
+
+
+def dpd_backward(ctx, dl_dprofile, dl_dphi=None):
+    """Returns dL/d{a_ff, a_fw, gamma, g_x, g_y, g_z} (host float64[6])."""
+    grads = np.zeros(6, np.float64)
+    _check(load_library().dpd_backward(ctx, _ptr(dl_dprofile), _ptr(grads), _ptr(dl_dphi)), ctx)
+    return grads

@@ -18,12 +18,12 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdpdphi.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["kernels.hip", "api.hip"]
+SOURCES = ["kernels.hip", "adjoint.hip", "api.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
     "-ffp-contract=fast-honor-pragmas",
-    # packed FP32 instructions stay off (see DESIGN notes on gfx950)
+    # no packed FP32 instructions (v_pk_*_f32)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
     "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,

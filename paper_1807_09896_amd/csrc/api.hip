@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -49,9 +50,29 @@ struct Replica {
   int64_t fo = 0, wo = 0, co = 0, ncell = 0, go = 0, bo = 0, nwords = 0;
   int nc[3] = {0, 0, 0}, ng[3] = {0, 0, 0};
   double L[3] = {0, 0, 0}, h[3] = {0, 0, 0};
+  double rc = 0;
   KGeom G{};
   KParams P{};
   int64_t flagged_cubes = 0;
+};
+
+// Buffers and bookkeeping of a recorded window (adjoint form).
+struct Window {
+  bool valid = false;
+  int steps = 0, ckpt = 0, nck = 0, axis = 2, nbins = 0;
+  float scale = 0.f;
+  uint64_t k0 = 0, gen = 0;
+  int64_t nf = 0;
+  float4 *ck = nullptr;    // nck checkpoints of 3 x NF (pos, vel, frc)
+  float4 *seg = nullptr;   // ckpt states of one segment, 3 x NF each
+  float4 *save = nullptr;  // the context state during a backward sweep
+  float4 *wpos = nullptr;  // positions of the sweep, NF + NW + 1
+  float4 *adj = nullptr;   // 11 x NF adjoint arrays
+  double *sums = nullptr, *acc = nullptr, *part_f = nullptr, *part_g = nullptr;
+  unsigned long long *counts = nullptr, *dk0 = nullptr;
+  float *lw = nullptr;
+  Status *status_save = nullptr;
+  int cap_nck = 0, cap_ckpt = 0, cap_nbins = 0, cap_f = 0, cap_g = 0;
 };
 
 }  // namespace
@@ -105,6 +126,9 @@ struct dpd_ctx {
   bool use_graph = false;
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
+
+  Window win;
+  uint64_t gen = 0;  // bumped when parameters, phi or the state are replaced
 };
 
 namespace {
@@ -417,6 +441,46 @@ struct HostBox {
   std::vector<int64_t> rows_f, rows_w;
 };
 
+// Kernel parameters of a box from validated dpd_params (cells of R set).
+void make_kparams(const dpd_params &P, const Replica &R, KParams &K) {
+  K.a_ff = (float)P.a[0];
+  K.a_fw = (float)P.a[1];
+  K.gamma = (float)P.gamma;
+  K.sigma_rdt = (float)(std::sqrt(2.0 * P.gamma * P.kBT) / std::sqrt(P.dt));
+  K.rc2 = (float)(P.rc * P.rc);
+  K.inv_rc = (float)(1.0 / P.rc);
+  K.dt = (float)P.dt;
+  K.hdt = (float)(0.5 * P.dt);
+  K.lamdt = (float)(P.lambda * P.dt);
+  for (int a = 0; a < 3; ++a) K.g[a] = (float)P.g[a];
+  double wmin = R.L[0] / R.nc[0];
+  for (int a = 1; a < 3; ++a) wmin = std::fmin(wmin, R.L[a] / R.nc[a]);
+  K.max_disp2 = (float)(0.25 * wmin * wmin);
+  {
+    const double sigma = std::sqrt(2.0 * P.gamma * P.kBT);
+    K.dsig_rdt = sigma > 0.0 ? (float)(P.kBT / (sigma * std::sqrt(P.dt))) : 0.0f;
+  }
+  K.key0 = (uint32_t)P.seed;
+  K.key1 = (uint32_t)(P.seed >> 32);
+  K.replica = P.replica;
+}
+
+// Checks of dpd_params that need no particles.
+std::string check_params(const dpd_params &P) {
+  if (!(std::isfinite(P.rc) && P.rc > 0)) return "rc must be > 0";
+  if (!(std::isfinite(P.dt) && P.dt > 0)) return "dt must be > 0";
+  if (!(std::isfinite(P.gamma) && P.gamma >= 0) || !(std::isfinite(P.kBT) && P.kBT >= 0))
+    return "gamma and kBT must be finite and >= 0";
+  if (!std::isfinite(P.lambda)) return "lambda must be finite";
+  for (int a = 0; a < 4; ++a)
+    if (!std::isfinite(P.a[a])) return "a_ij must be finite";
+  if (P.a[1] != P.a[2]) return "a_ij must be symmetric";
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(P.g[a])) return "g must be finite";
+  if (P.replica >= 65536u) return "replica must be < 65536";
+  return "";
+}
+
 int check_box(int r, const dpd_box *box, const dpd_particles *pp, const dpd_params *prm,
               const dpd_phi_grid *phi, Replica &R, HostBox &H) {
   const std::string pre = "box " + std::to_string(r) + ": ";
@@ -425,17 +489,10 @@ int check_box(int r, const dpd_box *box, const dpd_particles *pp, const dpd_para
   for (int a = 0; a < 3; ++a)
     if (!(std::isfinite(box->L[a]) && box->L[a] > 0))
       return fail(nullptr, DPD_E_INVAL, pre + "box edges must be finite and positive");
-  if (!(std::isfinite(P.rc) && P.rc > 0)) return fail(nullptr, DPD_E_INVAL, pre + "rc must be > 0");
-  if (!(std::isfinite(P.dt) && P.dt > 0)) return fail(nullptr, DPD_E_INVAL, pre + "dt must be > 0");
-  if (!(std::isfinite(P.gamma) && P.gamma >= 0) || !(std::isfinite(P.kBT) && P.kBT >= 0))
-    return fail(nullptr, DPD_E_INVAL, pre + "gamma and kBT must be finite and >= 0");
-  if (!std::isfinite(P.lambda)) return fail(nullptr, DPD_E_INVAL, pre + "lambda must be finite");
-  for (int a = 0; a < 4; ++a)
-    if (!std::isfinite(P.a[a])) return fail(nullptr, DPD_E_INVAL, pre + "a_ij must be finite");
-  if (P.a[1] != P.a[2]) return fail(nullptr, DPD_E_INVAL, pre + "a_ij must be symmetric");
-  for (int a = 0; a < 3; ++a)
-    if (!std::isfinite(P.g[a])) return fail(nullptr, DPD_E_INVAL, pre + "g must be finite");
-  if (P.replica >= 65536u) return fail(nullptr, DPD_E_INVAL, pre + "replica must be < 65536");
+  {
+    const std::string e = check_params(P);
+    if (!e.empty()) return fail(nullptr, DPD_E_INVAL, pre + e);
+  }
   for (int a = 0; a < 3; ++a) {
     R.nc[a] = (int)std::floor(box->L[a] / P.rc);
     if (R.nc[a] < 3)
@@ -511,23 +568,8 @@ int check_box(int r, const dpd_box *box, const dpd_particles *pp, const dpd_para
     R.G.inv_h64[a] = 1.0 / phi->h[a];
     R.G.h[a] = (float)phi->h[a];
   }
-  KParams &K = R.P;
-  K.a_ff = (float)P.a[0];
-  K.a_fw = (float)P.a[1];
-  K.gamma = (float)P.gamma;
-  K.sigma_rdt = (float)(std::sqrt(2.0 * P.gamma * P.kBT) / std::sqrt(P.dt));
-  K.rc2 = (float)(P.rc * P.rc);
-  K.inv_rc = (float)(1.0 / P.rc);
-  K.dt = (float)P.dt;
-  K.hdt = (float)(0.5 * P.dt);
-  K.lamdt = (float)(P.lambda * P.dt);
-  for (int a = 0; a < 3; ++a) K.g[a] = (float)P.g[a];
-  double wmin = box->L[0] / R.nc[0];
-  for (int a = 1; a < 3; ++a) wmin = std::fmin(wmin, box->L[a] / R.nc[a]);
-  K.max_disp2 = (float)(0.25 * wmin * wmin);
-  K.key0 = (uint32_t)P.seed;
-  K.key1 = (uint32_t)(P.seed >> 32);
-  K.replica = P.replica;
+  R.rc = P.rc;
+  make_kparams(P, R, R.P);
   return DPD_OK;
 }
 
@@ -831,6 +873,199 @@ std::string tune_signature(dpd_ctx *c) {
   return s.str();
 }
 
+
+// ---- adjoint form: window forward and backward sweep ----
+
+// Copy the fluid state (pos, vel, frc of the current buffers) to/from a
+// 3 x NF block.
+int save_state(dpd_ctx *c, float4 *dst) {
+  const size_t b = 16 * (size_t)c->NF;
+  if (!b) return DPD_OK;
+  HIP_TRY(c, hipMemcpyAsync(dst, c->pos[c->cur], b, hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(dst + c->NF, c->vel[c->cur], b, hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(dst + 2 * c->NF, c->frc[c->cur], b, hipMemcpyDeviceToDevice,
+                            c->stream));
+  return DPD_OK;
+}
+
+int load_state(dpd_ctx *c, const float4 *src) {
+  const size_t b = 16 * (size_t)c->NF;
+  if (!b) return DPD_OK;
+  HIP_TRY(c, hipMemcpyAsync(c->pos[c->cur], src, b, hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->vel[c->cur], src + c->NF, b, hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->frc[c->cur], src + 2 * c->NF, b, hipMemcpyDeviceToDevice,
+                            c->stream));
+  return DPD_OK;
+}
+
+// Carried force recomputed at the current (r, v) with the current
+// parameters and k: f = F(r, vt = v) + g (as at create).
+int refresh_forces(dpd_ctx *c) {
+  int rc = bin_all(c, c->stream);
+  if (!rc) rc = scan_scatter_sort(c, c->stream);
+  if (rc) return rc;
+  HIP_TRY(c, dpd::launch_vt_from_v(c->stream, c->NF, c->vel[c->cur], c->vt));
+  return force_pass(c, c->stream, 1);
+}
+
+template <typename P>
+int grow(dpd_ctx *c, P **ptr, size_t count, int *cap, int want) {
+  if (*ptr && *cap >= want) return DPD_OK;
+  if (*ptr) dfree(c, *ptr);
+  *ptr = (P *)dalloc(c, sizeof(P) * std::max<size_t>(count, 1));
+  if (!*ptr) return fail(c, DPD_E_NOMEM, "window buffer allocation failed");
+  *cap = want;
+  return DPD_OK;
+}
+
+int window_alloc(dpd_ctx *c, int steps, int ckpt, int nbins) {
+  Window &W = c->win;
+  const size_t nf = (size_t)std::max<int64_t>(c->NF, 1);
+  const int nck = (steps + ckpt - 1) / ckpt;
+  if (W.nf != c->NF) {
+    // sizes depend on NF: start over
+    for (void *q : {(void *)W.ck, (void *)W.seg, (void *)W.save, (void *)W.wpos, (void *)W.adj})
+      if (q) dfree(c, q);
+    W.ck = W.seg = W.save = W.wpos = W.adj = nullptr;
+    W.cap_nck = W.cap_ckpt = 0;
+    W.nf = c->NF;
+  }
+  int dummy = 0;
+  int rc = grow(c, &W.ck, 3 * nf * (size_t)nck, &W.cap_nck, nck);
+  if (!rc) rc = grow(c, &W.seg, 3 * nf * (size_t)ckpt, &W.cap_ckpt, ckpt);
+  if (!rc && !W.save) rc = grow(c, &W.save, 3 * nf, &dummy, 1);
+  if (!rc && !W.wpos) rc = grow(c, &W.wpos, (size_t)(c->NF + c->NW + 1), &dummy, 1);
+  if (!rc && !W.adj) rc = grow(c, &W.adj, 11 * nf, &dummy, 1);
+  if (!rc && W.cap_nbins < nbins) {
+    for (void *q : {(void *)W.sums, (void *)W.counts, (void *)W.lw})
+      if (q) dfree(c, q);
+    W.sums = nullptr;
+    W.counts = nullptr;
+    W.lw = nullptr;
+    W.sums = (double *)dalloc(c, 8 * (size_t)nbins);
+    W.counts = (unsigned long long *)dalloc(c, 8 * (size_t)nbins);
+    W.lw = (float *)dalloc(c, 4 * (size_t)nbins);
+    if (!W.sums || !W.counts || !W.lw) return fail(c, DPD_E_NOMEM, "window buffer allocation failed");
+    W.cap_nbins = nbins;
+  }
+  if (!rc && !W.acc) {
+    W.acc = (double *)dalloc(c, 8 * 8);
+    W.dk0 = (unsigned long long *)dalloc(c, 8);
+    W.status_save = (Status *)dalloc(c, sizeof(Status));
+    if (!W.acc || !W.dk0 || !W.status_save)
+      return fail(c, DPD_E_NOMEM, "window buffer allocation failed");
+  }
+  return rc;
+}
+
+// Recomputed step t of a segment in the backward sweep: from the stored
+// state X_t (3 x NF block x), redo the drift/bounce-back and the cell list
+// of r_{t+1} in the order of X_t, then the three VJP kernels.  A holds the
+// adjoints of X_{t+1} (slot order), B receives those of X_t.
+int backward_step(dpd_ctx *c, const float4 *x, uint64_t t, const float4 *A, float4 *B,
+                  double *dphi) {
+  Window &W = c->win;
+  const int64_t NF = c->NF;
+  hipStream_t s = c->stream;
+  float4 *rn = W.adj + 6 * NF, *vn = W.adj + 7 * NF, *fbar = W.adj + 8 * NF;
+  float4 *rt = W.adj + 9 * NF, *vtb = W.adj + 10 * NF;
+  HIP_TRY(c, hipMemcpyAsync(W.wpos, x, 16 * (size_t)NF, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(c, dpd::launch_integrate(s, c->ppt, c->boxes, c->itiles, c->n_itiles, W.wpos, x + NF,
+                                   x + 2 * NF, c->vt, c->cell_of, c->rank_of, c->count, c->bits,
+                                   c->use_mask, c->grid, c->grid_f64, c->status));
+  int rc = scan_scatter_sort(c, s);
+  if (rc) return rc;
+  HIP_TRY(c, dpd::launch_adj_prep(s, c->boxes, NF, 0, c->idx, W.wpos, c->vt, A, A + NF,
+                                  A + 2 * NF, W.lw, W.axis, W.nbins, W.scale, rn, vn, fbar,
+                                  W.part_g));
+  HIP_TRY(c, dpd::launch_force_vjp(s, c->fblock, c->boxes, c->ftiles, c->n_ftiles, NF,
+                                   (int32_t)(NF + c->NW), W.wpos, c->vt, c->idx, c->idx_all,
+                                   c->start_all, fbar, rn, rt, vtb, W.dk0, t + 1, W.part_f));
+  HIP_TRY(c, dpd::launch_integrate_vjp(s, c->boxes, NF, x, x + NF, x + 2 * NF, c->vt, rt, vtb,
+                                       vn, c->grid, c->grid_f64, dphi, B, B + NF, B + 2 * NF));
+  return DPD_OK;
+}
+
+int backward_impl(dpd_ctx *c, const double *dldp, double *grads, double *dphi) {
+  Window &W = c->win;
+  const int64_t NF = c->NF;
+  hipStream_t s = c->stream;
+  const int nb_f = dpd::force_vjp_blocks(c->n_ftiles), nb_g = dpd::adj_prep_blocks(NF);
+  int rc = grow(c, &W.part_f, 3 * (size_t)std::max(nb_f, 1), &W.cap_f, nb_f);
+  if (!rc) rc = grow(c, &W.part_g, 3 * (size_t)std::max(nb_g, 1), &W.cap_g, nb_g);
+  if (rc) return rc;
+  // keep the context's state; the sweep reuses the step buffers
+  const int cur0 = c->cur;
+  const uint64_t k_save = c->k;
+  const int64_t steps_save = c->steps;
+  rc = save_state(c, W.save);
+  if (rc) return rc;
+  HIP_TRY(c, hipMemcpyAsync(W.status_save, c->status, sizeof(Status), hipMemcpyDeviceToDevice, s));
+  const bool timing = c->timing;
+  c->timing = false;
+
+  float4 *A = W.adj, *B = W.adj + 3 * NF;
+  HIP_TRY(c, dpd::launch_fill_zero(s, A, 48 * (size_t)NF));
+  HIP_TRY(c, dpd::launch_fill_zero(s, W.part_f, 24 * (size_t)nb_f));
+  HIP_TRY(c, dpd::launch_fill_zero(s, W.part_g, 24 * (size_t)nb_g));
+  if (dphi) HIP_TRY(c, dpd::launch_fill_zero(s, dphi, 8 * (size_t)c->NGRID));
+  HIP_TRY(c, dpd::launch_loss_weights(s, W.nbins, dldp, W.counts, W.lw));
+  // walls and the pad of the sweep's position array
+  HIP_TRY(c, hipMemcpyAsync(W.wpos + NF, c->pos[c->cur] + NF, 16 * (size_t)(c->NW + 1),
+                            hipMemcpyDeviceToDevice, s));
+  for (int seg = W.nck - 1; seg >= 0 && !rc; --seg) {
+    const int t0 = seg * W.ckpt, t1 = std::min(W.steps, t0 + W.ckpt);
+    rc = load_state(c, W.ck + (size_t)seg * 3 * NF);
+    if (rc) break;
+    c->k = W.k0 + (uint64_t)t0;
+    HIP_TRY(c, dpd::launch_set_u64(s, c->dk, c->k));
+    // recompute the segment, storing X_t for t0 <= t < t1
+    for (int t = t0; t < t1 && !rc; ++t) {
+      rc = save_state(c, W.seg + (size_t)(t - t0) * 3 * NF);
+      if (!rc) rc = one_step(c);
+    }
+    for (int t = t1 - 1; t >= t0 && !rc; --t) {
+      rc = backward_step(c, W.seg + (size_t)(t - t0) * 3 * NF, (uint64_t)t, A, B, dphi);
+      std::swap(A, B);
+    }
+  }
+  if (!rc) {
+    // the refreshed starting force f0 = F(r0, v0; k0) + g
+    const float4 *x0 = W.ck;
+    float4 *rt = W.adj + 9 * NF, *vtb = W.adj + 10 * NF, *fbar = W.adj + 8 * NF;
+    const Replica &p = c->rep[0];
+    HIP_TRY(c, hipMemcpyAsync(W.wpos, x0, 16 * (size_t)NF, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(c, dpd::launch_vt_from_v(s, NF, x0 + NF, c->vt));
+    HIP_TRY(c, dpd::launch_bin(s, p.G, p.co, NF, W.wpos, c->cell_of, c->rank_of, c->count));
+    rc = scan_scatter_sort(c, s);
+    if (!rc) {
+      HIP_TRY(c, dpd::launch_adj_prep(s, c->boxes, NF, 1, c->idx, W.wpos, c->vt, A, A + NF,
+                                      A + 2 * NF, W.lw, W.axis, W.nbins, W.scale, nullptr,
+                                      nullptr, fbar, W.part_g));
+      HIP_TRY(c, dpd::launch_force_vjp(s, c->fblock, c->boxes, c->ftiles, c->n_ftiles, NF,
+                                       (int32_t)(NF + c->NW), W.wpos, c->vt, c->idx, c->idx_all,
+                                       c->start_all, fbar, nullptr, rt, vtb, W.dk0, 0, W.part_f));
+      HIP_TRY(c, dpd::launch_reduce_partials(s, nb_f, W.part_f, nb_g, W.part_g, W.acc));
+    }
+  }
+  // restore the context
+  c->timing = timing;
+  c->cur = cur0;
+  c->k = k_save;
+  c->steps = steps_save;
+  int r2 = load_state(c, W.save);
+  if (!rc) rc = r2;
+  HIP_TRY(c, hipMemcpyAsync(c->status, W.status_save, sizeof(Status), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(c, dpd::launch_set_u64(s, c->dk, c->k));
+  if (rc) return rc;
+  double acc[6];
+  HIP_TRY(c, hipMemcpyAsync(acc, W.acc, sizeof acc, hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  if (grads)
+    for (int q = 0; q < 6; ++q) grads[q] = acc[q];
+  return latched_error(c);
+}
+
 }  // namespace
 
 extern "C" {
@@ -929,6 +1164,7 @@ int dpd_replica_set_state(dpd_ctx *c, int32_t r, const float *pos, const float *
   HIP_TRY(c, dpd::launch_import(c->stream, p.nf, c->pos[a] + p.fo, c->vel[a] + p.fo,
                                 c->frc[a] + p.fo, dp, dv, df));
   drop_graphs(c);
+  c->gen += 1;
   int rc = resort(c);
   if (rc) return rc;
   c->k = k;
@@ -1110,6 +1346,120 @@ int dpd_autotune(dpd_ctx *c, int32_t steps, int32_t *shape_out, double *ms_out) 
   if (ms_out)
     for (int i = 0; i < 4; ++i) ms_out[i] = times[i];
   return DPD_OK;
+}
+
+int dpd_set_params(dpd_ctx *c, int32_t r, const dpd_params *prm) {
+  if (!c) return DPD_E_INVAL;
+  if (check_replica(c, r)) return DPD_E_INVAL;
+  if (!prm) return fail(c, DPD_E_INVAL, "params is NULL");
+  const std::string e = check_params(*prm);
+  if (!e.empty()) return fail(c, DPD_E_INVAL, e);
+  Replica &p = c->rep[r];
+  if (prm->rc != p.rc) return fail(c, DPD_E_INVAL, "rc fixes the cell grid and cannot change");
+  if ((prm->flags & DPD_FLAG_NO_MASK) != (c->use_mask ? 0 : DPD_FLAG_NO_MASK))
+    return fail(c, DPD_E_INVAL, "flags cannot change");
+  make_kparams(*prm, p, p.P);
+  HIP_TRY(c, hipMemcpyAsync((char *)c->boxes + sizeof(Box) * (size_t)r + offsetof(Box, P), &p.P,
+                            sizeof(KParams), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->gen += 1;
+  return DPD_OK;
+}
+
+int dpd_set_phi(dpd_ctx *c, int32_t r, const void *data, int32_t on_device) {
+  if (!c) return DPD_E_INVAL;
+  if (check_replica(c, r)) return DPD_E_INVAL;
+  if (!data) return fail(c, DPD_E_INVAL, "phi data is NULL");
+  const Replica &p = c->rep[r];
+  const size_t es = c->grid_f64 ? 8 : 4;
+  const int64_t nodes = (int64_t)p.ng[0] * p.ng[1] * p.ng[2];
+  void *stage = dalloc(c, es * (size_t)nodes);
+  if (!stage) return fail(c, DPD_E_NOMEM, "staging allocation failed");
+  HIP_TRY(c, hipMemcpyAsync(stage, data, es * (size_t)nodes,
+                            on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                            c->stream));
+  Status before;
+  int rc = read_status(c, before);
+  if (rc) return rc;
+  HIP_TRY(c, dpd::launch_check_grid(c->stream, stage, c->grid_f64, nodes, c->status));
+  HIP_TRY(c, dpd::launch_check_phi(c->stream, p.G, stage, c->grid_f64, p.nf,
+                                   c->pos[c->cur] + p.fo, c->status));
+  Status after;
+  rc = read_status(c, after);
+  if (rc) return rc;
+  if (after.bad_grid != before.bad_grid || after.bad_phi != before.bad_phi) {
+    HIP_TRY(c, hipMemcpyAsync(c->status, &before, sizeof(Status), hipMemcpyHostToDevice,
+                              c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    dfree(c, stage);
+    return fail(c, DPD_E_INVAL, after.bad_grid != before.bad_grid
+                                    ? "non-finite phi values"
+                                    : "fluid particles would sit at phi < 0");
+  }
+  void *g = (char *)c->grid + (size_t)p.go * es;
+  HIP_TRY(c, hipMemcpyAsync(g, stage, es * (size_t)nodes, hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, dpd::launch_cube_mask(c->stream, p.G, g, c->grid_f64, p.nwords, c->bits + p.bo));
+  std::vector<uint32_t> hb((size_t)p.nwords);
+  HIP_TRY(c, hipMemcpyAsync(hb.data(), c->bits + p.bo, 4 * (size_t)p.nwords,
+                            hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  dfree(c, stage);
+  int64_t m = 0;
+  for (uint32_t w : hb) m += __builtin_popcount(w);
+  c->rep[r].flagged_cubes = m;
+  c->gen += 1;
+  return DPD_OK;
+}
+
+int dpd_window_forward(dpd_ctx *c, int32_t steps, int32_t ckpt, int32_t axis, int32_t nbins,
+                       double *profile, int64_t *counts) {
+  if (!c) return DPD_E_INVAL;
+  if (c->R != 1) return fail(c, DPD_E_STATE, "the adjoint form needs a single-box context");
+  if (steps < 1 || ckpt < 1 || ckpt > steps)
+    return fail(c, DPD_E_INVAL, "need steps >= 1 and 1 <= ckpt <= steps");
+  if (axis < 0 || axis > 2 || nbins < 1 || nbins > dpd::kMaxBins)
+    return fail(c, DPD_E_INVAL, "bad axis or bin count");
+  Window &W = c->win;
+  W.valid = false;
+  int rc = window_alloc(c, steps, ckpt, nbins);
+  if (rc) return rc;
+  W.steps = steps;
+  W.ckpt = ckpt;
+  W.nck = (steps + ckpt - 1) / ckpt;
+  W.axis = axis;
+  W.nbins = nbins;
+  W.scale = (float)((double)nbins / c->rep[0].L[axis]);
+  rc = refresh_forces(c);
+  if (rc) return rc;
+  W.k0 = c->k;
+  HIP_TRY(c, dpd::launch_set_u64(c->stream, W.dk0, W.k0));
+  HIP_TRY(c, dpd::launch_fill_zero(c->stream, W.sums, 8 * (size_t)nbins));
+  HIP_TRY(c, dpd::launch_fill_zero(c->stream, W.counts, 8 * (size_t)nbins));
+  for (int t = 0; t < steps; ++t) {
+    if (t % ckpt == 0) {
+      rc = save_state(c, W.ck + (size_t)(t / ckpt) * 3 * c->NF);
+      if (rc) return rc;
+    }
+    rc = one_step(c);
+    if (rc) return rc;
+    HIP_TRY(c, dpd::launch_obs(c->stream, c->NF, c->pos[c->cur], c->vel[c->cur], axis, nbins,
+                               W.scale, W.sums, W.counts));
+  }
+  HIP_TRY(c, dpd::launch_obs_final(c->stream, nbins, W.sums, W.counts, profile, counts));
+  rc = latched_error(c);
+  if (rc) return rc;
+  W.valid = true;
+  W.gen = c->gen;
+  return DPD_OK;
+}
+
+int dpd_backward(dpd_ctx *c, const double *dL_dprofile, double *grads, double *dL_dphi) {
+  if (!c) return DPD_E_INVAL;
+  if (!c->win.valid) return fail(c, DPD_E_STATE, "backward needs a recorded window");
+  if (c->win.gen != c->gen)
+    return fail(c, DPD_E_STATE, "parameters, phi or state changed since the window was recorded");
+  if (!dL_dprofile) return fail(c, DPD_E_INVAL, "dL_dprofile is NULL");
+  return backward_impl(c, dL_dprofile, grads, dL_dphi);
 }
 
 int dpd_sync(dpd_ctx *c) {

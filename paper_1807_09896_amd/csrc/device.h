@@ -34,6 +34,7 @@ struct KParams {
   float lamdt;          // lambda * dt
   float g[3];           // body force on fluid particles
   float max_disp2;      // (half the smallest cell width)^2
+  float dsig_rdt;       // d(sigma / sqrt(dt)) / d gamma = kBT / (sigma sqrt(dt)), 0 if sigma = 0
   uint32_t key0, key1;  // seed words
   uint32_t replica;
 };
@@ -239,6 +240,35 @@ template <typename T>
 __device__ __forceinline__ T phi_at(const T *__restrict__ grid, const KGeom &G, float x, float y,
                                     float z) {
   return phi_interp(grid, G, grid_locate<T>(G, x, y, z));
+}
+
+// Minimum-image component (|d| < L/2 for every pair within the cutoff).
+__device__ __forceinline__ float min_image(float d, float L) {
+  return d > 0.5f * L ? d - L : (d < -0.5f * L ? d + L : d);
+}
+
+// Neighbour cell `code` (0..26) of (cx, cy, cz): wrapped index and the image
+// shift s L of its particles as seen from the home cell.
+struct NCell {
+  int c;
+  float sx, sy, sz;
+};
+
+__device__ __forceinline__ NCell neighbour_cell(const KGeom &G, int cx, int cy, int cz, int code) {
+  const int ox = code % 3 - 1, oy = (code / 3) % 3 - 1, oz = code / 9 - 1;
+  int qx = cx + ox, qy = cy + oy, qz = cz + oz;
+  NCell n;
+  n.sx = 0.f;
+  n.sy = 0.f;
+  n.sz = 0.f;
+  if (qx < 0) { qx += G.nc[0]; n.sx = -G.L[0]; }
+  else if (qx >= G.nc[0]) { qx -= G.nc[0]; n.sx = G.L[0]; }
+  if (qy < 0) { qy += G.nc[1]; n.sy = -G.L[1]; }
+  else if (qy >= G.nc[1]) { qy -= G.nc[1]; n.sy = G.L[1]; }
+  if (qz < 0) { qz += G.nc[2]; n.sz = -G.L[2]; }
+  else if (qz >= G.nc[2]) { qz -= G.nc[2]; n.sz = G.L[2]; }
+  n.c = (qz * G.nc[1] + qy) * G.nc[0] + qx;
+  return n;
 }
 
 // Map a hardware block index to a logical one so that each of the 8 XCDs

@@ -126,4 +126,42 @@ hipError_t launch_profile(hipStream_t s, const KGeom &G, int64_t nf, const float
 hipError_t launch_fill_zero(hipStream_t s, void *p, size_t bytes);
 hipError_t launch_copy(hipStream_t s, void *dst, const void *src, size_t bytes);
 
+// ---- adjoint form (adjoint.hip) ----
+constexpr int kMaxBins = 1024;
+
+// Window observable of one box: per bin (decision form
+// clamp(floor(fl(x_axis * scale)), 0, nbins - 1)) the sum of v_x and the
+// count, added to sums / counts.
+hipError_t launch_obs(hipStream_t s, int64_t nf, const float4 *pos4, const float4 *vel4,
+                      int axis, int nbins, float scale, double *sums,
+                      unsigned long long *counts);
+hipError_t launch_obs_final(hipStream_t s, int nbins, const double *sums,
+                            const unsigned long long *counts, double *profile,
+                            int64_t *counts_out);
+hipError_t launch_loss_weights(hipStream_t s, int nbins, const double *dldp,
+                               const unsigned long long *counts, float *lw);
+hipError_t launch_vt_from_v(hipStream_t s, int64_t nf, const float4 *vel4, float4 *vt4);
+hipError_t launch_set_u64(hipStream_t s, unsigned long long *p, unsigned long long v);
+
+int adj_prep_blocks(int64_t nf);
+hipError_t launch_adj_prep(hipStream_t s, const Box *boxes, int64_t nf, int initial,
+                           const int32_t *idx, const float4 *pos4, const float4 *vt4,
+                           const float4 *rb_s, const float4 *vb_s, const float4 *fb_s,
+                           const float *lw, int axis, int nbins, float scale, float4 *rn,
+                           float4 *vn, float4 *fbar, double *part_g);
+int force_vjp_blocks(int ntiles);
+hipError_t launch_force_vjp(hipStream_t s, int block, const Box *boxes, const Tile *tiles,
+                            int ntiles, int64_t NF, int32_t pad, const float4 *pos4,
+                            const float4 *vt4, const int32_t *idx, const int32_t *idx_all,
+                            const int32_t *start_all, const float4 *fbar, const float4 *rn,
+                            float4 *rt_out, float4 *vt_out, const unsigned long long *dk0,
+                            unsigned long long koff, double *part);
+hipError_t launch_integrate_vjp(hipStream_t s, const Box *boxes, int64_t nf, const float4 *pos_t,
+                                const float4 *vel_t, const float4 *frc_t, const float4 *vt4,
+                                const float4 *rt, const float4 *vtb, const float4 *vn,
+                                const void *grid, int grid_f64, double *dphi, float4 *rb_out,
+                                float4 *vb_out, float4 *fb_out);
+hipError_t launch_reduce_partials(hipStream_t s, int nb_f, const double *part_f, int nb_g,
+                                  const double *part_g, double *out);
+
 }  // namespace dpd

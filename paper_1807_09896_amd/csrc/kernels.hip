@@ -524,13 +524,6 @@ __global__ __launch_bounds__(kBlock) void k_count_flagged(const KGeom G, int64_t
 constexpr int kListCap = 24;
 constexpr int kBatch = 4;
 
-// Ordering point for LDS traffic between lanes of one wavefront.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 struct Acc {
   float x, y, z;
 };
@@ -549,35 +542,6 @@ __device__ __forceinline__ void add_pair(Acc &acc, float dx, float dy, float dz,
   acc.x += mag * ex;
   acc.y += mag * ey;
   acc.z += mag * ez;
-}
-
-// Minimum-image component (|d| < L/2 for every pair within the cutoff).
-__device__ __forceinline__ float min_image(float d, float L) {
-  return d > 0.5f * L ? d - L : (d < -0.5f * L ? d + L : d);
-}
-
-// Neighbour cell `code` (0..26) of (cx, cy, cz): wrapped index and the image
-// shift s L of its particles as seen from the home cell.
-struct NCell {
-  int c;
-  float sx, sy, sz;
-};
-
-__device__ __forceinline__ NCell neighbour_cell(const KGeom &G, int cx, int cy, int cz, int code) {
-  const int ox = code % 3 - 1, oy = (code / 3) % 3 - 1, oz = code / 9 - 1;
-  int qx = cx + ox, qy = cy + oy, qz = cz + oz;
-  NCell n;
-  n.sx = 0.f;
-  n.sy = 0.f;
-  n.sz = 0.f;
-  if (qx < 0) { qx += G.nc[0]; n.sx = -G.L[0]; }
-  else if (qx >= G.nc[0]) { qx -= G.nc[0]; n.sx = G.L[0]; }
-  if (qy < 0) { qy += G.nc[1]; n.sy = -G.L[1]; }
-  else if (qy >= G.nc[1]) { qy -= G.nc[1]; n.sy = G.L[1]; }
-  if (qz < 0) { qz += G.nc[2]; n.sz = -G.L[2]; }
-  else if (qz >= G.nc[2]) { qz -= G.nc[2]; n.sz = G.L[2]; }
-  n.c = (qz * G.nc[1] + qy) * G.nc[0] + qx;
-  return n;
 }
 
 template <bool INIT, int BS>

@@ -94,7 +94,7 @@ def main():
                     help="steps of the 256-replica batch leg and of its sequential "
                          "comparison (0 skips the leg)")
     ap.add_argument("--replicas", type=int, default=256)
-    ap.add_argument("--adjoint-reps", type=int, default=0,
+    ap.add_argument("--adjoint-reps", type=int, default=3,
                     help="timed repetitions of the 200-step adjoint window (0 skips the leg)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the run, copy this many MiB with the library's plain copy "

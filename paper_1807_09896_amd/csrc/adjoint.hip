@@ -32,7 +32,12 @@ __device__ __forceinline__ int bin_of(float x, float scale, int nbins) {
   return g >= 0.0f ? (g > (float)(nbins - 1) ? nbins - 1 : (int)g) : 0;
 }
 
-__device__ __forceinline__ float axis_of(const float4 &x, int axis) {
+// Coordinate `axis` of a position held in registers.  The argument is a
+// value on purpose: selecting through a reference to global memory lets the
+// compiler turn the choice into a choice of load address, which the gfx950
+// backend lowers incorrectly for the z case (a load through an address
+// register that the z path never writes).
+__device__ __forceinline__ float axis_of(const float4 x, int axis) {
   return axis == 0 ? x.x : (axis == 1 ? x.y : x.z);
 }
 
@@ -86,7 +91,8 @@ __global__ __launch_bounds__(kBlockA) void k_obs(int64_t nf, const float4 *__res
   __syncthreads();
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nf; p += stride) {
-    const int b = bin_of(axis_of(pos4[p], axis), scale, nbins);
+    const float4 x = pos4[p];
+    const int b = bin_of(axis_of(x, axis), scale, nbins);
     atomicAdd(&s_sum[b], (double)vel4[p].x);
     atomicAdd(&s_cnt[b], 1u);
   }
@@ -153,7 +159,8 @@ __global__ __launch_bounds__(kBlockA) void k_adj_prep(
       const int i = idx[s];
       const int ev = __float_as_int(vt4[i].w);
       float4 vb = vb_s[s];
-      vb.x += lw[bin_of(axis_of(pos4[i], axis), scale, nbins)];
+      const float4 xi = pos4[i];
+      vb.x += lw[bin_of(axis_of(xi, axis), scale, nbins)];
       if (ev == 0) {
         F.x += P.hdt * vb.x;
         F.y += P.hdt * vb.y;

@@ -330,7 +330,9 @@ int bin_all(dpd_ctx *c, hipStream_t s) {
   return DPD_OK;
 }
 
-int scan_scatter_sort(dpd_ctx *c, hipStream_t s) {
+// key4: sort each cell by gid (a state loaded from outside) instead of by
+// storage index.
+int scan_scatter_sort(dpd_ctx *c, hipStream_t s, const float4 *key4 = nullptr) {
   HIP_TRY(c, timed(c, s, K_SCAN_REDUCE, [&] {
             return dpd::launch_scan_reduce(s, c->NCELL, c->count, c->bsum);
           }));
@@ -343,7 +345,7 @@ int scan_scatter_sort(dpd_ctx *c, hipStream_t s) {
             return dpd::launch_scatter(s, c->NF, c->cell_of, c->rank_of, c->cstart, c->idx);
           }));
   HIP_TRY(c, timed(c, s, K_SORT, [&] {
-            return dpd::launch_sort_cells(s, c->NCELL, c->cstart, c->idx, c->fluid_off,
+            return dpd::launch_sort_cells(s, c->NCELL, c->cstart, c->idx, key4, c->fluid_off,
                                           c->idx_all);
           }));
   HIP_TRY(c, timed(c, s, K_OTHER, [&] {
@@ -422,9 +424,12 @@ int one_step(dpd_ctx *c) {
 
 // Re-sort the fluid state into cell order after positions changed outside a
 // step (set_state): bin, scan, scatter, sort, permute into the other buffers.
+// Within a cell particles are ordered by gid, so the stored order (and with
+// it every later summation order) depends only on the state, not on how the
+// context stored its particles before.
 int resort(dpd_ctx *c) {
   int rc = bin_all(c, c->stream);
-  if (!rc) rc = scan_scatter_sort(c, c->stream);
+  if (!rc) rc = scan_scatter_sort(c, c->stream, c->pos[c->cur]);
   if (rc) return rc;
   const int a = c->cur, b = 1 - a;
   HIP_TRY(c, dpd::launch_permute(c->stream, c->NF, c->idx, c->pos[a], c->pos[b], c->vel[a],
@@ -746,7 +751,7 @@ int create_impl(int32_t nbox, const dpd_box *boxes, const dpd_particles *parts,
       // into the tail of both position buffers, with zero predicted velocity
       chk(dpd::launch_scatter(c->stream, NW, c->cell_of, c->rank_of, c->wcstart, c->idx),
           "scatter walls");
-      chk(dpd::launch_sort_cells(c->stream, NCELL, c->wcstart, c->idx, nullptr, nullptr),
+      chk(dpd::launch_sort_cells(c->stream, NCELL, c->wcstart, c->idx, nullptr, nullptr, nullptr),
           "sort walls");
       chk(dpd::launch_permute(c->stream, NW, c->idx, wtmp, c->pos[0] + nf, nullptr, nullptr,
                               nullptr, nullptr),

@@ -35,11 +35,12 @@ hipError_t launch_scan_down(hipStream_t s, int64_t ncell, int32_t *count, int32_
                             int32_t *fluid_off);
 
 // idx[start[cell_of[p]] + rank_of[p]] = p, then each cell's run sorted by p
-// (and copied to the fluid part of the merged run when idx_all is given).
+// (by the gid bits of key4[p].w when key4 is given), and copied to the fluid
+// part of the merged run when idx_all is given.
 hipError_t launch_scatter(hipStream_t s, int64_t n, const int32_t *cell_of,
                           const int32_t *rank_of, const int32_t *start, int32_t *idx);
 hipError_t launch_sort_cells(hipStream_t s, int64_t ncell, const int32_t *start, int32_t *idx,
-                             const int32_t *fluid_off, int32_t *idx_all);
+                             const float4 *key4, const int32_t *fluid_off, int32_t *idx_all);
 
 // Wall part of the merged per-cell runs (walls stored at index nf + w).
 hipError_t launch_fill_walls(hipStream_t s, int64_t nw, int64_t nf, const int32_t *wcell,

@@ -194,18 +194,23 @@ __global__ void k_scatter(int64_t n, const int32_t *__restrict__ cell_of,
 }
 
 // Atomic ranks arrive in any order: sort each cell's run by storage index so
-// that the cell list, and every sum over it, is deterministic.  With idx_all
-// the sorted run is also written to the fluid part of the merged run.
+// that the cell list, and every sum over it, is deterministic.  With key4 the
+// run is sorted by the gid bits of key4[i].w instead, which makes the order
+// independent of how the particles were stored before (used when a state is
+// loaded from outside).  With idx_all the sorted run is also written to the
+// fluid part of the merged run.
 __global__ void k_sort_cells(int64_t ncell, const int32_t *__restrict__ start,
-                             int32_t *__restrict__ idx, const int32_t *__restrict__ fluid_off,
+                             int32_t *__restrict__ idx, const float4 *__restrict__ key4,
+                             const int32_t *__restrict__ fluid_off,
                              int32_t *__restrict__ idx_all) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncell) return;
   const int a = start[c], b = start[c + 1];
   for (int i = a + 1; i < b; ++i) {
     const int v = idx[i];
+    const uint32_t kv = key4 ? __float_as_uint(key4[v].w) : (uint32_t)v;
     int j = i - 1;
-    while (j >= a && idx[j] > v) {
+    while (j >= a && (key4 ? __float_as_uint(key4[idx[j]].w) : (uint32_t)idx[j]) > kv) {
       idx[j + 1] = idx[j];
       --j;
     }
@@ -844,8 +849,9 @@ hipError_t launch_scatter(hipStream_t s, int64_t n, const int32_t *cell_of,
 }
 
 hipError_t launch_sort_cells(hipStream_t s, int64_t ncell, const int32_t *start, int32_t *idx,
+                             const float4 *key4,
                              const int32_t *fluid_off, int32_t *idx_all) {
-  k_sort_cells<<<grid_for(ncell), kBlock, 0, s>>>(ncell, start, idx, fluid_off, idx_all);
+  k_sort_cells<<<grid_for(ncell), kBlock, 0, s>>>(ncell, start, idx, key4, fluid_off, idx_all);
   return hipGetLastError();
 }
 

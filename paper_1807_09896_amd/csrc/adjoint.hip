@@ -228,24 +228,23 @@ __global__ __launch_bounds__(BS) void k_force_vjp(
     cell_index(G, pi.x, pi.y, pi.z, cx, cy, cz);
     uint32_t *mine = list + threadIdx.x;
     float rbx = 0.f, rby = 0.f, rbz = 0.f, vbx = 0.f, vby = 0.f, vbz = 0.f;
-    int code = 0, t = 0, t_end = 0;
+    NeighbourRows rows;
+    rows.init(cx, cy, cz);
+    int t = 0, t_end = 0;
     float ax = pi.x, ay = pi.y, az = pi.z;
     bool done = false;
     while (!done) {
       int cnt = 0;
       while (cnt <= kListCapA - kBatchA) {
         if (t >= t_end) {
-          if (code == 27) {
+          float sx, sy, sz;
+          if (!rows.next(G, start_all, co, t, t_end, sx, sy, sz)) {
             done = true;
             break;
           }
-          const NCell nc = neighbour_cell(G, cx, cy, cz, code);
-          ++code;
-          ax = sub_nc(pi.x, nc.sx);
-          ay = sub_nc(pi.y, nc.sy);
-          az = sub_nc(pi.z, nc.sz);
-          t = start_all[co + nc.c];
-          t_end = start_all[co + nc.c + 1];
+          ax = sub_nc(pi.x, sx);
+          ay = sub_nc(pi.y, sy);
+          az = sub_nc(pi.z, sz);
           continue;
         }
         int jb[kBatchA];

@@ -271,6 +271,76 @@ __device__ __forceinline__ NCell neighbour_cell(const KGeom &G, int cx, int cy, 
   return n;
 }
 
+// The 27-cell neighbourhood of a home cell (cx, cy, cz) as contiguous ranges
+// of the merged per-cell runs.  Cells x-1, x, x+1 of one (y, z) row are
+// consecutive cell indices, so each of the 9 rows is one range, or two where
+// the row wraps around x.  The ranges come in the order of the 27 cells (x
+// fastest, then y, then z), so candidates are visited in the same order as
+// cell by cell, with the image shift s L of each cell.
+struct NeighbourRows {
+  int cx, cy, cz, oy, oz, pend, base;
+  float sy, sz;
+
+  __device__ __forceinline__ void init(int x, int y, int z) {
+    cx = x;
+    cy = y;
+    cz = z;
+    oy = -1;
+    oz = -1;
+    pend = 0;
+    base = 0;
+    sy = 0.f;
+    sz = 0.f;
+  }
+
+  // Next range [t, t_end) and its shifts; false when the neighbourhood is done.
+  __device__ __forceinline__ bool next(const KGeom &G, const int32_t *__restrict__ start_all,
+                                       int co, int &t, int &t_end, float &sx, float &sy_out,
+                                       float &sz_out) {
+    const int nx = G.nc[0];
+    if (pend) {
+      // second part of a row that wraps: cells 0, 1 (left edge) or cell 0
+      // seen across the right edge
+      t = start_all[co + base];
+      t_end = start_all[co + base + (pend == 1 ? 2 : 1)];
+      sx = pend == 1 ? 0.f : G.L[0];
+      pend = 0;
+    } else {
+      if (oz == 2) return false;
+      int qy = cy + oy, qz = cz + oz;
+      sy = 0.f;
+      sz = 0.f;
+      if (qy < 0) { qy += G.nc[1]; sy = -G.L[1]; }
+      else if (qy >= G.nc[1]) { qy -= G.nc[1]; sy = G.L[1]; }
+      if (qz < 0) { qz += G.nc[2]; sz = -G.L[2]; }
+      else if (qz >= G.nc[2]) { qz -= G.nc[2]; sz = G.L[2]; }
+      base = (qz * G.nc[1] + qy) * nx;
+      if (cx > 0 && cx < nx - 1) {
+        t = start_all[co + base + cx - 1];
+        t_end = start_all[co + base + cx + 2];
+        sx = 0.f;
+      } else if (cx == 0) {
+        t = start_all[co + base + nx - 1];
+        t_end = start_all[co + base + nx];
+        sx = -G.L[0];
+        pend = 1;
+      } else {
+        t = start_all[co + base + nx - 2];
+        t_end = start_all[co + base + nx];
+        sx = 0.f;
+        pend = 2;
+      }
+      if (++oy == 2) {
+        oy = -1;
+        ++oz;
+      }
+    }
+    sy_out = sy;
+    sz_out = sz;
+    return true;
+  }
+};
+
 // Map a hardware block index to a logical one so that each of the 8 XCDs
 // (which receive blocks round-robin) works on one contiguous eighth of the
 // index space and its L2 sees one spatial region.  gridDim.x must be a

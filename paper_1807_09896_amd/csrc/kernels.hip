@@ -199,6 +199,7 @@ __global__ void k_scatter(int64_t n, const int32_t *__restrict__ cell_of,
 // independent of how the particles were stored before (used when a state is
 // loaded from outside).  With idx_all the sorted run is also written to the
 // fluid part of the merged run.
+template <bool BY_GID>
 __global__ void k_sort_cells(int64_t ncell, const int32_t *__restrict__ start,
                              int32_t *__restrict__ idx, const float4 *__restrict__ key4,
                              const int32_t *__restrict__ fluid_off,
@@ -208,9 +209,9 @@ __global__ void k_sort_cells(int64_t ncell, const int32_t *__restrict__ start,
   const int a = start[c], b = start[c + 1];
   for (int i = a + 1; i < b; ++i) {
     const int v = idx[i];
-    const uint32_t kv = key4 ? __float_as_uint(key4[v].w) : (uint32_t)v;
+    const uint32_t kv = BY_GID ? __float_as_uint(key4[v].w) : (uint32_t)v;
     int j = i - 1;
-    while (j >= a && (key4 ? __float_as_uint(key4[idx[j]].w) : (uint32_t)idx[j]) > kv) {
+    while (j >= a && (BY_GID ? __float_as_uint(key4[idx[j]].w) : (uint32_t)idx[j]) > kv) {
       idx[j + 1] = idx[j];
       --j;
     }
@@ -517,8 +518,9 @@ __global__ __launch_bounds__(kBlock) void k_count_flagged(const KGeom G, int64_t
 //
 // One thread per fluid particle i, in cell-sorted slot order; a wavefront is
 // 64 consecutive particles.  Phase A: each lane scans the merged runs (walls
-// then fluid) of its 27 neighbour cells with the FP32 cutoff decision, four
-// run entries at a time so that their loads overlap, and appends the hits to
+// then fluid) of its 27 neighbour cells, as 9 row ranges (the x-neighbours of
+// a row are consecutive cells, see NeighbourRows), with the FP32 cutoff
+// decision, four run entries at a time so that their loads overlap, and appends the hits to
 // its column of an LDS list (slot-major, so the wavefront's appends fall in
 // different banks).  Phase B: the lane evaluates its listed pairs; the
 // random-number and force arithmetic runs only for pairs inside the cutoff,
@@ -581,7 +583,9 @@ __global__ __launch_bounds__(BS) void k_force(
   cell_index(G, pi.x, pi.y, pi.z, cx, cy, cz);
   uint32_t *mine = list + threadIdx.x;
   Acc acc = {0.f, 0.f, 0.f};
-  int code = 0, t = 0, t_end = 0;
+  NeighbourRows rows;
+  rows.init(cx, cy, cz);
+  int t = 0, t_end = 0;
   float ax = pi.x, ay = pi.y, az = pi.z;   // i shifted to the current cell's image
   bool done = false;
   while (!done) {
@@ -590,17 +594,14 @@ __global__ __launch_bounds__(BS) void k_force(
     int cnt = 0;
     while (cnt <= kListCap - kBatch) {
       if (t >= t_end) {
-        if (code == 27) {
+        float sx, sy, sz;
+        if (!rows.next(G, start_all, co, t, t_end, sx, sy, sz)) {
           done = true;
           break;
         }
-        const NCell nc = neighbour_cell(G, cx, cy, cz, code);
-        ++code;
-        ax = sub_nc(pi.x, nc.sx);
-        ay = sub_nc(pi.y, nc.sy);
-        az = sub_nc(pi.z, nc.sz);
-        t = start_all[co + nc.c];
-        t_end = start_all[co + nc.c + 1];
+        ax = sub_nc(pi.x, sx);
+        ay = sub_nc(pi.y, sy);
+        az = sub_nc(pi.z, sz);
         continue;
       }
       int jb[kBatch];
@@ -851,7 +852,11 @@ hipError_t launch_scatter(hipStream_t s, int64_t n, const int32_t *cell_of,
 hipError_t launch_sort_cells(hipStream_t s, int64_t ncell, const int32_t *start, int32_t *idx,
                              const float4 *key4,
                              const int32_t *fluid_off, int32_t *idx_all) {
-  k_sort_cells<<<grid_for(ncell), kBlock, 0, s>>>(ncell, start, idx, key4, fluid_off, idx_all);
+  if (key4)
+    k_sort_cells<true><<<grid_for(ncell), kBlock, 0, s>>>(ncell, start, idx, key4, fluid_off, idx_all);
+  else
+    k_sort_cells<false><<<grid_for(ncell), kBlock, 0, s>>>(ncell, start, idx, key4, fluid_off,
+                                                         idx_all);
   return hipGetLastError();
 }
 

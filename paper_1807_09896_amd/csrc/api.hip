@@ -360,7 +360,8 @@ int force_pass(dpd_ctx *c, hipStream_t s, int init) {
   const int a = c->cur, b = 1 - c->cur;
   HIP_TRY(c, timed(c, s, K_FORCE, [&] {
             return dpd::launch_force(s, c->fblock, c->boxes, c->ftiles, c->n_ftiles, c->NF,
-                                     (int32_t)(c->NF + c->NW), init, c->pos[a], c->vt, c->vel[a],
+                                     (int32_t)(c->NF + c->NW), (int32_t)c->NCELL, init, c->pos[a],
+                                     c->vt, c->vel[a],
                                      c->frc[a], c->idx, c->idx_all, c->start_all, c->pos[b],
                                      c->vel[b], c->frc[b], c->dk, c->status);
           }));
@@ -668,8 +669,8 @@ int create_impl(int32_t nbox, const dpd_box *boxes, const dpd_particles *parts,
   c->bsum = (int32_t *)dalloc(c, 4 * (size_t)c->nscan);
   c->wcstart = (int32_t *)dalloc(c, 4 * (ncell + 1));
   c->wcell = (int32_t *)dalloc(c, 4 * nw);
-  c->idx_all = (int32_t *)dalloc(c, 4 * (nf + nw));
-  c->start_all = (int32_t *)dalloc(c, 4 * (ncell + 1));
+  c->idx_all = (int32_t *)dalloc(c, 4 * (nf + nw + dpd::kIdxSlack));
+  c->start_all = (int32_t *)dalloc(c, 4 * (ncell + 1 + dpd::kStartSlack));
   c->fluid_off = (int32_t *)dalloc(c, 4 * ncell);
   c->grid = dalloc(c, (size_t)NGRID * (size_t)grids[0].dtype);
   c->bits = (uint32_t *)dalloc(c, 4 * (size_t)NWORDS);
@@ -681,7 +682,8 @@ int create_impl(int32_t nbox, const dpd_box *boxes, const dpd_particles *parts,
     if (!c->pos[b] || !c->vel[b] || !c->frc[b])
       return bail(fail(c, DPD_E_NOMEM, "device allocation failed"));
   if (!c->vt || !c->cell_of || !c->rank_of || !c->idx || !c->count || !c->cstart || !c->bsum ||
-      !c->wcstart || !c->wcell || !c->idx_all || !c->start_all || !c->fluid_off || !c->grid ||
+      !c->wcstart || !c->wcell || !c->idx_all || !c->start_all || !c->fluid_off ||
+      !c->grid ||
       !c->bits || !c->boxes || !c->status || !c->dk || !c->pair_counter)
     return bail(fail(c, DPD_E_NOMEM, "device allocation failed"));
 
@@ -766,8 +768,9 @@ int create_impl(int32_t nbox, const dpd_box *boxes, const dpd_particles *parts,
             "wall cells");
       }
     }
-    chk(dpd::launch_set_pad(c->stream, c->pos[0] + nf + nw, c->vt + nf + nw), "pad");
-    chk(dpd::launch_set_pad(c->stream, c->pos[1] + nf + nw, nullptr), "pad");
+    chk(dpd::launch_set_pad(c->stream, c->pos[0] + nf + nw, c->vt + nf + nw, c->idx_all + nf + nw,
+                            (int32_t)(nf + nw)), "pad");
+    chk(dpd::launch_set_pad(c->stream, c->pos[1] + nf + nw, nullptr, nullptr, 0), "pad");
     chk(hipStreamSynchronize(c->stream), "sync");
     dfree(c, wtmp);
     if (rc) return bail(rc);

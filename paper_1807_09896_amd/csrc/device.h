@@ -341,6 +341,47 @@ struct NeighbourRows {
   }
 };
 
+// Buffer-resource loads.  A buffer resource carries the base address, the
+// record stride and the extent; an indexed load takes the record index and
+// the memory unit forms the address, so a gather costs no per-lane 64-bit
+// address arithmetic.  Word 3 is the gfx9 default (32-bit data format).  The
+// extent is the array's true length; every index the kernels form lies
+// inside it (the arrays carry spare entries where a pass reads ahead).
+typedef int v4i32_t __attribute__((ext_vector_type(4)));
+extern "C" __device__ v4i32_t dpd_struct_buffer_load_v4i32(__amdgpu_buffer_rsrc_t rsrc, int vindex,
+                                                           int voffset, int soffset, int aux)
+    __asm("llvm.amdgcn.struct.ptr.buffer.load.v4i32");
+constexpr int kBufferWord3 = 0x00020000;
+
+// An array of 16-byte records (float4) read by index.
+struct Records16 {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ Records16(const float4 *p, int n)
+      : r(__builtin_amdgcn_make_buffer_rsrc((void *)p, (short)16, n, kBufferWord3)) {}
+  __device__ __forceinline__ float4 operator[](int i) const {
+    const v4i32_t v = dpd_struct_buffer_load_v4i32(r, i, 0, 0, 0);
+    return make_float4(__int_as_float(v.x), __int_as_float(v.y), __int_as_float(v.z),
+                       __int_as_float(v.w));
+  }
+};
+
+// An int32 array read four entries at a time from any entry.
+struct Ints4 {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ Ints4(const int32_t *p, int n)
+      : r(__builtin_amdgcn_make_buffer_rsrc((void *)p, (short)0, 4 * n, kBufferWord3)) {}
+  __device__ __forceinline__ void load(int i, int out[4]) const {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, 4 * i, 0, 0);
+    out[0] = (int)v[0];
+    out[1] = (int)v[1];
+    out[2] = (int)v[2];
+    out[3] = (int)v[3];
+  }
+};
+
+// True when the predicate holds on any active lane of the wavefront.
+__device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
+
 // Map a hardware block index to a logical one so that each of the 8 XCDs
 // (which receive blocks round-robin) works on one contiguous eighth of the
 // index space and its L2 sees one spatial region.  gridDim.x must be a

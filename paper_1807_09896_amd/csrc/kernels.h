@@ -13,6 +13,11 @@ namespace dpd {
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanChunk = kScanThreads * kScanItems;
+// Spare entries after the merged cell runs: the pair kernel reads a few run
+// entries past a run's end (and discards them) instead of branching.
+constexpr int kIdxSlack = 8;
+// Spare entries after the run starts: the pair kernel reads them four at a time.
+constexpr int kStartSlack = 4;
 inline int scan_blocks(int64_t n) { return (int)((n + kScanChunk - 1) / kScanChunk); }
 
 // Upload: pack host-order rows of one particle class into float4 arrays.
@@ -46,8 +51,9 @@ hipError_t launch_sort_cells(hipStream_t s, int64_t ncell, const int32_t *start,
 hipError_t launch_fill_walls(hipStream_t s, int64_t nw, int64_t nf, const int32_t *wcell,
                              const int32_t *wstart, const int32_t *start_all, int32_t *idx_all);
 
-// Write the pad entry (far-away position, zero velocity) at pos4[0], vt4[0].
-hipError_t launch_set_pad(hipStream_t s, float4 *pos4, float4 *vt4);
+// Write the pad entry (far-away position, zero velocity) at pos4[0], vt4[0];
+// with slack given, the kIdxSlack spare run entries name it.
+hipError_t launch_set_pad(hipStream_t s, float4 *pos4, float4 *vt4, int32_t *slack, int32_t pad);
 
 // Cell index of each position.
 hipError_t launch_cells(hipStream_t s, const KGeom &G, int64_t cell_off, int64_t n,
@@ -90,9 +96,10 @@ hipError_t launch_integrate(hipStream_t s, int ppt, const Box *boxes, const Tile
 // order.  pos4 and vt4 hold NF fluid entries, the walls and the pad entry
 // (index pad).  init = 1: forces only (velocities unchanged).
 hipError_t launch_force(hipStream_t s, int block, const Box *boxes, const Tile *tiles,
-                        int ntiles, int64_t NF, int32_t pad, int init, const float4 *pos4,
-                        const float4 *vt4, const float4 *vel4, const float4 *frc4,
-                        const int32_t *idx, const int32_t *idx_all, const int32_t *start_all,
+                        int ntiles, int64_t NF, int32_t pad, int32_t ncell_all, int init,
+                        const float4 *pos4, const float4 *vt4, const float4 *vel4,
+                        const float4 *frc4, const int32_t *idx, const int32_t *idx_all,
+                        const int32_t *start_all,
                         float4 *pos_out, float4 *vel_out, float4 *frc_out,
                         const unsigned long long *dk, Status *st);
 

@@ -238,10 +238,13 @@ __global__ void k_fill_walls(int64_t nw, int64_t nf, const int32_t *__restrict__
 __global__ void k_bump(unsigned long long *dk) { *dk += 1ull; }
 
 // The pad entry after fluid and walls: a position far outside the box, so
-// that a batch past the end of a run never tests as a neighbour.
-__global__ void k_set_pad(float4 *pos4, float4 *vt4) {
+// that it never tests as a neighbour; the spare run-array entries after the
+// last run name it.
+__global__ void k_set_pad(float4 *pos4, float4 *vt4, int32_t *slack, int32_t pad) {
   *pos4 = make_float4(1e30f, 1e30f, 1e30f, __uint_as_float(0xFFFFFFFFu));
   if (vt4) *vt4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (slack)
+    for (int u = 0; u < kIdxSlack; ++u) slack[u] = pad;
 }
 
 __global__ void k_cells(const KGeom G, int64_t cell_off, int64_t n,
@@ -517,19 +520,22 @@ __global__ __launch_bounds__(kBlock) void k_count_flagged(const KGeom G, int64_t
 // Pair force (Eq. 3-10), body force, velocity update
 //
 // One thread per fluid particle i, in cell-sorted slot order; a wavefront is
-// 64 consecutive particles.  Phase A: each lane scans the merged runs (walls
-// then fluid) of its 27 neighbour cells, as 9 row ranges (the x-neighbours of
-// a row are consecutive cells, see NeighbourRows), with the FP32 cutoff
-// decision, four run entries at a time so that their loads overlap, and appends the hits to
-// its column of an LDS list (slot-major, so the wavefront's appends fall in
-// different banks).  Phase B: the lane evaluates its listed pairs; the
-// random-number and force arithmetic runs only for pairs inside the cutoff,
-// so the wavefront pays for max(hits) iterations instead of diverging on
-// every candidate.  Sums run in candidate order, so runs are deterministic.
-// If a list fills, phases A and B alternate until the scan is done.
+// 64 consecutive particles.  Phase A: the wavefront visits the 9 rows of the
+// 27-cell neighbourhood together (the x-neighbours of a row are consecutive
+// cells, so a row is one run of merged entries, walls then fluid, or two
+// where it wraps in x) and walks each row in lockstep, four run entries per
+// lane and pass so that their loads overlap, with the FP32 cutoff decision;
+// hits go to the lane's column of an LDS list (slot-major, so the
+// wavefront's appends fall in different banks).  Phase B: each lane
+// evaluates its listed pairs; the random-number and force arithmetic runs
+// only for pairs inside the cutoff.  The wavefront runs phase B when any
+// lane's list could overflow in the next pass, and once at the end.  Lanes
+// never branch apart inside a pass, so the wavefront pays for the longest
+// run of each row, not for every lane's row switches.  Sums run in
+// candidate order, so runs are deterministic.
 // ---------------------------------------------------------------------------
-constexpr int kListCap = 24;
-constexpr int kBatch = 4;
+constexpr int kListCap = 20;
+constexpr int kBatch = 4;   // = the width of one run-array load
 
 struct Acc {
   float x, y, z;
@@ -551,14 +557,16 @@ __device__ __forceinline__ void add_pair(Acc &acc, float dx, float dy, float dz,
   acc.z += mag * ez;
 }
 
+// Eight wavefronts per SIMD (at most 64 VGPRs): the walk waits on dependent
+// loads, and more wavefronts in flight hide more of that wait.
 template <bool INIT, int BS>
-__global__ __launch_bounds__(BS) void k_force(
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_force(
     const Box *__restrict__ boxes, const Tile *__restrict__ tiles, int ntiles, int64_t NF,
-    int32_t pad, const float4 *__restrict__ pos4, const float4 *__restrict__ vt4,
-    const float4 *__restrict__ vel4, const float4 *__restrict__ frc4,
-    const int32_t *__restrict__ idx, const int32_t *__restrict__ idx_all,
-    const int32_t *__restrict__ start_all, float4 *__restrict__ pos_out,
-    float4 *__restrict__ vel_out, float4 *__restrict__ frc_out,
+    int32_t pad, int32_t ncell_all, const float4 *__restrict__ pos4,
+    const float4 *__restrict__ vt4, const float4 *__restrict__ vel4,
+    const float4 *__restrict__ frc4, const int32_t *__restrict__ idx,
+    const int32_t *__restrict__ idx_all, const int32_t *__restrict__ start_all,
+    float4 *__restrict__ pos_out, float4 *__restrict__ vel_out, float4 *__restrict__ frc_out,
     const unsigned long long *__restrict__ dk, Status *st) {
   __shared__ uint32_t list[kListCap * BS];
   const int tid = xcd_block();
@@ -581,51 +589,27 @@ __global__ __launch_bounds__(BS) void k_force(
   const uint32_t gi = __float_as_uint(pi.w);
   int cx, cy, cz;
   cell_index(G, pi.x, pi.y, pi.z, cx, cy, cz);
-  uint32_t *mine = list + threadIdx.x;
+  // pos4 and vt4 hold NF + NW + 1 records (the pad last); the run array
+  // holds NF + NW entries and kIdxSlack spare ones, which read as the pad;
+  // the run starts hold ncell_all + 1 entries and kStartSlack spare ones
+  const Records16 posr(pos4, pad + 1), vtr(vt4, pad + 1);
+  const Ints4 runs(idx_all, pad + kIdxSlack);
+  const Ints4 starts(start_all, ncell_all + 1 + kStartSlack);
+  // this lane's list column as LDS byte offsets: entry q at lane0 + q * BS * 4
+  char *const lds = (char *)list;
+  const uint32_t lane0 = threadIdx.x * 4u;
+  const uint32_t full = lane0 + (uint32_t)((kListCap - kBatch) * BS * 4);
+  uint32_t tail = lane0;   // next free entry
   Acc acc = {0.f, 0.f, 0.f};
-  NeighbourRows rows;
-  rows.init(cx, cy, cz);
-  int t = 0, t_end = 0;
-  float ax = pi.x, ay = pi.y, az = pi.z;   // i shifted to the current cell's image
-  bool done = false;
-  while (!done) {
-    // phase A: candidates into the list, kBatch run entries at a time (a
-    // batch past the run's end reads the far-away pad particle)
-    int cnt = 0;
-    while (cnt <= kListCap - kBatch) {
-      if (t >= t_end) {
-        float sx, sy, sz;
-        if (!rows.next(G, start_all, co, t, t_end, sx, sy, sz)) {
-          done = true;
-          break;
-        }
-        ax = sub_nc(pi.x, sx);
-        ay = sub_nc(pi.y, sy);
-        az = sub_nc(pi.z, sz);
-        continue;
-      }
-      int jb[kBatch];
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u) jb[u] = t + u < t_end ? idx_all[t + u] : pad;
-      float4 pb[kBatch];
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u) pb[u] = pos4[jb[u]];
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
-        const float r2 = pair_r2(sub_nc(ax, pb[u].x), sub_nc(ay, pb[u].y), sub_nc(az, pb[u].z));
-        // r2 > 0 drops i itself (and coincident particles, whose force is 0)
-        if (r2 < P.rc2 && r2 > 0.0f) {
-          mine[cnt * BS] = (uint32_t)jb[u];
-          ++cnt;
-        }
-      }
-      t += kBatch;
-    }
-    // phase B: the listed pairs of this lane
-    for (int q = 0; q < cnt; ++q) {
-      const uint32_t j = mine[q * BS];
-      const float4 pj = pos4[j];
-      const float4 vtj = vt4[j];
+  // phase B: the listed pairs of this lane, in list (= candidate) order; the
+  // next pair's data is fetched while the current one is evaluated
+  auto flush = [&]() {
+    int j = tail > lane0 ? *(const int *)(lds + lane0) : pad;
+    float4 pj = posr[j], vtj = vtr[j];
+    for (uint32_t q = lane0; q < tail; q += BS * 4u) {
+      const uint32_t qn = q + BS * 4u;
+      const int jn = qn < tail ? *(const int *)(lds + qn) : pad;
+      const float4 pjn = posr[jn], vtjn = vtr[jn];
       const float dx = min_image(pi.x - pj.x, G.L[0]);
       const float dy = min_image(pi.y - pj.y, G.L[1]);
       const float dz = min_image(pi.z - pj.z, G.L[2]);
@@ -633,8 +617,90 @@ __global__ __launch_bounds__(BS) void k_force(
       const float a = (int64_t)j < NF ? P.a_ff : P.a_fw;
       add_pair(acc, dx, dy, dz, r2, vti.x - vtj.x, vti.y - vtj.y, vti.z - vtj.z, a, P, gi,
                __float_as_uint(pj.w), klo, khi);
+      j = jn;
+      pj = pjn;
+      vtj = vtjn;
+    }
+    tail = lane0;
+  };
+  // Phase A for one neighbour row: the wavefront walks the lane's runs in
+  // lockstep, kBatch run entries per lane and pass (run A, then run B where
+  // the row wraps; a lane moves to B on its own).  Entries past the lane's
+  // run are read (other cells' entries, or the pad) but never listed.
+  // Phase B runs when a lane's list could overflow in the next pass.
+  auto walk = [&](int t, int t_end, int tb, int tb_end, float ax, float axb, float ay,
+                  float az) {
+    {
+      const bool sw = t >= t_end;
+      t = sw ? tb : t;
+      t_end = sw ? tb_end : t_end;
+      tb = sw ? tb_end : tb;
+      ax = sw ? axb : ax;
+    }
+    for (;;) {
+      while (wave_any(t < t_end) && !wave_any(tail > full)) {
+        const int rem = t_end - t;
+        int jb[kBatch];
+        runs.load(t, jb);
+        float4 pb[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) pb[u] = posr[jb[u]];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+          const float r2 =
+              pair_r2(sub_nc(ax, pb[u].x), sub_nc(ay, pb[u].y), sub_nc(az, pb[u].z));
+          // r2 > 0 drops i itself (and coincident particles, whose force is 0)
+          const bool hit = r2 < P.rc2 && r2 > 0.0f && u < rem;
+          *(int *)(lds + tail) = jb[u];
+          tail += hit ? (uint32_t)(BS * 4) : 0u;
+        }
+        t = rem > 0 ? t + kBatch : t;
+        const bool sw = t >= t_end && tb < tb_end;
+        t = sw ? tb : t;
+        t_end = sw ? tb_end : t_end;
+        tb = sw ? tb_end : tb;
+        ax = sw ? axb : ax;
+      }
+      if (!wave_any(t < t_end)) break;
+      flush();
+    }
+  };
+
+  const int nx = G.nc[0], ny = G.nc[1], nz = G.nc[2];
+  for (int oz = -1; oz <= 1; ++oz) {
+    int qz = cz + oz;
+    float sz = 0.f;
+    if (qz < 0) { qz += nz; sz = -G.L[2]; }
+    else if (qz >= nz) { qz -= nz; sz = G.L[2]; }
+    const float az = sub_nc(pi.z, sz);
+    for (int oy = -1; oy <= 1; ++oy) {
+      int qy = cy + oy;
+      float sy = 0.f;
+      if (qy < 0) { qy += ny; sy = -G.L[1]; }
+      else if (qy >= ny) { qy -= ny; sy = G.L[1]; }
+      const float ay = sub_nc(pi.y, sy);
+      // the row's x-neighbours [cx-1, cx+1] as run A, plus run B where the
+      // row wraps (cell nx-1 seen across the left edge, then cells 0 and 1;
+      // or cells nx-2 and nx-1, then cell 0 seen across the right edge)
+      const int base = co + (qz * ny + qy) * nx;
+      const bool left = cx == 0, right = cx == nx - 1;
+      const int a0 = left ? base + nx - 1 : (right ? base + nx - 2 : base + cx - 1);
+      int v[4];
+      starts.load(a0, v);
+      const int ta = v[0], ta_end = left ? v[1] : (right ? v[2] : v[3]);
+      int tb = 0, tb_end = 0;
+      if (wave_any(left || right)) {
+        int w[4];
+        starts.load(base, w);
+        tb = (left || right) ? w[0] : 0;
+        tb_end = left ? w[2] : (right ? w[1] : 0);
+      }
+      const float sxa = left ? -G.L[0] : 0.f, sxb = right ? G.L[0] : 0.f;
+      const float ax = sub_nc(pi.x, sxa), axb = sub_nc(pi.x, sxb);
+      walk(ta, ta_end, tb, tb_end, ax, axb, ay, az);
     }
   }
+  flush();
   const float fx = acc.x + P.g[0], fy = acc.y + P.g[1], fz = acc.z + P.g[2];
   const float4 vo = vel4[i];
   float4 vn;
@@ -850,10 +916,10 @@ hipError_t launch_scatter(hipStream_t s, int64_t n, const int32_t *cell_of,
 }
 
 hipError_t launch_sort_cells(hipStream_t s, int64_t ncell, const int32_t *start, int32_t *idx,
-                             const float4 *key4,
-                             const int32_t *fluid_off, int32_t *idx_all) {
+                             const float4 *key4, const int32_t *fluid_off, int32_t *idx_all) {
   if (key4)
-    k_sort_cells<true><<<grid_for(ncell), kBlock, 0, s>>>(ncell, start, idx, key4, fluid_off, idx_all);
+    k_sort_cells<true><<<grid_for(ncell), kBlock, 0, s>>>(ncell, start, idx, key4, fluid_off,
+                                                        idx_all);
   else
     k_sort_cells<false><<<grid_for(ncell), kBlock, 0, s>>>(ncell, start, idx, key4, fluid_off,
                                                          idx_all);
@@ -872,8 +938,8 @@ hipError_t launch_bump_k(hipStream_t s, unsigned long long *dk) {
   return hipGetLastError();
 }
 
-hipError_t launch_set_pad(hipStream_t s, float4 *pos4, float4 *vt4) {
-  k_set_pad<<<1, 1, 0, s>>>(pos4, vt4);
+hipError_t launch_set_pad(hipStream_t s, float4 *pos4, float4 *vt4, int32_t *slack, int32_t pad) {
+  k_set_pad<<<1, 1, 0, s>>>(pos4, vt4, slack, pad);
   return hipGetLastError();
 }
 
@@ -960,7 +1026,8 @@ hipError_t launch_integrate(hipStream_t s, int ppt, const Box *boxes, const Tile
 }
 
 hipError_t launch_force(hipStream_t s, int block, const Box *boxes, const Tile *tiles,
-                        int ntiles, int64_t NF, int32_t pad, int init, const float4 *pos4,
+                        int ntiles, int64_t NF, int32_t pad, int32_t ncell_all, int init,
+                        const float4 *pos4,
                         const float4 *vt4, const float4 *vel4, const float4 *frc4,
                         const int32_t *idx, const int32_t *idx_all, const int32_t *start_all,
                         float4 *pos_out, float4 *vel_out, float4 *frc_out,
@@ -968,8 +1035,8 @@ hipError_t launch_force(hipStream_t s, int block, const Box *boxes, const Tile *
   if (ntiles <= 0) return hipSuccess;
   const unsigned nb = (unsigned)(((ntiles + 7) / 8) * 8);
 #define DPD_FORCE(I, BS)                                                                        \
-  k_force<I, BS><<<nb, BS, 0, s>>>(boxes, tiles, ntiles, NF, pad, pos4, vt4, vel4, frc4, idx,   \
-                                   idx_all, start_all, pos_out, vel_out, frc_out, dk, st)
+  k_force<I, BS><<<nb, BS, 0, s>>>(boxes, tiles, ntiles, NF, pad, ncell_all, pos4, vt4, vel4,   \
+                                   frc4, idx, idx_all, start_all, pos_out, vel_out, frc_out, dk, st)
   if (block == 128) {
     if (init) DPD_FORCE(true, 128); else DPD_FORCE(false, 128);
   } else {

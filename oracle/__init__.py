@@ -44,7 +44,8 @@ class Geom(C.Structure):
 class Params(C.Structure):
     _fields_ = [("a", (C.c_double * 2) * 2), ("gamma", C.c_double), ("kBT", C.c_double),
                 ("rc", C.c_double), ("dt", C.c_double), ("lam", C.c_double),
-                ("g", C.c_double * 3), ("seed", C.c_uint64), ("replica", C.c_uint32)]
+                ("g", C.c_double * 3), ("seed", C.c_uint64), ("replica", C.c_uint32),
+                ("specular", C.c_int32)]
 
 
 _lib = None
@@ -149,8 +150,8 @@ class Oracle:
         self.type = np.ascontiguousarray(system.type, dtype=np.int32)
         self.gid = np.ascontiguousarray(system.gid, dtype=np.uint32)
         self.r = np.ascontiguousarray(system.pos, dtype=np.float64).copy()
+        # a wall particle's velocity is the velocity of its solid (it stays in place)
         self.v = np.ascontiguousarray(system.vel, dtype=np.float64).copy()
-        self.v[self.type != 0] = 0.0
         self.f = np.zeros((self.n, 3), np.float64)
         self.vt = self.v.copy()
         self.xs = np.ascontiguousarray(system.pos, dtype=np.float32).copy()
@@ -197,6 +198,7 @@ class Oracle:
             cp.g[a] = float(p["g"][a])
         cp.seed = int(p["seed"]) & 0xFFFFFFFFFFFFFFFF
         cp.replica = int(p["replica"])
+        cp.specular = 1 if p.get("specular", False) else 0
         return cp
 
     def set_params(self, **kw):
@@ -261,6 +263,8 @@ class Oracle:
         Returns dict(profile, sums, counts, logs, r, v): profile[b] =
         sums[b] / counts[b] is the window mean of v_x in bin b along `axis`."""
         n, T = self.n, int(T)
+        if self.params.get("specular", False) or np.any(self.v[self.type != 0] != 0.0):
+            raise ValueError("the window covers resting walls with bounce-back only")
         record = logs is None
         if record:
             logs = dict(ev=np.zeros((T, n), np.int32), xs=np.zeros((T, n, 3), np.float32),

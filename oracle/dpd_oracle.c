@@ -24,6 +24,18 @@
  *   - Eq. 17 with the start-of-step velocity v^t as printed; if the mirrored
  *     point is still in the solid the particle returns to r^t
  *   - after a bounce v = -v^t and the predicted velocity is -v^t as well
+ *   - moving walls (Sec. II.C): a wall particle's velocity is the velocity of
+ *     its solid, a body that keeps its shape and phase field while it moves
+ *     (a plate sliding in its own plane): wall particles translate with it,
+ *     r_w += dt v_w, and carry it as their predicted velocity in the pair
+ *     forces.  A reflection takes v_wall from the wall particle nearest to r*
+ *     (start-of-step wall positions, the 27-cell neighbourhood of r*'s cell,
+ *     the FP32 pair-decision distance, ties to the smaller gid; none: zero),
+ *     uses v^t - v_wall in Eq. 17 and leaves v = -v^t + 2 v_wall
+ *   - specular reflection (Sec. I): only the component of v^t - v_wall along
+ *     the normal n = grad Phi / |grad Phi| at r* is reversed, in the velocity
+ *     and in the Eq. 17 displacement; |grad Phi| = 0 falls back to
+ *     bounce-back
  *   - atanh arguments clamped to [0, 1 - 2^-20]
  *   - mass 1, box periodic in all three axes, phi grid periodic and
  *     node-centred, trilinear interpolation ("linear interpolation", Sec. II.C)
@@ -138,6 +150,7 @@ typedef struct {
     double g[3];        /* body force on fluid particles */
     uint64_t seed;
     uint32_t replica;
+    int32_t specular;   /* 1: specular reflection, 0: bounce-back */
 } orc_params;
 
 static int orc_mod(int a, int n)
@@ -538,13 +551,61 @@ static void drift32(const orc_geom *G, const orc_params *P, const float x[3],
     }
 }
 
+/* Velocity of the solid at a reflection at r* (FP32 shadow y32): that of the
+ * wall particle nearest to r* among the walls (at their start-of-step
+ * positions xs) in the 27-cell neighbourhood of the cell of y32, nearness by
+ * the FP32 pair-decision r2 (image shift of the neighbour cell), ties to the
+ * smaller gid; no wall there: zero.  Brute force over all walls. */
+static void wall_velocity(const orc_geom *G, int64_t n, const double *v, const float *xs,
+                          const int32_t *type, const uint32_t *gid, const float y32[3],
+                          double out[3])
+{
+    const int nx = G->nc[0], ny = G->nc[1], nz = G->nc[2];
+    const int ncs[3] = {nx, ny, nz};
+    const int32_t c = orc_cell_of(G, y32);
+    const int cc[3] = {c % nx, (c / nx) % ny, c / (nx * ny)};
+    float best = INFINITY;
+    uint32_t best_gid = 0;
+    int64_t best_j = -1;
+    for (int64_t j = 0; j < n; ++j) {
+        if (type[j] == 0) continue;
+        int32_t wc = orc_cell_of(G, xs + 3 * j);
+        const int wcc[3] = {wc % nx, (wc / nx) % ny, wc / (nx * ny)};
+        int near = 1, sh[3];
+        for (int a = 0; a < 3; ++a) {
+            /* neighbour offset o in {-1, 0, 1} with q = cc + o wrapped; the
+             * image shift is -1 below 0 and +1 past the last cell */
+            int o = wcc[a] - cc[a];
+            if (o == ncs[a] - 1) o = -1;
+            else if (o == -(ncs[a] - 1)) o = 1;
+            if (o < -1 || o > 1) { near = 0; break; }
+            int q = cc[a] + o;
+            sh[a] = q < 0 ? -1 : (q >= ncs[a] ? 1 : 0);
+        }
+        if (!near) continue;
+        float ax = y32[0] - (float)sh[0] * G->L32[0];
+        float ay = y32[1] - (float)sh[1] * G->L32[1];
+        float az = y32[2] - (float)sh[2] * G->L32[2];
+        float dx = ax - xs[3 * j], dy = ay - xs[3 * j + 1], dz = az - xs[3 * j + 2];
+        float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        if (r2 < best || (r2 == best && gid[j] < best_gid)) {
+            best = r2;
+            best_gid = gid[j];
+            best_j = j;
+        }
+    }
+    for (int a = 0; a < 3; ++a) out[a] = best_j >= 0 ? v[3 * best_j + a] : 0.0;
+}
+
 /*
  * One step of the method for every fluid particle (walls frozen):
  *   1. r* = r + dt v + dt^2/2 f,  vt = v + lambda dt f   (Groot-Warren)
- *   2. if phi(r*) < 0: bounce back (Sec. II.C, Eq. 16-17):
+ *   2. if phi(r*) < 0: reflect (Sec. II.C, Eq. 16-17):
  *        c1 = atanh(-phi*), c0 = atanh(phi^t),  s = c1 / (c0 + c1)
- *        r_bb = r* - 2 s dt v^t;  if phi(r_bb) < 0 then r_bb = r^t (code 2)
- *        r = r_bb,  v = -v^t,  vt = -v^t  (code 1 or 2)
+ *        u = v^t - v_wall (bounce-back) or ((v^t - v_wall) . n) n (specular)
+ *        r_bb = r* - 2 s dt u;  if phi(r_bb) < 0 then r_bb = r^t (code 2)
+ *        r = r_bb,  v = v^t - 2 u,  vt = v  (code 1 or 2)
+ *      (resting walls, bounce-back: u = v^t, v = -v^t)
  *   3. k += 1;  f' = forces(r, vt) with the random numbers of evaluation k
  *   4. non-bounced particles: v = v + dt/2 (f + f');  f = f'
  * Positions r, v, f are FP64 arrays of n*3; xs receives the FP32 shadow
@@ -564,14 +625,17 @@ int orc_step(const orc_geom *G, const orc_params *P, int64_t n, double *r,
     double *fnew = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
     if (!vold || !fnew) { free(vold); free(fnew); return -1; }
 
+    int moving = 0;
+    for (int64_t i = 0; i < n; ++i)
+        if (type[i] != 0 && (v[3 * i] != 0.0 || v[3 * i + 1] != 0.0 || v[3 * i + 2] != 0.0))
+            moving = 1;
+
     for (int64_t i = 0; i < n; ++i) {
         events[i] = 0;
         for (int a = 0; a < 3; ++a) vold[3 * i + a] = v[3 * i + a];
         if (type[i] != 0) {
-            for (int a = 0; a < 3; ++a) {
-                vt[3 * i + a] = 0.0;
-                xs[3 * i + a] = (float)r[3 * i + a];
-            }
+            /* a wall particle's velocity is its solid's (moved below) */
+            for (int a = 0; a < 3; ++a) vt[3 * i + a] = v[3 * i + a];
             continue;
         }
         float x32[3], v32[3], f32[3], y32[3];
@@ -606,9 +670,23 @@ int orc_step(const orc_geom *G, const orc_params *P, int64_t n, double *r,
         if (a0 > 1.0 - delta) a0 = 1.0 - delta;
         double c1 = atanh(a1), c0 = atanh(a0);
         double sfrac = (c1 > 0.0) ? c1 / (c0 + c1) : 0.0;
+        /* the reversed part u of the velocity relative to the wall */
+        double vw[3] = {0.0, 0.0, 0.0}, u[3];
+        if (moving) wall_velocity(G, n, v, xs, type, gid, y32, vw);
+        for (int a = 0; a < 3; ++a) u[a] = v[3 * i + a] - vw[a];
+        if (P->specular) {
+            double gr[3];
+            orc_phi64(G, rs, gr);
+            double gn = sqrt(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]);
+            if (gn > 0.0) {
+                double nrm[3] = {gr[0] / gn, gr[1] / gn, gr[2] / gn};
+                double un = u[0] * nrm[0] + u[1] * nrm[1] + u[2] * nrm[2];
+                for (int a = 0; a < 3; ++a) u[a] = un * nrm[a];
+            }
+        }
         double rbb[3];
         float bb32[3];
-        for (int a = 0; a < 3; ++a) rbb[a] = rs[a] - 2.0 * sfrac * dt * v[3 * i + a];
+        for (int a = 0; a < 3; ++a) rbb[a] = rs[a] - 2.0 * sfrac * dt * u[a];
         for (int a = 0; a < 3; ++a) {
             bb32[a] = (float)rbb[a];
             int sh = wrap32(&bb32[a], G->L32[a]);
@@ -626,8 +704,25 @@ int orc_step(const orc_geom *G, const orc_params *P, int64_t n, double *r,
         for (int a = 0; a < 3; ++a) {
             r[3 * i + a] = rbb[a];
             xs[3 * i + a] = bb32[a];
-            vt[3 * i + a] = -v[3 * i + a];
-            v[3 * i + a] = -v[3 * i + a];
+            v[3 * i + a] = v[3 * i + a] - 2.0 * u[a];
+            vt[3 * i + a] = v[3 * i + a];
+        }
+    }
+
+    /* walls translate with their solid: r_w += dt v_w, decided in FP32 as
+     * the fluid drift with zero force */
+    for (int64_t i = 0; i < n; ++i) {
+        if (type[i] == 0) continue;
+        float x32[3], v32[3], z32[3] = {0.0f, 0.0f, 0.0f}, y32[3];
+        int s[3];
+        for (int a = 0; a < 3; ++a) {
+            x32[a] = (float)r[3 * i + a];
+            v32[a] = (float)v[3 * i + a];
+        }
+        drift32(G, P, x32, v32, z32, y32, s);
+        for (int a = 0; a < 3; ++a) {
+            r[3 * i + a] += dt * v[3 * i + a] + s[a] * G->L[a];
+            xs[3 * i + a] = y32[a];
         }
     }
 

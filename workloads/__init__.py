@@ -21,7 +21,7 @@ import math
 import numpy as np
 
 __all__ = [
-    "System", "slab_system", "sinusoid_cylinder_system", "porous_system",
+    "System", "slab_system", "couette_system", "sinusoid_cylinder_system", "porous_system",
     "sinusoid_slit_system", "replica_systems", "tiny_slab_system",
     "corner_minmax", "maxwell_velocities", "bulk_system",
 ]
@@ -245,6 +245,31 @@ def slab_system(L=(10.0, 10.0, 10.0), wall=1.5, rho=3.0, h=0.25, width=0.5,
     rng_v = np.random.default_rng(seed_fluid + 1000)
     return _assemble(name, L, fluid, wallp, params["kBT"], rng_v, phi,
                      (h, h, h), params, dict(lo=lo, hi=hi, width=width))
+
+
+def couette_system(L=(6.0, 4.0, 7.0), wall=1.5, U=1.0, rho=3.0, h=0.25, grid_dtype=np.float32,
+                   seed=50, specular=False, linear_start=True, params=None, name="couette"):
+    """Plane Couette flow: the slab channel of `slab_system` without body
+    force, the wall below the fluid at rest and the wall above it moving at
+    U along x (its wall particles carry that velocity; positions stay
+    fixed).  With `linear_start` the fluid starts on the steady profile
+    v_x = U (z - wall) / (Lz - 2 wall) plus thermal velocities.  `specular`
+    is stored in the parameters (reflection mode)."""
+    p = dict(params or default_params(g=(0.0, 0.0, 0.0), seed=seed))
+    p["specular"] = bool(specular)
+    s = slab_system(L=L, wall=wall, rho=rho, h=h, grid_dtype=grid_dtype, seed_fluid=seed,
+                    seed_wall=seed + 1, params=p, wall_fill="uniform", name=name)
+    lo, hi = s.meta["lo"], s.meta["hi"]
+    z = s.pos[:, 2].astype(np.float64)
+    top = (s.type != 0) & (z >= hi)
+    vel = s.vel.astype(np.float64)
+    vel[top, 0] = U
+    if linear_start:
+        fl = s.type == 0
+        vel[fl, 0] += U * (z[fl] - lo) / (hi - lo)
+    s.vel = vel.astype(np.float32)
+    s.meta.update(U=float(U), specular=bool(specular))
+    return s
 
 
 def tiny_slab_system(L=(4.0, 4.0, 6.0), wall=1.0, rho=3.0, seed=7, g=(0.05, 0, 0),

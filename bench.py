@@ -94,6 +94,8 @@ def main():
                     help="steps of the 256-replica batch leg and of its sequential "
                          "comparison (0 skips the leg)")
     ap.add_argument("--replicas", type=int, default=256)
+    ap.add_argument("--walls-steps", type=int, default=200,
+                    help="steps of the moving-wall leg (plane Couette channel); 0 skips it")
     ap.add_argument("--adjoint-reps", type=int, default=3,
                     help="timed repetitions of the 200-step adjoint window (0 skips the leg)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -183,6 +185,10 @@ def main():
         sim.close()
         adjoint = adjoint_leg(dpd, args.adjoint_reps)
 
+    walls = None
+    if args.walls_steps > 0:
+        walls = walls_leg(dpd, args.walls_steps)
+
     cpu = None
     if args.cpu_steps > 0:
         import oracle
@@ -225,6 +231,7 @@ def main():
         "cpu_baseline": cpu,
         "batch": batch,
         "adjoint": adjoint,
+        "moving_walls": walls,
     }
     print(json.dumps(out), flush=True)
     sim.close()
@@ -282,6 +289,45 @@ def batch_leg(dpd, replicas, steps):
             "speedup_vs_sequential": batched / seq, "shape": list(shape),
             "trial_ms_per_step": trials, "graph": True,
             "kernel_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in kt.items() if v[1]}}
+
+
+def walls_leg(dpd, steps, L=(192.0, 192.0, 10.0)):
+    """Moving walls and specular reflection: a plane Couette channel (fluid
+    1.5 < z < 8.5 at density 3, the plate above sliding at U = 1), stepped
+    with resting plates, with the sliding plate (bounce-back: the walls
+    translate and are re-sorted every step, reflections look up the plate's
+    velocity) and with the sliding plate and specular reflection."""
+    import torch
+    import workloads
+    import dataclasses
+    t0 = time.time()
+    base = workloads.couette_system(L=L, U=1.0, seed=80)
+    walls = base.type != 0
+    res = {}
+    for name, U, spec in (("resting", 0.0, False), ("sliding", 1.0, False),
+                          ("sliding_specular", 1.0, True)):
+        vel = base.vel.copy()
+        if U == 0.0:
+            vel[walls] = 0.0
+        s = dataclasses.replace(base, vel=vel, params=dict(base.params, specular=spec))
+        sim = dpd.Simulation(s, graph=True)
+        sim.step(20)
+        sim.sync()
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        sim.step(steps)
+        sim.sync()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - ta
+        c = sim.counters()
+        sim.close()
+        res[name] = {"ms_per_step": dt * 1e3 / steps, "value": s.n * steps / dt,
+                     "unit": "particle-steps/s", "bounces_per_step": c["bounce"] / (steps + 20)}
+        log("walls leg %-16s %d particles: %.4f ms/step, %.4e particle-steps/s" %
+            (name, s.n, dt * 1e3 / steps, s.n * steps / dt))
+    return {"workload": "couette_channel", "box": list(L), "particles": s.n,
+            "fluid": int((s.type == 0).sum()), "steps": steps, **res,
+            "generated_in_s": time.time() - t0}
 
 
 def adjoint_leg(dpd, reps, steps=200, ckpt=20, nbins=40):

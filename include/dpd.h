@@ -49,8 +49,14 @@ enum {
 
 /* params.flags */
 enum {
-    DPD_FLAG_NO_MASK = 1  /* test phi for every particle, not only in cells
-                             near the interface (results are identical) */
+    DPD_FLAG_NO_MASK = 1,  /* test phi for every particle, not only in cells
+                              near the interface (results are identical) */
+    DPD_FLAG_SPECULAR = 2  /* specular reflection (Sec. I): only the component
+                              of the velocity relative to the wall along the
+                              normal grad phi / |grad phi| at the crossing
+                              position is reversed, in the new velocity and
+                              in the displacement of Eq. 17; without it,
+                              bounce-back (Sec. II.C) reverses all of it */
 };
 
 typedef struct dpd_ctx dpd_ctx;
@@ -64,7 +70,15 @@ typedef struct {
  * fluid particles where phi > 0, frozen wall particles where phi <= 0).
  *   n     number of particles, fluid and wall together
  *   pos   n x 3 float32, row-major, each coordinate in [0, L)
- *   vel   n x 3 float32 (rows of wall particles are ignored: walls are frozen)
+ *   vel   n x 3 float32; for a wall particle, the velocity of its solid
+ *         (Sec. II.C, moving walls): a solid keeps its shape and phase
+ *         field while it moves, e.g. a plate sliding in its own plane; its
+ *         wall particles translate by dt v per step and carry v into the
+ *         pair forces, and a reflection uses the velocity of the wall
+ *         particle nearest to the crossing position (start-of-step walls
+ *         of the 27 cells around it, FP32 pair distance, ties to the
+ *         smaller gid): v = -v^t + 2 v_wall, Eq. 17 with v^t - v_wall.
+ *         Zero rows: resting walls.  |v| dt must stay below half a cell.
  *   type  n int32, DPD_TYPE_FLUID or DPD_TYPE_WALL
  *   gid   n uint32, a permutation of 0..n-1 naming the particle in the
  *         random-number counter and in every getter's row order; NULL means
@@ -158,8 +172,8 @@ int dpd_step(dpd_ctx *ctx, int64_t n);
 int dpd_forces(dpd_ctx *ctx, float *f_out);
 
 /* Current state in gid order, into device buffers; any pointer may be NULL.
- *   pos     n x 3 float32 positions (walls: their fixed positions)
- *   vel     n x 3 float32 velocities (walls: zero)
+ *   pos     n x 3 float32 positions (walls: fixed, or moved with their solid)
+ *   vel     n x 3 float32 velocities (walls: their solid's velocity)
  *   events  n int32: the last step's bounce-back code per particle,
  *           0 none, 1 reflected by Eq. 17, 2 returned to the start position
  *   cell_of n int32: cell index (cz * ncy + cy) * ncx + cx of the position,
@@ -168,7 +182,8 @@ int dpd_get_state(dpd_ctx *ctx, float *pos, float *vel, int32_t *events,
                   int32_t *cell_of);
 
 /* Replace the fluid state: pos, vel, force are n x 3 float32 rows in gid
- * order (wall rows are ignored; walls keep their positions), k the index of
+ * order (wall rows are ignored, except that walls of a box with moving walls
+ * take their positions from pos; wall velocities never change), k the index of
  * the random numbers the forces were evaluated with.  Host or device memory
  * per on_device.  Positions must lie in [0, L) and satisfy phi >= 0. */
 int dpd_set_state(dpd_ctx *ctx, const float *pos, const float *vel,
@@ -281,7 +296,8 @@ int dpd_set_phi(dpd_ctx *ctx, int32_t r, const void *data, int32_t on_device);
  * profile (device, nbins float64) and counts (device, nbins int64: N_b) may
  * be NULL.  A checkpoint of the fluid state is stored every ckpt steps
  * (1 <= ckpt <= steps, nbins <= 1024); the context ends at the window's last
- * state.  DPD_E_STATE for a batch context.
+ * state.  DPD_E_STATE for a batch context; DPD_E_INVAL for moving walls or
+ * DPD_FLAG_SPECULAR (the adjoint covers resting walls with bounce-back).
  *
  * dpd_backward: gradients of a loss L(profile) from dL_dprofile (device,
  * nbins float64) by the hand-written adjoint of every step of the window

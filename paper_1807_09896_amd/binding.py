@@ -24,6 +24,7 @@ DPD_E_DEVICE = -3
 DPD_E_UNSTABLE = -4
 DPD_E_STATE = -5
 DPD_FLAG_NO_MASK = 1
+DPD_FLAG_SPECULAR = 2
 DPD_NUM_KERNELS = 8
 
 _ERRNAMES = {DPD_E_INVAL: "DPD_E_INVAL", DPD_E_NOMEM: "DPD_E_NOMEM",
@@ -225,7 +226,11 @@ def _marshal_box(L, pos, vel, type_, gid, params, phi, h, flags, keep):
 
 
 def _params_struct(params, flags=0):
+    """dpd_params from a parameter dict; a true params["specular"] adds
+    DPD_FLAG_SPECULAR to flags."""
     a = params["a"]
+    if params.get("specular", False):
+        flags = int(flags) | DPD_FLAG_SPECULAR
     return dpd_params((C.c_double * 4)(a[0][0], a[0][1], a[1][0], a[1][1]), params["gamma"],
                       params["kBT"], params["rc"], params["dt"], params["lam"],
                       (C.c_double * 3)(*params["g"]),

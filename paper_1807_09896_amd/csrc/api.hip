@@ -51,6 +51,7 @@ struct Replica {
   int nc[3] = {0, 0, 0}, ng[3] = {0, 0, 0};
   double L[3] = {0, 0, 0}, h[3] = {0, 0, 0};
   double rc = 0;
+  bool moving = false;   // some wall particle has a nonzero velocity
   KGeom G{};
   KParams P{};
   int64_t flagged_cubes = 0;
@@ -106,6 +107,12 @@ struct dpd_ctx {
   int32_t *wcstart = nullptr;   // exclusive scan of wall counts per cell (static)
   int32_t *wcell = nullptr;     // global cell of each cell-sorted wall (static)
   int32_t *idx_all = nullptr;   // merged per-cell runs: walls (NF + w), then fluid
+  // moving walls: re-sorted by cell every step (moved copy, velocities,
+  // cells, ranks, per-cell counts)
+  bool moving = false;
+  bool reflect = false;   // some box has moving walls or specular reflection
+  float4 *wtmp = nullptr, *wvtmp = nullptr;
+  int32_t *wcell_tmp = nullptr, *wrank = nullptr, *wcount = nullptr;
   int32_t *start_all = nullptr; // start of each cell's merged run
   int32_t *fluid_off = nullptr; // start of each cell's fluid part in the merged run
   void *grid = nullptr;
@@ -370,14 +377,76 @@ int force_pass(dpd_ctx *c, hipStream_t s, int init) {
 }
 
 // The launches of one step on stream s (swaps cur).
+// Walls re-sorted by cell after their positions changed; with `move` the
+// walls of every box whose solid moves first advance by dt v.  Reads the
+// walls at pos[cur] + NF (velocities at vt + NF), writes them back in cell
+// order (within a cell by storage index) to both position buffers and vt,
+// and rebuilds wcell and wcstart.
+int wall_pass(dpd_ctx *c, hipStream_t s, int move) {
+  if (c->NW == 0) return DPD_OK;
+  const int a = c->cur, b = 1 - a;
+  float4 *wp = c->pos[a] + c->NF, *wv = c->vt + c->NF;
+  for (int r = 0; r < c->R; ++r) {
+    const Replica &p = c->rep[r];
+    if (p.nw == 0) continue;
+    HIP_TRY(c, timed(c, s, K_OTHER, [&] {
+              if (move && p.moving)
+                return dpd::launch_wall_move(s, p.G, p.P.hdt, p.P.dt, p.nw, wp + p.wo, wv + p.wo,
+                                             c->wtmp + p.wo);
+              return dpd::launch_copy(s, c->wtmp + p.wo, wp + p.wo, 16 * (size_t)p.nw);
+            }));
+    HIP_TRY(c, timed(c, s, K_OTHER, [&] {
+              return dpd::launch_bin(s, p.G, p.co, p.nw, c->wtmp + p.wo, c->wcell_tmp + p.wo,
+                                     c->wrank + p.wo, c->wcount);
+            }));
+  }
+  HIP_TRY(c, timed(c, s, K_OTHER, [&] {
+            return dpd::launch_copy(s, c->wvtmp, wv, 16 * (size_t)c->NW);
+          }));
+  HIP_TRY(c, timed(c, s, K_SCAN_REDUCE, [&] {
+            return dpd::launch_scan_reduce(s, c->NCELL, c->wcount, c->bsum);
+          }));
+  HIP_TRY(c, timed(c, s, K_SCAN_TOP, [&] { return dpd::launch_scan_top(s, c->nscan, c->bsum); }));
+  HIP_TRY(c, timed(c, s, K_SCAN_DOWN, [&] {
+            return dpd::launch_scan_down(s, c->NCELL, c->wcount, c->wcstart, c->bsum, nullptr,
+                                         nullptr, nullptr);
+          }));
+  HIP_TRY(c, timed(c, s, K_SCATTER, [&] {
+            return dpd::launch_scatter(s, c->NW, c->wcell_tmp, c->wrank, c->wcstart, c->idx);
+          }));
+  HIP_TRY(c, timed(c, s, K_SORT, [&] {
+            return dpd::launch_sort_cells(s, c->NCELL, c->wcstart, c->idx, nullptr, nullptr,
+                                          nullptr);
+          }));
+  HIP_TRY(c, timed(c, s, K_OTHER, [&] {
+            return dpd::launch_permute(s, c->NW, c->idx, c->wtmp, wp, c->wvtmp, wv, nullptr,
+                                       nullptr);
+          }));
+  HIP_TRY(c, timed(c, s, K_OTHER, [&] {
+            return dpd::launch_copy(s, c->pos[b] + c->NF, wp, 16 * (size_t)c->NW);
+          }));
+  for (int r = 0; r < c->R; ++r) {
+    const Replica &p = c->rep[r];
+    if (p.nw == 0) continue;
+    HIP_TRY(c, timed(c, s, K_OTHER, [&] {
+              return dpd::launch_cells(s, p.G, p.co, p.nw, wp + p.wo, c->wcell + p.wo);
+            }));
+  }
+  return DPD_OK;
+}
+
 int enqueue_step(dpd_ctx *c, hipStream_t s) {
   const int a = c->cur;
   HIP_TRY(c, timed(c, s, K_INTEGRATE, [&] {
             return dpd::launch_integrate(s, c->ppt, c->boxes, c->itiles, c->n_itiles, c->pos[a],
                                          c->vel[a], c->frc[a], c->vt, c->cell_of, c->rank_of,
                                          c->count, c->bits, c->use_mask, c->grid, c->grid_f64,
-                                         c->status);
+                                         c->status, c->NF, c->wcstart, c->reflect ? 1 : 0);
           }));
+  if (c->moving) {
+    int rc = wall_pass(c, s, 1);
+    if (rc) return rc;
+  }
   int rc = scan_scatter_sort(c, s);
   if (rc) return rc;
   HIP_TRY(c, timed(c, s, K_OTHER, [&] { return dpd::launch_bump_k(s, c->dk); }));
@@ -429,7 +498,8 @@ int one_step(dpd_ctx *c) {
 // it every later summation order) depends only on the state, not on how the
 // context stored its particles before.
 int resort(dpd_ctx *c) {
-  int rc = bin_all(c, c->stream);
+  int rc = c->moving ? wall_pass(c, c->stream, 0) : DPD_OK;
+  if (!rc) rc = bin_all(c, c->stream);
   if (!rc) rc = scan_scatter_sort(c, c->stream, c->pos[c->cur]);
   if (rc) return rc;
   const int a = c->cur, b = 1 - a;
@@ -469,6 +539,8 @@ void make_kparams(const dpd_params &P, const Replica &R, KParams &K) {
   K.key0 = (uint32_t)P.seed;
   K.key1 = (uint32_t)(P.seed >> 32);
   K.replica = P.replica;
+  K.reflect = (R.moving ? dpd::kReflectMoving : 0u) |
+              ((P.flags & DPD_FLAG_SPECULAR) ? dpd::kReflectSpecular : 0u);
 }
 
 // Checks of dpd_params that need no particles.
@@ -552,7 +624,7 @@ int check_box(int r, const dpd_box *box, const dpd_particles *pp, const dpd_para
   for (int64_t i = 0; i < n; ++i) {
     if (H.type[i] != DPD_TYPE_FLUID && H.type[i] != DPD_TYPE_WALL)
       return fail(nullptr, DPD_E_INVAL, pre + "type must be 0 (fluid) or 1 (wall)");
-    if (!finite3(&H.pos[3 * i]) || (H.type[i] == DPD_TYPE_FLUID && !finite3(&H.vel[3 * i])))
+    if (!finite3(&H.pos[3 * i]) || !finite3(&H.vel[3 * i]))
       return fail(nullptr, DPD_E_INVAL, pre + "non-finite particle position or velocity");
     for (int a = 0; a < 3; ++a)
       if (!(H.pos[3 * i + a] >= 0.0f && H.pos[3 * i + a] < (float)box->L[a]))
@@ -562,6 +634,15 @@ int check_box(int r, const dpd_box *box, const dpd_particles *pp, const dpd_para
   R.n = n;
   R.nf = (int64_t)H.rows_f.size();
   R.nw = (int64_t)H.rows_w.size();
+  // a wall particle's velocity is the velocity of its solid; nonzero ones
+  // translate the walls, by less than half a cell per step
+  for (int64_t i : H.rows_w) {
+    const float *v = &H.vel[3 * i];
+    if (v[0] != 0.0f || v[1] != 0.0f || v[2] != 0.0f) R.moving = true;
+    for (int a = 0; a < 3; ++a)
+      if (std::fabs((double)v[a]) * P.dt > 0.5 * box->L[a] / R.nc[a])
+        return fail(nullptr, DPD_E_INVAL, pre + "a wall moves more than half a cell per step");
+  }
   for (int a = 0; a < 3; ++a) {
     R.ng[a] = phi->n[a];
     R.L[a] = box->L[a];
@@ -670,6 +751,19 @@ int create_impl(int32_t nbox, const dpd_box *boxes, const dpd_particles *parts,
   c->wcstart = (int32_t *)dalloc(c, 4 * (ncell + 1));
   c->wcell = (int32_t *)dalloc(c, 4 * nw);
   c->idx_all = (int32_t *)dalloc(c, 4 * (nf + nw + dpd::kIdxSlack));
+  for (const Replica &p : c->rep) {
+    c->moving = c->moving || p.moving;
+    c->reflect = c->reflect || p.P.reflect != 0;
+  }
+  if (c->moving) {
+    c->wtmp = (float4 *)dalloc(c, 16 * nw);
+    c->wvtmp = (float4 *)dalloc(c, 16 * nw);
+    c->wcell_tmp = (int32_t *)dalloc(c, 4 * nw);
+    c->wrank = (int32_t *)dalloc(c, 4 * nw);
+    c->wcount = (int32_t *)dalloc(c, 4 * ncell);
+    if (!c->wtmp || !c->wvtmp || !c->wcell_tmp || !c->wrank || !c->wcount)
+      return bail(fail(c, DPD_E_NOMEM, "device allocation failed"));
+  }
   c->start_all = (int32_t *)dalloc(c, 4 * (ncell + 1 + dpd::kStartSlack));
   c->fluid_off = (int32_t *)dalloc(c, 4 * ncell);
   c->grid = dalloc(c, (size_t)NGRID * (size_t)grids[0].dtype);
@@ -708,7 +802,8 @@ int create_impl(int32_t nbox, const dpd_box *boxes, const dpd_particles *parts,
   // ---- particles: fluid into its slots, walls sorted by cell (once) ----
   {
     float4 *wtmp = (float4 *)dalloc(c, 16 * std::max<size_t>(nw, 1));
-    if (!wtmp) return bail(fail(c, DPD_E_NOMEM, "staging allocation failed"));
+    float4 *wvel = (float4 *)dalloc(c, 16 * std::max<size_t>(nw, 1));
+    if (!wtmp || !wvel) return bail(fail(c, DPD_E_NOMEM, "staging allocation failed"));
     for (int r = 0; r < nbox && !rc; ++r) {
       const Replica &p = c->rep[r];
       const HostBox &H = host[r];
@@ -733,8 +828,8 @@ int create_impl(int32_t nbox, const dpd_box *boxes, const dpd_particles *parts,
       if (p.nw > 0) {
         chk(hipStreamSynchronize(c->stream), "sync");
         chk(hipMemcpyAsync(drows, H.rows_w.data(), 8 * (size_t)p.nw, hipMemcpyHostToDevice, c->stream), "rows");
-        chk(dpd::launch_pack(c->stream, p.nw, dpos, nullptr, dgid, drows, wtmp + p.wo, nullptr,
-                             nullptr, nullptr),
+        chk(dpd::launch_pack(c->stream, p.nw, dpos, dvel, dgid, drows, wtmp + p.wo,
+                             wvel + p.wo, nullptr, nullptr),
             "pack walls");
         chk(dpd::launch_bin(c->stream, p.G, p.co, p.nw, wtmp + p.wo, c->cell_of + p.wo,
                             c->rank_of + p.wo, c->count),
@@ -750,29 +845,32 @@ int create_impl(int32_t nbox, const dpd_box *boxes, const dpd_particles *parts,
         "scan");
     if (nw > 0) {
       // walls sorted by global cell (so each box's walls stay contiguous)
-      // into the tail of both position buffers, with zero predicted velocity
+      // into the tail of both position buffers, with their solid's velocity
+      // as predicted velocity
       chk(dpd::launch_scatter(c->stream, NW, c->cell_of, c->rank_of, c->wcstart, c->idx),
           "scatter walls");
       chk(dpd::launch_sort_cells(c->stream, NCELL, c->wcstart, c->idx, nullptr, nullptr, nullptr),
           "sort walls");
-      chk(dpd::launch_permute(c->stream, NW, c->idx, wtmp, c->pos[0] + nf, nullptr, nullptr,
+      chk(dpd::launch_permute(c->stream, NW, c->idx, wtmp, c->pos[0] + nf, wvel, c->vt + nf,
                               nullptr, nullptr),
           "permute walls");
       chk(hipMemcpyAsync(c->pos[1] + nf, c->pos[0] + nf, 16 * nw, hipMemcpyDeviceToDevice,
                          c->stream),
           "copy walls");
-      chk(dpd::launch_fill_zero(c->stream, c->vt + nf, 16 * nw), "zero wall velocities");
       for (int r = 0; r < nbox; ++r) {
         const Replica &p = c->rep[r];
         chk(dpd::launch_cells(c->stream, p.G, p.co, p.nw, c->pos[0] + nf + p.wo, c->wcell + p.wo),
             "wall cells");
       }
     }
+    // the wall counts start at zero (each wall pass leaves them zero again)
+    if (c->moving) chk(dpd::launch_fill_zero(c->stream, c->wcount, 4 * ncell), "zero wall counts");
     chk(dpd::launch_set_pad(c->stream, c->pos[0] + nf + nw, c->vt + nf + nw, c->idx_all + nf + nw,
                             (int32_t)(nf + nw)), "pad");
     chk(dpd::launch_set_pad(c->stream, c->pos[1] + nf + nw, nullptr, nullptr, 0), "pad");
     chk(hipStreamSynchronize(c->stream), "sync");
     dfree(c, wtmp);
+    dfree(c, wvel);
     if (rc) return bail(rc);
   }
 
@@ -980,7 +1078,8 @@ int backward_step(dpd_ctx *c, const float4 *x, uint64_t t, const float4 *A, floa
   HIP_TRY(c, hipMemcpyAsync(W.wpos, x, 16 * (size_t)NF, hipMemcpyDeviceToDevice, s));
   HIP_TRY(c, dpd::launch_integrate(s, c->ppt, c->boxes, c->itiles, c->n_itiles, W.wpos, x + NF,
                                    x + 2 * NF, c->vt, c->cell_of, c->rank_of, c->count, c->bits,
-                                   c->use_mask, c->grid, c->grid_f64, c->status));
+                                   c->use_mask, c->grid, c->grid_f64, c->status, NF, c->wcstart,
+                                   0));
   int rc = scan_scatter_sort(c, s);
   if (rc) return rc;
   HIP_TRY(c, dpd::launch_adj_prep(s, c->boxes, NF, 0, c->idx, W.wpos, c->vt, A, A + NF,
@@ -1140,8 +1239,9 @@ int dpd_replica_state(dpd_ctx *c, int32_t r, float *pos, float *vel, int32_t *ev
   HIP_TRY(c, dpd::launch_export(c->stream, p.G, p.nf, c->pos[c->cur] + p.fo,
                                 c->vel[c->cur] + p.fo, c->frc[c->cur] + p.fo, 0, pos, vel,
                                 nullptr, events, cell_of));
-  HIP_TRY(c, dpd::launch_export(c->stream, p.G, p.nw, c->pos[c->cur] + c->NF + p.wo, nullptr,
-                                nullptr, 1, pos, vel, nullptr, events, cell_of));
+  HIP_TRY(c, dpd::launch_export(c->stream, p.G, p.nw, c->pos[c->cur] + c->NF + p.wo,
+                                c->vt + c->NF + p.wo, nullptr, 1, pos, vel, nullptr, events,
+                                cell_of));
   return latched_error(c);
 }
 
@@ -1171,6 +1271,8 @@ int dpd_replica_set_state(dpd_ctx *c, int32_t r, const float *pos, const float *
   const int a = c->cur;
   HIP_TRY(c, dpd::launch_import(c->stream, p.nf, c->pos[a] + p.fo, c->vel[a] + p.fo,
                                 c->frc[a] + p.fo, dp, dv, df));
+  if (p.moving)
+    HIP_TRY(c, dpd::launch_import_walls(c->stream, p.nw, c->pos[a] + c->NF + p.wo, dp));
   drop_graphs(c);
   c->gen += 1;
   int rc = resort(c);
@@ -1307,8 +1409,12 @@ int dpd_autotune(dpd_ctx *c, int32_t steps, int32_t *shape_out, double *ms_out) 
     const uint64_t k0 = c->k;
     const int64_t steps0 = c->steps;
     const size_t np = 16 * (size_t)(c->NF + c->NW + 1), nv = 16 * (size_t)c->NF;
-    char *save = (char *)dalloc(c, np + 2 * nv + sizeof(Status));
+    const size_t nwv = c->moving ? 16 * (size_t)c->NW : 0;   // moving walls' velocities
+    char *save = (char *)dalloc(c, np + 2 * nv + sizeof(Status) + nwv);
     if (!save) return fail(c, DPD_E_NOMEM, "autotune snapshot allocation failed");
+    char *save_wv = save + np + 2 * nv + sizeof(Status);
+    if (nwv)
+      HIP_TRY(c, hipMemcpyAsync(save_wv, c->vt + c->NF, nwv, hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(save, c->pos[cur0], np, hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(save + np, c->vel[cur0], nv, hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(save + np + nv, c->frc[cur0], nv, hipMemcpyDeviceToDevice,
@@ -1334,6 +1440,14 @@ int dpd_autotune(dpd_ctx *c, int32_t steps, int32_t *shape_out, double *ms_out) 
       HIP_TRY(c, hipMemcpyAsync(c->status, save + np + 2 * nv, sizeof(Status),
                                 hipMemcpyDeviceToDevice, c->stream));
       HIP_TRY(c, hipMemcpyAsync(c->dk, &c->k, 8, hipMemcpyHostToDevice, c->stream));
+      if (nwv) {
+        // the walls moved during the trial: their saved positions (above) and
+        // velocities, and the cell list of that order
+        HIP_TRY(c, hipMemcpyAsync(c->vt + c->NF, save_wv, nwv, hipMemcpyDeviceToDevice,
+                                  c->stream));
+        const int wrc = wall_pass(c, c->stream, 0);
+        if (wrc && !rc) rc = wrc;
+      }
       if (!rc && (best < 0 || times[i] < times[best])) best = i;
     }
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -1369,6 +1483,14 @@ int dpd_set_params(dpd_ctx *c, int32_t r, const dpd_params *prm) {
   make_kparams(*prm, p, p.P);
   HIP_TRY(c, hipMemcpyAsync((char *)c->boxes + sizeof(Box) * (size_t)r + offsetof(Box, P), &p.P,
                             sizeof(KParams), hipMemcpyHostToDevice, c->stream));
+  // the integrate instance with the moving-wall and specular forms, if any
+  // box needs it (a captured step holds the instance it was captured with)
+  bool reflect = false;
+  for (const Replica &q : c->rep) reflect = reflect || q.P.reflect != 0;
+  if (reflect != c->reflect) {
+    c->reflect = reflect;
+    drop_graphs(c);
+  }
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->gen += 1;
   return DPD_OK;
@@ -1423,6 +1545,8 @@ int dpd_window_forward(dpd_ctx *c, int32_t steps, int32_t ckpt, int32_t axis, in
                        double *profile, int64_t *counts) {
   if (!c) return DPD_E_INVAL;
   if (c->R != 1) return fail(c, DPD_E_STATE, "the adjoint form needs a single-box context");
+  if (c->rep[0].P.reflect)
+    return fail(c, DPD_E_INVAL, "the adjoint form covers resting walls with bounce-back only");
   if (steps < 1 || ckpt < 1 || ckpt > steps)
     return fail(c, DPD_E_INVAL, "need steps >= 1 and 1 <= ckpt <= steps");
   if (axis < 0 || axis > 2 || nbins < 1 || nbins > dpd::kMaxBins)

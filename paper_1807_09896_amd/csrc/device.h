@@ -37,7 +37,14 @@ struct KParams {
   float dsig_rdt;       // d(sigma / sqrt(dt)) / d gamma = kBT / (sigma sqrt(dt)), 0 if sigma = 0
   uint32_t key0, key1;  // seed words
   uint32_t replica;
+  uint32_t reflect;     // kReflectMoving | kReflectSpecular
 };
+
+// How a fluid particle that crossed phi = 0 is reflected (Sec. II.C): the
+// box's walls move (the velocity of the solid comes from the nearest wall
+// particle), and specular instead of bounce-back reflection.
+constexpr uint32_t kReflectMoving = 1u;
+constexpr uint32_t kReflectSpecular = 2u;
 
 // One box of a batch: its geometry and parameters, and where its slices lie
 // in the concatenated arrays (a single box is a batch of one).
@@ -234,6 +241,29 @@ __device__ __forceinline__ T phi_interp(const T *__restrict__ grid, const KGeom 
   const T y0 = lerp_nc(e00, e01, L.t[1]);
   const T y1 = lerp_nc(e10, e11, L.t[1]);
   return lerp_nc(y0, y1, L.t[2]);
+}
+
+// Gradient of the trilinear interpolant at L (the derivative of the
+// 8-corner weights), in the grid's precision.
+template <typename T>
+__device__ __forceinline__ void phi_grad(const T *__restrict__ grid, const KGeom &G,
+                                         const GridLoc<T> &L, T &gx, T &gy, T &gz) {
+  const size_t nx = (size_t)G.ng[0], nxy = nx * (size_t)G.ng[1];
+  const T *r00 = grid + (size_t)L.i0[2] * nxy + (size_t)L.i0[1] * nx;
+  const T *r01 = grid + (size_t)L.i0[2] * nxy + (size_t)L.i1[1] * nx;
+  const T *r10 = grid + (size_t)L.i1[2] * nxy + (size_t)L.i0[1] * nx;
+  const T *r11 = grid + (size_t)L.i1[2] * nxy + (size_t)L.i1[1] * nx;
+  // corners c[z][y][x]
+  const T c000 = r00[L.i0[0]], c001 = r00[L.i1[0]], c010 = r01[L.i0[0]], c011 = r01[L.i1[0]];
+  const T c100 = r10[L.i0[0]], c101 = r10[L.i1[0]], c110 = r11[L.i0[0]], c111 = r11[L.i1[0]];
+  const T tx = L.t[0], ty = L.t[1], tz = L.t[2];
+  const T ux = (T)1 - tx, uy = (T)1 - ty, uz = (T)1 - tz;
+  gx = (uz * (uy * (c001 - c000) + ty * (c011 - c010)) +
+        tz * (uy * (c101 - c100) + ty * (c111 - c110))) * GridScale<T>::inv_h(G, 0);
+  gy = (uz * (ux * (c010 - c000) + tx * (c011 - c001)) +
+        tz * (ux * (c110 - c100) + tx * (c111 - c101))) * GridScale<T>::inv_h(G, 1);
+  gz = (uy * (ux * (c100 - c000) + tx * (c101 - c001)) +
+        ty * (ux * (c110 - c010) + tx * (c111 - c011))) * GridScale<T>::inv_h(G, 2);
 }
 
 template <typename T>

@@ -342,11 +342,50 @@ struct Moved {
   int cell;
 };
 
-template <typename T>
+// Velocity of the solid at a reflection at (x, y, z): that of the wall
+// particle nearest to the point among the walls of the 27 cells around its
+// cell, nearness by the FP32 pair-decision r2 (with the neighbour cell's
+// image shift), ties to the smaller gid; zero where there is none.  Walls
+// are at their start-of-step positions: entry NF + w of pos4 and vt4, wall
+// runs wcstart over the global cells (box offset co).
+__device__ __forceinline__ float4 wall_velocity(const KGeom &G, int co, int64_t NF, float x, float y,
+                                             float z, const int32_t *__restrict__ wcstart,
+                                             const float4 *__restrict__ pos4,
+                                             const float4 *__restrict__ vt4) {
+  int cx, cy, cz;
+  cell_index(G, x, y, z, cx, cy, cz);
+  float best = INFINITY;
+  uint32_t best_gid = 0;
+  int best_w = -1;
+  for (int code = 0; code < 27; ++code) {
+    const NCell nc = neighbour_cell(G, cx, cy, cz, code);
+    const float ax = sub_nc(x, nc.sx), ay = sub_nc(y, nc.sy), az = sub_nc(z, nc.sz);
+    const int w1 = wcstart[co + nc.c + 1];
+    for (int w = wcstart[co + nc.c]; w < w1; ++w) {
+      const float4 q = pos4[NF + w];
+      const float r2 = pair_r2(sub_nc(ax, q.x), sub_nc(ay, q.y), sub_nc(az, q.z));
+      const uint32_t g = __float_as_uint(q.w);
+      if (r2 < best || (r2 == best && g < best_gid)) {
+        best = r2;
+        best_gid = g;
+        best_w = w;
+      }
+    }
+  }
+  if (best_w < 0) return make_float4(0.f, 0.f, 0.f, 0.f);
+  return vt4[NF + best_w];
+}
+
+// REFLECT: compiled with the moving-wall and specular forms (the other
+// instances keep the register budget of plain bounce-back off resting walls).
+template <typename T, bool REFLECT>
 __device__ __forceinline__ Moved integrate_one(const KGeom &G, const KParams &P, float4 x,
                                                float4 v, float4 f,
                                                const uint32_t *__restrict__ bits, int use_mask,
-                                               const T *__restrict__ grid, Status *st) {
+                                               const T *__restrict__ grid, Status *st, int co,
+                                               int64_t NF, const int32_t *__restrict__ wcstart,
+                                               const float4 *__restrict__ pos4,
+                                               const float4 *__restrict__ vt4) {
   float xs = drift1(x.x, v.x, f.x, P.hdt, P.dt, G.L[0]);
   float ys = drift1(x.y, v.y, f.y, P.hdt, P.dt, G.L[1]);
   float zs = drift1(x.z, v.z, f.z, P.hdt, P.dt, G.L[2]);
@@ -379,9 +418,27 @@ __device__ __forceinline__ Moved integrate_one(const KGeom &G, const KParams &P,
       const T c1 = atanh(a1), c0 = atanh(a0);
       const T sfrac = c1 > (T)0 ? c1 / (c0 + c1) : (T)0;
       const float k2 = (float)((T)2 * sfrac * (T)P.dt);
-      float bx = wrap1(xs - k2 * v.x, G.L[0]);
-      float by = wrap1(ys - k2 * v.y, G.L[1]);
-      float bz = wrap1(zs - k2 * v.z, G.L[2]);
+      // the reversed part u of the velocity relative to the wall: all of it
+      // (bounce-back) or its component along the normal (specular)
+      float4 vw = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (REFLECT && (P.reflect & kReflectMoving))
+        vw = wall_velocity(G, co, NF, xs, ys, zs, wcstart, pos4, vt4);
+      float ux = v.x - vw.x, uy = v.y - vw.y, uz = v.z - vw.z;
+      if (REFLECT && (P.reflect & kReflectSpecular)) {
+        T gx, gy, gz;
+        phi_grad(grid, G, loc, gx, gy, gz);
+        const T gn = sqrt(gx * gx + gy * gy + gz * gz);
+        if (gn > (T)0) {
+          const T nx = gx / gn, ny = gy / gn, nz = gz / gn;
+          const T un = (T)ux * nx + (T)uy * ny + (T)uz * nz;
+          ux = (float)(un * nx);
+          uy = (float)(un * ny);
+          uz = (float)(un * nz);
+        }
+      }
+      float bx = wrap1(xs - k2 * ux, G.L[0]);
+      float by = wrap1(ys - k2 * uy, G.L[1]);
+      float bz = wrap1(zs - k2 * uz, G.L[2]);
       if (phi_at(grid, G, bx, by, bz) < (T)0) {
         bx = x.x;
         by = x.y;
@@ -395,7 +452,7 @@ __device__ __forceinline__ Moved integrate_one(const KGeom &G, const KParams &P,
       xs = bx;
       ys = by;
       zs = bz;
-      vt = make_float4(-v.x, -v.y, -v.z, 0.f);
+      vt = make_float4(v.x - 2.f * ux, v.y - 2.f * uy, v.z - 2.f * uz, 0.f);
     }
   }
   vt.w = __int_as_float(event);
@@ -434,13 +491,13 @@ __device__ __forceinline__ int wave_rank(const RunInfo &r, int base) {
 
 // One block per tile of up to PPT x kBlock particles of one box; each thread
 // advances PPT particles.
-template <typename T, int PPT>
+template <typename T, int PPT, bool REFLECT>
 __global__ __launch_bounds__(kBlock) void k_integrate(
     const Box *__restrict__ boxes, const Tile *__restrict__ tiles, int ntiles,
     float4 *__restrict__ pos4, const float4 *__restrict__ vel4, const float4 *__restrict__ frc4,
     float4 *__restrict__ vt4, int32_t *__restrict__ cell_of, int32_t *__restrict__ rank_of,
     int32_t *__restrict__ count, const uint32_t *__restrict__ bits_base, int use_mask,
-    const T *__restrict__ grid_base, Status *st) {
+    const T *__restrict__ grid_base, Status *st, int64_t NF, const int32_t *__restrict__ wcstart) {
   const int tid = xcd_block();
   if (tid >= ntiles) return;
   const Tile tile = tiles[tid];
@@ -472,7 +529,8 @@ __global__ __launch_bounds__(kBlock) void k_integrate(
   for (int u = 0; u < PPT; ++u) {
     m[u].cell = -1;
     if (a[u]) {
-      m[u] = integrate_one<T>(G, P, x[u], v[u], f[u], bits, use_mask, grid, st);
+      m[u] = integrate_one<T, REFLECT>(G, P, x[u], v[u], f[u], bits, use_mask, grid, st, co, NF,
+                                       wcstart, pos4, vt4);
       m[u].cell += co;
     }
     r[u] = wave_runs(m[u].cell);
@@ -491,6 +549,29 @@ __global__ __launch_bounds__(kBlock) void k_integrate(
       rank_of[p[u]] = k;
     }
   }
+}
+
+// Walls of a box whose solid moves translate with it: x += dt v per axis in
+// the decision form of the fluid drift with zero force, then the single-edge
+// wrap.  Reads walls_in, writes the moved copy to walls_out.
+__global__ void k_wall_move(const KGeom G, float hdt, float dt, int64_t nw,
+                            const float4 *__restrict__ walls_in, const float4 *__restrict__ vt_in,
+                            float4 *__restrict__ walls_out) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= nw) return;
+  const float4 x = walls_in[w], v = vt_in[w];
+  walls_out[w] = make_float4(drift1(x.x, v.x, 0.f, hdt, dt, G.L[0]),
+                             drift1(x.y, v.y, 0.f, hdt, dt, G.L[1]),
+                             drift1(x.z, v.z, 0.f, hdt, dt, G.L[2]), x.w);
+}
+
+// Wall positions from gid-ordered rows (gid in pos4[w].w).
+__global__ void k_import_walls(int64_t nw, float4 *__restrict__ walls, const float *__restrict__ pos) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= nw) return;
+  const float4 x = walls[w];
+  const size_t g = (size_t)__float_as_uint(x.w);
+  walls[w] = make_float4(pos[3 * g], pos[3 * g + 1], pos[3 * g + 2], x.w);
 }
 
 // Number of fluid particles whose grid cube is flagged (the particles that
@@ -822,6 +903,7 @@ __global__ void k_export(const KGeom G, int64_t n, const float4 *__restrict__ po
   }
   float4 v = make_float4(0.f, 0.f, 0.f, __int_as_float(0));
   if (!wall) v = vel4[s];
+  else if (vel4) v = make_float4(vel4[s].x, vel4[s].y, vel4[s].z, __int_as_float(0));
   if (vel) {
     vel[3 * g] = v.x;
     vel[3 * g + 1] = v.y;
@@ -933,6 +1015,19 @@ hipError_t launch_fill_walls(hipStream_t s, int64_t nw, int64_t nf, const int32_
   return hipGetLastError();
 }
 
+hipError_t launch_wall_move(hipStream_t s, const KGeom &G, float hdt, float dt, int64_t nw,
+                            const float4 *walls_in, const float4 *vt_in, float4 *walls_out) {
+  if (nw <= 0) return hipSuccess;
+  k_wall_move<<<grid_for(nw), kBlock, 0, s>>>(G, hdt, dt, nw, walls_in, vt_in, walls_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_import_walls(hipStream_t s, int64_t nw, float4 *walls, const float *pos) {
+  if (nw <= 0) return hipSuccess;
+  k_import_walls<<<grid_for(nw), kBlock, 0, s>>>(nw, walls, pos);
+  return hipGetLastError();
+}
+
 hipError_t launch_bump_k(hipStream_t s, unsigned long long *dk) {
   k_bump<<<1, 1, 0, s>>>(dk);
   return hipGetLastError();
@@ -1010,17 +1105,21 @@ hipError_t launch_integrate(hipStream_t s, int ppt, const Box *boxes, const Tile
                             int ntiles, float4 *pos4, const float4 *vel4, const float4 *frc4,
                             float4 *vt4, int32_t *cell_of, int32_t *rank_of, int32_t *count,
                             const uint32_t *bits, int use_mask, const void *grid, int grid_f64,
-                            Status *st) {
+                            Status *st, int64_t NF, const int32_t *wcstart, int reflect) {
   if (ntiles <= 0) return hipSuccess;
   const unsigned nb = (unsigned)(((ntiles + 7) / 8) * 8);
-#define DPD_INTEGRATE(T, K)                                                                     \
-  k_integrate<T, K><<<nb, kBlock, 0, s>>>(boxes, tiles, ntiles, pos4, vel4, frc4, vt4, cell_of, \
-                                          rank_of, count, bits, use_mask, (const T *)grid, st)
+#define DPD_INTEGRATE(T, K, R)                                                                   \
+  k_integrate<T, K, R><<<nb, kBlock, 0, s>>>(boxes, tiles, ntiles, pos4, vel4, frc4, vt4,       \
+                                             cell_of, rank_of, count, bits, use_mask,           \
+                                             (const T *)grid, st, NF, wcstart)
+#define DPD_INTEGRATE_T(T, K) \
+  if (reflect) DPD_INTEGRATE(T, K, true); else DPD_INTEGRATE(T, K, false)
   if (grid_f64) {
-    if (ppt == 1) DPD_INTEGRATE(double, 1); else DPD_INTEGRATE(double, 2);
+    if (ppt == 1) { DPD_INTEGRATE_T(double, 1); } else { DPD_INTEGRATE_T(double, 2); }
   } else {
-    if (ppt == 1) DPD_INTEGRATE(float, 1); else DPD_INTEGRATE(float, 2);
+    if (ppt == 1) { DPD_INTEGRATE_T(float, 1); } else { DPD_INTEGRATE_T(float, 2); }
   }
+#undef DPD_INTEGRATE_T
 #undef DPD_INTEGRATE
   return hipGetLastError();
 }

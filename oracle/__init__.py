@@ -45,7 +45,8 @@ class Params(C.Structure):
     _fields_ = [("a", (C.c_double * 2) * 2), ("gamma", C.c_double), ("kBT", C.c_double),
                 ("rc", C.c_double), ("dt", C.c_double), ("lam", C.c_double),
                 ("g", C.c_double * 3), ("seed", C.c_uint64), ("replica", C.c_uint32),
-                ("specular", C.c_int32)]
+                ("specular", C.c_int32), ("sph", C.c_int32), ("sr", (C.c_double * 2) * 2),
+                ("sa", (C.c_double * 2) * 2), ("r0r", C.c_double), ("r0a", C.c_double)]
 
 
 _lib = None
@@ -73,6 +74,10 @@ def lib():
         L.orc_phi_decide64.restype = C.c_double
         L.orc_phi64.argtypes = [P, P, P]
         L.orc_phi64.restype = C.c_double
+        L.orc_sph_w.argtypes = [C.c_double, C.c_double]
+        L.orc_sph_w.restype = C.c_double
+        L.orc_sph_dw.argtypes = [C.c_double, C.c_double]
+        L.orc_sph_dw.restype = C.c_double
         L.orc_forces.argtypes = [P, P, C.c_int64, P, P, P, P, P, C.c_uint64, C.c_int, C.c_int, P]
         L.orc_forces.restype = C.c_int
         L.orc_cells_of.argtypes = [P, C.c_int64, P, P]
@@ -124,6 +129,16 @@ def pairs_random(seed, gi, gj, k, replica=0):
     lib().orc_pairs_random(int(seed) & 0xFFFFFFFFFFFFFFFF, _p(gi), _p(gj), n, int(k),
                            int(replica), _p(words), _p(xi_out))
     return words, xi_out
+
+
+def sph_w(r, r0):
+    """Smoothing function of Eq. 23 (3-D) with support r0."""
+    return lib().orc_sph_w(float(r), float(r0))
+
+
+def sph_dw(r, r0):
+    """dW/dr of Eq. 23 (3-D) with support r0."""
+    return lib().orc_sph_dw(float(r), float(r0))
 
 
 def cell_counts(L, rc):
@@ -199,6 +214,16 @@ class Oracle:
         cp.seed = int(p["seed"]) & 0xFFFFFFFFFFFFFFFF
         cp.replica = int(p["replica"])
         cp.specular = 1 if p.get("specular", False) else 0
+        sph = p.get("sph")
+        if sph:
+            # Eq. 22-24: strengths by type and the two ranges
+            cp.sph = 1
+            for i in range(2):
+                for j in range(2):
+                    cp.sr[i][j] = float(sph["sr"][i][j])
+                    cp.sa[i][j] = float(sph["sa"][i][j])
+            cp.r0r = float(sph["r0r"])
+            cp.r0a = float(sph["r0a"])
         return cp
 
     def set_params(self, **kw):
@@ -265,6 +290,8 @@ class Oracle:
         n, T = self.n, int(T)
         if self.params.get("specular", False) or np.any(self.v[self.type != 0] != 0.0):
             raise ValueError("the window covers resting walls with bounce-back only")
+        if self.params.get("sph"):
+            raise ValueError("the window covers the a w conservative force only")
         record = logs is None
         if record:
             logs = dict(ev=np.zeros((T, n), np.int32), xs=np.zeros((T, n, 3), np.float32),

@@ -37,6 +37,10 @@
  *     and in the Eq. 17 displacement; |grad Phi| = 0 falls back to
  *     bounce-back
  *   - atanh arguments clamped to [0, 1 - 2^-20]
+ *   - the attractive-repulsive force of Eq. 22-24 replaces a w when enabled:
+ *     the conservative force is -dE/dr along r_i - r_j (Eq. 24 prints the
+ *     derivative without the minus sign, which would make the repulsive
+ *     term attract); dissipative and random forces keep w = 1 - r/rc
  *   - mass 1, box periodic in all three axes, phi grid periodic and
  *     node-centred, trilinear interpolation ("linear interpolation", Sec. II.C)
  */
@@ -151,6 +155,10 @@ typedef struct {
     uint64_t seed;
     uint32_t replica;
     int32_t specular;   /* 1: specular reflection, 0: bounce-back */
+    int32_t sph;        /* 1: conservative force of Eq. 22-24 instead of a w */
+    double sr[2][2];    /* S^r_ij: repulsive strengths by type */
+    double sa[2][2];    /* S^a_ij: attractive strengths by type */
+    double r0r, r0a;    /* their ranges r0^r, r0^a (support of W) */
 } orc_params;
 
 static int orc_mod(int a, int n)
@@ -301,6 +309,34 @@ double orc_phi64(const orc_geom *G, const double x[3], double grad[3])
  *   F_ij = [ a_ij w - gamma w^2 (e . (vt_i - vt_j)) + sigma w xi_ij / sqrt(dt) ] e
  * Zero for r >= rc (Eq. 5) and for r = 0.
  * ---------------------------------------------------------------------- */
+/* ------------------------------------------------------------------------
+ * Smoothing function of Eq. 23 in 3-D (alpha_3 = 1/pi) with support r0:
+ * h = r0/2, v = r/h,
+ *   W = (1/(pi h^3)) {1 - 3/2 v^2 + 3/4 v^3 (v < 1); 1/4 (2 - v)^3 (v < 2); 0}
+ * and its derivative dW/dr.
+ * ---------------------------------------------------------------------- */
+double orc_sph_w(double r, double r0)
+{
+    const double h = 0.5 * r0, v = r / h, c = 1.0 / (ORC_PI * h * h * h);
+    if (v < 1.0) return c * (1.0 - 1.5 * v * v + 0.75 * v * v * v);
+    if (v < 2.0) return c * 0.25 * (2.0 - v) * (2.0 - v) * (2.0 - v);
+    return 0.0;
+}
+
+double orc_sph_dw(double r, double r0)
+{
+    const double h = 0.5 * r0, v = r / h, c = 1.0 / (ORC_PI * h * h * h * h);
+    if (v < 1.0) return c * (-3.0 * v + 2.25 * v * v);
+    if (v < 2.0) return c * (-0.75 * (2.0 - v) * (2.0 - v));
+    return 0.0;
+}
+
+/* Pair energy of Eq. 22: S^r W(r, r0^r) - S^a W(r, r0^a). */
+static double sph_energy(const orc_params *P, double r, int ti, int tj)
+{
+    return P->sr[ti][tj] * orc_sph_w(r, P->r0r) - P->sa[ti][tj] * orc_sph_w(r, P->r0a);
+}
+
 static void pair_force(const orc_params *P, double sigma, double inv_sqrt_dt,
                        const double d[3], const double dv[3], int ti, int tj,
                        uint32_t gi, uint32_t gj, uint64_t k, int noclamp, double out[3])
@@ -314,7 +350,11 @@ static void pair_force(const orc_params *P, double sigma, double inv_sqrt_dt,
     double e[3] = {d[0] / r, d[1] / r, d[2] / r};
     double edv = e[0] * dv[0] + e[1] * dv[1] + e[2] * dv[2];
     double xi = orc_xi(P->seed, gi, gj, k, P->replica);
-    double mag = P->a[ti][tj] * w - P->gamma * w * w * edv + sigma * w * xi * inv_sqrt_dt;
+    /* conservative part: a w (Eq. 4), or -dE/dr of Eq. 22 (Eq. 24) */
+    double fc = P->a[ti][tj] * w;
+    if (P->sph)
+        fc = -(P->sr[ti][tj] * orc_sph_dw(r, P->r0r) - P->sa[ti][tj] * orc_sph_dw(r, P->r0a));
+    double mag = fc - P->gamma * w * w * edv + sigma * w * xi * inv_sqrt_dt;
     out[0] = mag * e[0];
     out[1] = mag * e[1];
     out[2] = mag * e[2];
@@ -744,8 +784,8 @@ int orc_step(const orc_geom *G, const orc_params *P, int64_t n, double *r,
 }
 
 /* Conservative potential energy sum_{pairs} a_ij rc/2 (1 - r/rc)^2 (the
- * potential of Eq. 4-5), brute force with minimum image; wall-wall pairs
- * excluded (they are frozen and never interact). */
+ * potential of Eq. 4-5), or the energy of Eq. 22, brute force with minimum
+ * image; wall-wall pairs excluded (they are frozen and never interact). */
 double orc_potential(const orc_geom *G, const orc_params *P, int64_t n,
                      const double *r, const int32_t *type)
 {
@@ -762,8 +802,12 @@ double orc_potential(const orc_geom *G, const orc_params *P, int64_t n,
             }
             double rr = sqrt(d2);
             if (rr < P->rc) {
-                double w = 1.0 - rr / P->rc;
-                U += 0.5 * P->a[type[i]][type[j]] * P->rc * w * w;
+                if (P->sph) {
+                    U += sph_energy(P, rr, type[i], type[j]);
+                } else {
+                    double w = 1.0 - rr / P->rc;
+                    U += 0.5 * P->a[type[i]][type[j]] * P->rc * w * w;
+                }
             }
         }
     }

@@ -21,7 +21,7 @@ import math
 import numpy as np
 
 __all__ = [
-    "System", "slab_system", "couette_system", "sinusoid_cylinder_system", "porous_system",
+    "System", "slab_system", "couette_system", "sph_force", "sinusoid_cylinder_system", "porous_system",
     "sinusoid_slit_system", "replica_systems", "tiny_slab_system",
     "corner_minmax", "maxwell_velocities", "bulk_system",
 ]
@@ -72,6 +72,16 @@ def default_params(a_ff=25.0, a_fs=25.0, gamma=4.5, kBT=1.0, rc=1.0, dt=0.01,
 # ----------------------------------------------------------------------------
 # geometry helpers
 # ----------------------------------------------------------------------------
+
+def sph_force(s_ff_r=37.5, s_ff_a=18.75, fs_factor=2.0, r0r=0.73, r0a=1.0):
+    """Parameters of the attractive-repulsive conservative force of Eq. 22-24
+    (Sec. III.C's values: S^r_ff = 37.5, S^a_ff = 18.75, ranges 0.73 and 1.0,
+    fluid-solid strengths `fs_factor` times the fluid-fluid ones), for
+    params["sph"]."""
+    sr = [[s_ff_r, fs_factor * s_ff_r], [fs_factor * s_ff_r, fs_factor * s_ff_r]]
+    sa = [[s_ff_a, fs_factor * s_ff_a], [fs_factor * s_ff_a, fs_factor * s_ff_a]]
+    return dict(sr=sr, sa=sa, r0r=float(r0r), r0a=float(r0a))
+
 
 def _periodic_abs(x, period):
     x = np.mod(x, period)

@@ -96,6 +96,9 @@ def main():
     ap.add_argument("--replicas", type=int, default=256)
     ap.add_argument("--walls-steps", type=int, default=200,
                     help="steps of the moving-wall leg (plane Couette channel); 0 skips it")
+    ap.add_argument("--sph-steps", type=int, default=100,
+                    help="steps of the attractive-repulsive force leg (the same workload "
+                         "with the Eq. 22-24 force); 0 skips it")
     ap.add_argument("--adjoint-reps", type=int, default=3,
                     help="timed repetitions of the 200-step adjoint window (0 skips the leg)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -175,6 +178,11 @@ def main():
         if tr.get("kernel_source_hash") == kernel_source_hash():
             traffic = tr.get("bytes_per_launch")
 
+    sph = None
+    if args.sph_steps > 0:
+        sim.close()
+        sph = sph_leg(dpd, system, args.sph_steps, args.timing_steps, force_ms, ms_per_step)
+
     batch = None
     if args.batch_steps > 0:
         sim.close()
@@ -232,9 +240,45 @@ def main():
         "batch": batch,
         "adjoint": adjoint,
         "moving_walls": walls,
+        "sph_force": sph,
     }
     print(json.dumps(out), flush=True)
     sim.close()
+
+
+def sph_leg(dpd, system, steps, timing_steps, force_ms, ms_per_step):
+    """The attractive-repulsive conservative force of Eq. 22-24 on the same
+    workload (Sec. IV's fluid: kBT = 0.5, the paper's strengths and ranges,
+    fluid-solid strengths twice the fluid-fluid ones, dt = 0.005): whole
+    step and pair-force launch against the linear force's."""
+    import dataclasses
+    import torch
+    import workloads
+    p = dict(system.params, sph=workloads.sph_force(), kBT=0.5, dt=0.005)
+    s = dataclasses.replace(system, params=p)
+    sim = dpd.Simulation(s)
+    sim.step(20)
+    sim.sync()
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - ta
+    sim.kernel_times(1)
+    sim.step(timing_steps)
+    kt = sim.kernel_times(0)
+    c = sim.counters()
+    sim.close()
+    f_ms, f_n = kt["pair_force"]
+    f_ms /= max(f_n, 1)
+    log("sph leg: %.4f ms/step, %.4e particle-steps/s, pair_force %.4f ms/launch (linear force %.4f)"
+        % (dt * 1e3 / steps, s.n * steps / dt, f_ms, force_ms))
+    return {"workload": system.name, "particles": s.n, "steps": steps,
+            "ms_per_step": dt * 1e3 / steps, "value": s.n * steps / dt,
+            "unit": "particle-steps/s", "pair_force_ms": f_ms,
+            "pair_force_ms_linear": force_ms, "step_ms_linear": ms_per_step,
+            "unstable": c["unstable"]}
 
 
 def batch_leg(dpd, replicas, steps):

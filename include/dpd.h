@@ -51,12 +51,14 @@ enum {
 enum {
     DPD_FLAG_NO_MASK = 1,  /* test phi for every particle, not only in cells
                               near the interface (results are identical) */
-    DPD_FLAG_SPECULAR = 2  /* specular reflection (Sec. I): only the component
+    DPD_FLAG_SPECULAR = 2, /* specular reflection (Sec. I): only the component
                               of the velocity relative to the wall along the
                               normal grad phi / |grad phi| at the crossing
                               position is reversed, in the new velocity and
                               in the displacement of Eq. 17; without it,
                               bounce-back (Sec. II.C) reverses all of it */
+    DPD_FLAG_SPH = 4       /* conservative force of Eq. 22-24 (sr, sa, r0r,
+                              r0a) instead of a_ij w */
 };
 
 typedef struct dpd_ctx dpd_ctx;
@@ -119,7 +121,14 @@ typedef struct {
  *   g       body force per fluid particle
  *   seed    64-bit key of the random numbers
  *   replica replica id entering the random-number counter (< 65536)
- *   flags   DPD_FLAG_* */
+ *   flags   DPD_FLAG_*
+ *   sr, sa  with DPD_FLAG_SPH: 2 x 2 strengths S^r_ij, S^a_ij by type of the
+ *           attractive-repulsive energy of Eq. 22, E = S^r W(r, r0r) -
+ *           S^a W(r, r0a), W the cubic spline of Eq. 23 in 3-D with support
+ *           r0 (h = r0/2, alpha_3 = 1/pi); the conservative pair force is
+ *           -dE/dr along r_i - r_j (Eq. 24), replacing a_ij w; dissipative
+ *           and random forces are unchanged.  Symmetric like a.
+ *   r0r, r0a  ranges of the repulsive and attractive parts, 0 < r0 <= rc */
 typedef struct {
     double a[4];
     double gamma;
@@ -131,6 +140,10 @@ typedef struct {
     uint64_t seed;
     uint32_t replica;
     int32_t flags;
+    double sr[4];
+    double sa[4];
+    double r0r;
+    double r0a;
 } dpd_params;
 
 /* Optional device allocator (e.g. PyTorch's caching allocator through the
@@ -296,8 +309,9 @@ int dpd_set_phi(dpd_ctx *ctx, int32_t r, const void *data, int32_t on_device);
  * profile (device, nbins float64) and counts (device, nbins int64: N_b) may
  * be NULL.  A checkpoint of the fluid state is stored every ckpt steps
  * (1 <= ckpt <= steps, nbins <= 1024); the context ends at the window's last
- * state.  DPD_E_STATE for a batch context; DPD_E_INVAL for moving walls or
- * DPD_FLAG_SPECULAR (the adjoint covers resting walls with bounce-back).
+ * state.  DPD_E_STATE for a batch context; DPD_E_INVAL for moving walls,
+ * DPD_FLAG_SPECULAR or DPD_FLAG_SPH (the adjoint covers the a_ij w force and
+ * resting walls with bounce-back).
  *
  * dpd_backward: gradients of a loss L(profile) from dL_dprofile (device,
  * nbins float64) by the hand-written adjoint of every step of the window

@@ -25,6 +25,7 @@ DPD_E_UNSTABLE = -4
 DPD_E_STATE = -5
 DPD_FLAG_NO_MASK = 1
 DPD_FLAG_SPECULAR = 2
+DPD_FLAG_SPH = 4
 DPD_NUM_KERNELS = 8
 
 _ERRNAMES = {DPD_E_INVAL: "DPD_E_INVAL", DPD_E_NOMEM: "DPD_E_NOMEM",
@@ -65,7 +66,8 @@ class dpd_params(C.Structure):
     _fields_ = [("a", C.c_double * 4), ("gamma", C.c_double), ("kBT", C.c_double),
                 ("rc", C.c_double), ("dt", C.c_double), ("lambda_", C.c_double),
                 ("g", C.c_double * 3), ("seed", C.c_uint64), ("replica", C.c_uint32),
-                ("flags", C.c_int32)]
+                ("flags", C.c_int32), ("sr", C.c_double * 4), ("sa", C.c_double * 4),
+                ("r0r", C.c_double), ("r0a", C.c_double)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
@@ -227,15 +229,24 @@ def _marshal_box(L, pos, vel, type_, gid, params, phi, h, flags, keep):
 
 def _params_struct(params, flags=0):
     """dpd_params from a parameter dict; a true params["specular"] adds
-    DPD_FLAG_SPECULAR to flags."""
+    DPD_FLAG_SPECULAR to flags, a params["sph"] dict (sr, sa, r0r, r0a)
+    DPD_FLAG_SPH with its fields."""
     a = params["a"]
     if params.get("specular", False):
         flags = int(flags) | DPD_FLAG_SPECULAR
+    sph = params.get("sph")
+    sr = sa = ((0.0, 0.0), (0.0, 0.0))
+    r0r = r0a = 0.0
+    if sph:
+        flags = int(flags) | DPD_FLAG_SPH
+        sr, sa, r0r, r0a = sph["sr"], sph["sa"], sph["r0r"], sph["r0a"]
     return dpd_params((C.c_double * 4)(a[0][0], a[0][1], a[1][0], a[1][1]), params["gamma"],
                       params["kBT"], params["rc"], params["dt"], params["lam"],
                       (C.c_double * 3)(*params["g"]),
                       int(params["seed"]) & 0xFFFFFFFFFFFFFFFF, int(params["replica"]),
-                      int(flags))
+                      int(flags), (C.c_double * 4)(sr[0][0], sr[0][1], sr[1][0], sr[1][1]),
+                      (C.c_double * 4)(sa[0][0], sa[0][1], sa[1][0], sa[1][1]), float(r0r),
+                      float(r0a))
 
 
 def dpd_create(L, pos, vel, type_, gid, params, phi, h, stream=None, use_torch_allocator=True,

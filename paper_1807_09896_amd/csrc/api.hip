@@ -111,6 +111,7 @@ struct dpd_ctx {
   // cells, ranks, per-cell counts)
   bool moving = false;
   bool reflect = false;   // some box has moving walls or specular reflection
+  bool sph = false;       // some box uses the attractive-repulsive conservative force
   float4 *wtmp = nullptr, *wvtmp = nullptr;
   int32_t *wcell_tmp = nullptr, *wrank = nullptr, *wcount = nullptr;
   int32_t *start_all = nullptr; // start of each cell's merged run
@@ -370,7 +371,7 @@ int force_pass(dpd_ctx *c, hipStream_t s, int init) {
                                      (int32_t)(c->NF + c->NW), (int32_t)c->NCELL, init, c->pos[a],
                                      c->vt, c->vel[a],
                                      c->frc[a], c->idx, c->idx_all, c->start_all, c->pos[b],
-                                     c->vel[b], c->frc[b], c->dk, c->status);
+                                     c->vel[b], c->frc[b], c->dk, c->status, c->sph ? 1 : 0);
           }));
   c->cur = b;
   return DPD_OK;
@@ -541,6 +542,22 @@ void make_kparams(const dpd_params &P, const Replica &R, KParams &K) {
   K.replica = P.replica;
   K.reflect = (R.moving ? dpd::kReflectMoving : 0u) |
               ((P.flags & DPD_FLAG_SPECULAR) ? dpd::kReflectSpecular : 0u);
+  // Eq. 22-24: F_c = -cr P'(r / h_r) + ca P'(r / h_a), with c = S / (pi h^4)
+  // and P' the derivative of Eq. 23's polynomial in v = r / h
+  K.sph = (P.flags & DPD_FLAG_SPH) ? 1u : 0u;
+  K.cr_ff = K.cr_fw = K.ca_ff = K.ca_fw = 0.f;
+  K.inv_hr = K.inv_ha = 0.f;
+  if (K.sph) {
+    const double pi = 3.14159265358979323846;
+    const double hr = 0.5 * P.r0r, ha = 0.5 * P.r0a;
+    const double qr = 1.0 / (pi * hr * hr * hr * hr), qa = 1.0 / (pi * ha * ha * ha * ha);
+    K.cr_ff = (float)(P.sr[0] * qr);
+    K.cr_fw = (float)(P.sr[1] * qr);
+    K.ca_ff = (float)(P.sa[0] * qa);
+    K.ca_fw = (float)(P.sa[1] * qa);
+    K.inv_hr = (float)(1.0 / hr);
+    K.inv_ha = (float)(1.0 / ha);
+  }
 }
 
 // Checks of dpd_params that need no particles.
@@ -556,6 +573,13 @@ std::string check_params(const dpd_params &P) {
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(P.g[a])) return "g must be finite";
   if (P.replica >= 65536u) return "replica must be < 65536";
+  if (P.flags & DPD_FLAG_SPH) {
+    for (int a = 0; a < 4; ++a)
+      if (!std::isfinite(P.sr[a]) || !std::isfinite(P.sa[a])) return "sr, sa must be finite";
+    if (P.sr[1] != P.sr[2] || P.sa[1] != P.sa[2]) return "sr, sa must be symmetric";
+    if (!(P.r0r > 0 && P.r0r <= P.rc && P.r0a > 0 && P.r0a <= P.rc))
+      return "r0r and r0a must lie in (0, rc]";
+  }
   return "";
 }
 
@@ -754,6 +778,7 @@ int create_impl(int32_t nbox, const dpd_box *boxes, const dpd_particles *parts,
   for (const Replica &p : c->rep) {
     c->moving = c->moving || p.moving;
     c->reflect = c->reflect || p.P.reflect != 0;
+    c->sph = c->sph || p.P.sph != 0;
   }
   if (c->moving) {
     c->wtmp = (float4 *)dalloc(c, 16 * nw);
@@ -1485,10 +1510,15 @@ int dpd_set_params(dpd_ctx *c, int32_t r, const dpd_params *prm) {
                             sizeof(KParams), hipMemcpyHostToDevice, c->stream));
   // the integrate instance with the moving-wall and specular forms, if any
   // box needs it (a captured step holds the instance it was captured with)
-  bool reflect = false;
-  for (const Replica &q : c->rep) reflect = reflect || q.P.reflect != 0;
-  if (reflect != c->reflect) {
+  // and the force instance with the conservative force of Eq. 22-24
+  bool reflect = false, sph = false;
+  for (const Replica &q : c->rep) {
+    reflect = reflect || q.P.reflect != 0;
+    sph = sph || q.P.sph != 0;
+  }
+  if (reflect != c->reflect || sph != c->sph) {
     c->reflect = reflect;
+    c->sph = sph;
     drop_graphs(c);
   }
   HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -1547,6 +1577,8 @@ int dpd_window_forward(dpd_ctx *c, int32_t steps, int32_t ckpt, int32_t axis, in
   if (c->R != 1) return fail(c, DPD_E_STATE, "the adjoint form needs a single-box context");
   if (c->rep[0].P.reflect)
     return fail(c, DPD_E_INVAL, "the adjoint form covers resting walls with bounce-back only");
+  if (c->rep[0].P.sph)
+    return fail(c, DPD_E_INVAL, "the adjoint form covers the linear conservative force only");
   if (steps < 1 || ckpt < 1 || ckpt > steps)
     return fail(c, DPD_E_INVAL, "need steps >= 1 and 1 <= ckpt <= steps");
   if (axis < 0 || axis > 2 || nbins < 1 || nbins > dpd::kMaxBins)

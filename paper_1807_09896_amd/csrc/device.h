@@ -38,7 +38,19 @@ struct KParams {
   uint32_t key0, key1;  // seed words
   uint32_t replica;
   uint32_t reflect;     // kReflectMoving | kReflectSpecular
+  // conservative force of Eq. 22-24 (sph = 1): -cr P'(r inv_hr) + ca P'(r inv_ha)
+  // by pair type, c = S / (pi h^4)
+  uint32_t sph;
+  float cr_ff, cr_fw, ca_ff, ca_fw;
+  float inv_hr, inv_ha;
 };
+
+// Derivative of Eq. 23's cubic spline in v = r / h (3-D), without the
+// prefactor: -3 v + 9/4 v^2 (v < 1), -3/4 (2 - v)^2 (v < 2), 0.
+__device__ __forceinline__ float spline_dp(float v) {
+  const float u = 2.0f - v;
+  return v < 1.0f ? v * (2.25f * v - 3.0f) : (v < 2.0f ? -0.75f * u * u : 0.0f);
+}
 
 // How a fluid particle that crossed phi = 0 is reflected (Sec. II.C): the
 // box's walls move (the velocity of the solid comes from the nearest wall

@@ -112,7 +112,7 @@ hipError_t launch_force(hipStream_t s, int block, const Box *boxes, const Tile *
                         const float4 *frc4, const int32_t *idx, const int32_t *idx_all,
                         const int32_t *start_all,
                         float4 *pos_out, float4 *vel_out, float4 *frc_out,
-                        const unsigned long long *dk, Status *st);
+                        const unsigned long long *dk, Status *st, int sph);
 
 // *dk += 1 (the force evaluation index, on the device).
 hipError_t launch_bump_k(hipStream_t s, unsigned long long *dk);

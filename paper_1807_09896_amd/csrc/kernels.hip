@@ -622,8 +622,11 @@ struct Acc {
   float x, y, z;
 };
 
+// SPH: compiled with the conservative force of Eq. 22-24 for boxes that use
+// it (wall: j is a wall particle, selecting the fluid-wall strengths).
+template <bool SPH>
 __device__ __forceinline__ void add_pair(Acc &acc, float dx, float dy, float dz, float r2,
-                                         float dvx, float dvy, float dvz, float a,
+                                         float dvx, float dvy, float dvz, float a, bool wall,
                                          const KParams &P, uint32_t gi, uint32_t gj,
                                          uint32_t klo, uint32_t khi) {
   const float rinv = rsqrtf(r2);
@@ -632,7 +635,14 @@ __device__ __forceinline__ void add_pair(Acc &acc, float dx, float dy, float dz,
   const float ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
   const float edv = ex * dvx + ey * dvy + ez * dvz;
   const float xi = pair_gauss(gi, gj, klo, khi, P.key0, P.key1);
-  const float mag = w * (a - P.gamma * w * edv + P.sigma_rdt * xi);
+  float mag;
+  if (SPH && P.sph) {
+    const float cr = wall ? P.cr_fw : P.cr_ff, ca = wall ? P.ca_fw : P.ca_ff;
+    const float fc = ca * spline_dp(r * P.inv_ha) - cr * spline_dp(r * P.inv_hr);
+    mag = fc + w * (P.sigma_rdt * xi - P.gamma * w * edv);
+  } else {
+    mag = w * (a - P.gamma * w * edv + P.sigma_rdt * xi);
+  }
   acc.x += mag * ex;
   acc.y += mag * ey;
   acc.z += mag * ez;
@@ -640,7 +650,7 @@ __device__ __forceinline__ void add_pair(Acc &acc, float dx, float dy, float dz,
 
 // Eight wavefronts per SIMD (at most 64 VGPRs): the walk waits on dependent
 // loads, and more wavefronts in flight hide more of that wait.
-template <bool INIT, int BS>
+template <bool INIT, int BS, bool SPH>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_force(
     const Box *__restrict__ boxes, const Tile *__restrict__ tiles, int ntiles, int64_t NF,
     int32_t pad, int32_t ncell_all, const float4 *__restrict__ pos4,
@@ -695,9 +705,10 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_
       const float dy = min_image(pi.y - pj.y, G.L[1]);
       const float dz = min_image(pi.z - pj.z, G.L[2]);
       const float r2 = dx * dx + dy * dy + dz * dz;
-      const float a = (int64_t)j < NF ? P.a_ff : P.a_fw;
-      add_pair(acc, dx, dy, dz, r2, vti.x - vtj.x, vti.y - vtj.y, vti.z - vtj.z, a, P, gi,
-               __float_as_uint(pj.w), klo, khi);
+      const bool wall = (int64_t)j >= NF;
+      const float a = wall ? P.a_fw : P.a_ff;
+      add_pair<SPH>(acc, dx, dy, dz, r2, vti.x - vtj.x, vti.y - vtj.y, vti.z - vtj.z, a, wall, P,
+                    gi, __float_as_uint(pj.w), klo, khi);
       j = jn;
       pj = pjn;
       vtj = vtjn;
@@ -1130,17 +1141,21 @@ hipError_t launch_force(hipStream_t s, int block, const Box *boxes, const Tile *
                         const float4 *vt4, const float4 *vel4, const float4 *frc4,
                         const int32_t *idx, const int32_t *idx_all, const int32_t *start_all,
                         float4 *pos_out, float4 *vel_out, float4 *frc_out,
-                        const unsigned long long *dk, Status *st) {
+                        const unsigned long long *dk, Status *st, int sph) {
   if (ntiles <= 0) return hipSuccess;
   const unsigned nb = (unsigned)(((ntiles + 7) / 8) * 8);
-#define DPD_FORCE(I, BS)                                                                        \
-  k_force<I, BS><<<nb, BS, 0, s>>>(boxes, tiles, ntiles, NF, pad, ncell_all, pos4, vt4, vel4,   \
-                                   frc4, idx, idx_all, start_all, pos_out, vel_out, frc_out, dk, st)
+#define DPD_FORCE(I, BS, S)                                                                      \
+  k_force<I, BS, S><<<nb, BS, 0, s>>>(boxes, tiles, ntiles, NF, pad, ncell_all, pos4, vt4, vel4, \
+                                      frc4, idx, idx_all, start_all, pos_out, vel_out, frc_out,  \
+                                      dk, st)
+#define DPD_FORCE_S(I, BS) \
+  if (sph) DPD_FORCE(I, BS, true); else DPD_FORCE(I, BS, false)
   if (block == 128) {
-    if (init) DPD_FORCE(true, 128); else DPD_FORCE(false, 128);
+    if (init) { DPD_FORCE_S(true, 128); } else { DPD_FORCE_S(false, 128); }
   } else {
-    if (init) DPD_FORCE(true, 256); else DPD_FORCE(false, 256);
+    if (init) { DPD_FORCE_S(true, 256); } else { DPD_FORCE_S(false, 256); }
   }
+#undef DPD_FORCE_S
 #undef DPD_FORCE
   return hipGetLastError();
 }

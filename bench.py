@@ -99,6 +99,9 @@ def main():
     ap.add_argument("--sph-steps", type=int, default=100,
                     help="steps of the attractive-repulsive force leg (the same workload "
                          "with the Eq. 22-24 force); 0 skips it")
+    ap.add_argument("--phase-field-iters", type=int, default=200,
+                    help="relaxation steps of the phase-field leg (Eq. 15 on the workload's "
+                         "grid from its step function); 0 skips it")
     ap.add_argument("--adjoint-reps", type=int, default=3,
                     help="timed repetitions of the 200-step adjoint window (0 skips the leg)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -178,6 +181,10 @@ def main():
         if tr.get("kernel_source_hash") == kernel_source_hash():
             traffic = tr.get("bytes_per_launch")
 
+    pfield = None
+    if args.phase_field_iters > 0:
+        pfield = phase_field_leg(dpd, system, args.phase_field_iters)
+
     sph = None
     if args.sph_steps > 0:
         sim.close()
@@ -241,9 +248,54 @@ def main():
         "adjoint": adjoint,
         "moving_walls": walls,
         "sph_force": sph,
+        "phase_field": pfield,
     }
     print(json.dumps(out), flush=True)
     sim.close()
+
+
+def phase_field_leg(dpd, system, iters):
+    """Phase-field relaxation (Sec. II.B, Eq. 15) of the workload's grid from
+    its step function (-1 solid, +1 fluid) with sqrt(2) eps = 0.5, the
+    interface width of the workload's tanh field, and dtau at half the
+    explicit bound.  One launch per pseudo-time step; the launches are timed
+    with HIP events on the stream they run on.  Algorithmic traffic: one
+    read and one write of every node per step."""
+    import numpy as np
+    import torch
+    t0 = time.time()
+    phi = torch.from_numpy(system.phi).to("cuda")
+    phi = torch.where(phi > 0, 1.0, -1.0).to(phi.dtype).contiguous()
+    work = torch.empty(phi.numel() + 1, dtype=phi.dtype, device="cuda")
+    h = [float(x) for x in system.h]
+    eps = 0.5 / math.sqrt(2.0)
+    dtau = 0.5 / (2.0 * sum((eps / x) ** 2 for x in h))
+    es = phi.element_size()
+    dpd.dpd_phi_relax(phi, work, h, eps, dtau, 2, residual=False)
+    torch.cuda.synchronize()
+    iters -= iters % 2
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    dpd.dpd_phi_relax(phi, work, h, eps, dtau, iters, residual=False)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / iters
+    res = dpd.dpd_phi_relax(phi, work, h, eps, dtau, 2, residual=True)
+    nodes = phi.numel()
+    gbs = 2 * es * nodes / (ms * 1e-3) / 1e9
+    frac_interface = float((phi.abs() < 0.9).float().mean())
+    del phi, work
+    log("phase-field leg: %d nodes (%s), %.4f ms per step, %.1f GB/s (%.3f of HBM peak), "
+        "residual after %d steps %.3e" % (nodes, "f%d" % (8 * es), ms, gbs, gbs / HBM_PEAK_GBS,
+                                          iters + 4, res))
+    return {"grid": list(system.phi.shape[::-1]), "dtype": "f%d" % (8 * es), "steps": iters,
+            "eps": eps, "dtau": dtau, "ms_per_step": ms,
+            "roofline": {"bound": "hbm", "kernel": "k_phi_relax", "achieved": gbs,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                         "bytes_per_launch": 2 * es * nodes, "avg_launch_ms": ms},
+            "residual_after": res, "pseudo_time": (iters + 4) * dtau,
+            "interface_fraction": frac_interface, "seconds": time.time() - t0}
 
 
 def sph_leg(dpd, system, steps, timing_steps, force_ms, ms_per_step):

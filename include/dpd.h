@@ -358,6 +358,34 @@ int dpd_pair_random(uint64_t seed, uint64_t k, uint32_t replica, const uint32_t 
  * hardware byte counters are calibrated against. */
 int dpd_copy_probe(void *dst, const void *src, size_t bytes, void *hip_stream);
 
+/* ---- Phase-field relaxation (Sec. II.B, Eq. 13-15) ----
+ * Integrates d phi / d t' = lap' phi + phi (1 - phi^2) - kappa |grad' phi|
+ * with kappa = div'(grad' phi / |grad' phi|) and grad' = eps grad (Eq. 15)
+ * in the pseudo time t' by `iters` explicit Euler steps of length dtau,
+ * from the field in phi (a step function -1 solid / +1 fluid in the
+ * paper), on the periodic node-centred grid of dpd_phi_grid (n[2] x n[1] x
+ * n[0] values, x fastest, node (i, j, k) at (i h[0], j h[1], k h[2])).
+ * Differences: the compact 7-point Laplacian; central differences for
+ * grad' phi and for the divergence of n = grad' phi / max(|grad' phi|,
+ * 0.01), the unit normal wherever |grad' phi| >= 0.01, going linearly to
+ * zero where phi is flat.
+ *   phi    device, dtype 4 (float32) or 8 (float64) values; input, and the
+ *          field after the last step on return
+ *   work   device, n[0] n[1] n[2] + 1 values of the same dtype, owned by
+ *          the caller, overwritten (ping-pong buffer and one reduction word)
+ *   eps    interface coefficient of Eq. 12 (phi = tanh(x / (sqrt(2) eps))
+ *          at a plane, Eq. 14); > 0
+ *   dtau   pseudo-time step, 0 < dtau <= 1 / (2 sum_a (eps / h[a])^2), the
+ *          explicit-Euler bound of the diffusion part
+ *   iters  >= 0 steps
+ *   residual  host, may be NULL: receives max over nodes of |d phi / d t'|
+ *          in the last step (0 when iters = 0); the call then synchronises
+ *          hip_stream, otherwise it only enqueues work on it.
+ * Needs n[a] >= 1 and n[0] n[1] < 2^31.  DPD_E_INVAL for bad arguments,
+ * DPD_E_DEVICE for a HIP error (dpd_last_error(NULL) says which). */
+int dpd_phi_relax(void *phi, void *work, int32_t dtype, const int32_t n[3], const double h[3],
+                  double eps, double dtau, int32_t iters, double *residual, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,9 +20,13 @@ these are the readings):
   - lap' phi: the compact 7-point Laplacian, eps^2 sum_a (phi[+a] - 2 phi +
     phi[-a]) / h_a^2;
   - grad' phi: central differences, eps (phi[+a] - phi[-a]) / (2 h_a);
-  - the unit normal n = grad' phi / sqrt(|grad' phi|^2 + delta^2) with
-    delta = 1e-3, so that n goes smoothly to zero where phi is flat (the
-    bulk phases) instead of being a direction of rounding noise;
+  - the unit normal n = grad' phi / max(|grad' phi|, delta) with
+    delta = 0.01: exactly the unit normal wherever |grad' phi| >= delta
+    (on the planar profile, everywhere with |phi| < 0.9929), and going
+    linearly to zero where phi is flat (the bulk phases) instead of being
+    a direction of rounding noise; the map from grad' phi to n then has
+    slope <= 1/delta, which bounds how much the counter term amplifies
+    rounding where grad' phi passes through zero;
   - kappa: central differences of n, sum_a eps (n_a[+a] - n_a[-a]) / (2 h_a);
   - the counter term kappa |grad' phi| uses the same |grad' phi|.
 Pins: the planar steady state is Eq. 14's tanh profile, converging at
@@ -35,7 +39,7 @@ from __future__ import annotations
 
 import numpy as np
 
-DELTA = 1e-3
+DELTA = 0.01
 
 
 def _d1(phi, axis, h):
@@ -61,7 +65,7 @@ def rhs(phi, h, eps, counter_term=True, delta=DELTA):
     g = [eps * _d1(phi, ax, h[a]) for a, ax in enumerate(axes)]
     gmag = np.sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2])
     # unit normal (regularised where phi is flat) and its divergence
-    den = np.sqrt(gmag * gmag + delta * delta)
+    den = np.maximum(gmag, delta)
     kappa = np.zeros_like(phi)
     for a, ax in enumerate(axes):
         kappa += eps * _d1(g[a] / den, ax, h[a])

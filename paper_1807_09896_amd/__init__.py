@@ -17,15 +17,24 @@ from .binding import (DPDError, dpd_autotune, dpd_batch_create, dpd_counters, dp
                       dpd_destroy, dpd_forces, dpd_get_state, dpd_kernel_times, dpd_last_error,
                       dpd_neighbor_pairs, dpd_profile, dpd_replica_count, dpd_replica_forces,
                       dpd_replica_pairs, dpd_replica_profile, dpd_replica_set_state,
-                      dpd_replica_state, dpd_set_state, dpd_step, dpd_sync, dpd_use_graph,
-                      load_library)
+                      dpd_phi_relax, dpd_replica_state, dpd_set_state, dpd_step, dpd_sync,
+                      dpd_use_graph, load_library)
 
 __all__ = ["Simulation", "DPDError", "load_library", "dpd_create", "dpd_batch_create",
            "dpd_step", "dpd_forces", "dpd_get_state", "dpd_set_state", "dpd_neighbor_pairs",
            "dpd_profile", "dpd_counters", "dpd_kernel_times", "dpd_sync", "dpd_last_error",
            "dpd_destroy", "dpd_replica_count", "dpd_replica_forces", "dpd_replica_state",
            "dpd_replica_set_state", "dpd_replica_pairs", "dpd_replica_profile",
-           "dpd_use_graph", "dpd_autotune"]
+           "dpd_use_graph", "dpd_autotune", "dpd_phi_relax", "relax_phi"]
+
+
+def relax_phi(phi, h, eps, dtau, iters, stream=None):
+    """Relax a phase field on the GPU by Eq. 15 (Sec. II.B): `iters` explicit
+    Euler steps of length dtau in the pseudo time, in place on the device
+    tensor phi (nz, ny, nx).  Returns the last step's max |d phi / d t'|."""
+    import torch
+    work = torch.empty(phi.numel() + 1, dtype=phi.dtype, device=phi.device)
+    return dpd_phi_relax(phi, work, h, eps, dtau, iters, residual=True, stream=stream)
 
 
 def _box_args(system, params=None):

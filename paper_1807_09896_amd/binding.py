@@ -39,7 +39,7 @@ EXPORTED = ["dpd_create", "dpd_step", "dpd_forces", "dpd_get_state", "dpd_set_st
             "dpd_pair_random", "dpd_batch_create", "dpd_replica_count", "dpd_replica_forces",
             "dpd_replica_state", "dpd_replica_set_state", "dpd_replica_pairs",
             "dpd_replica_profile", "dpd_use_graph", "dpd_autotune", "dpd_set_params",
-            "dpd_set_phi", "dpd_window_forward", "dpd_backward"]
+            "dpd_set_phi", "dpd_window_forward", "dpd_backward", "dpd_phi_relax"]
 
 
 class DPDError(RuntimeError):
@@ -119,6 +119,9 @@ def load_library(path: str = LIB_PATH):
     L.dpd_destroy.restype = None
     L.dpd_copy_probe.argtypes = [P, P, C.c_size_t, P]
     L.dpd_copy_probe.restype = C.c_int
+    L.dpd_phi_relax.argtypes = [P, P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                C.c_double, C.c_double, C.c_int32, C.POINTER(C.c_double), P]
+    L.dpd_phi_relax.restype = C.c_int
     L.dpd_pair_random.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, P, P, C.c_int64, P, P, P]
     L.dpd_pair_random.restype = C.c_int
     L.dpd_batch_create.argtypes = [C.c_int32, P, P, P, P, P, P, C.POINTER(P)]
@@ -414,6 +417,26 @@ def dpd_destroy(ctx):
 
 def dpd_copy_probe(dst, src, nbytes, stream=None):
     _check(load_library().dpd_copy_probe(_ptr(dst), _ptr(src), int(nbytes), _stream_handle(stream)))
+
+
+def dpd_phi_relax(phi, work, h, eps, dtau, iters, residual=True, stream=None):
+    """phi: contiguous device tensor (nz, ny, nx) of float32 or float64,
+    relaxed in place; work: device tensor of the same dtype with at least
+    phi.numel() + 1 elements.  Returns the last step's max |d phi / d t'|
+    (synchronising) or None when residual is False."""
+    import torch
+    if phi.dim() != 3 or not phi.is_contiguous() or phi.dtype not in (torch.float32, torch.float64):
+        raise ValueError("phi must be a contiguous (nz, ny, nx) float32 or float64 tensor")
+    if work.dtype != phi.dtype or work.numel() < phi.numel() + 1 or not work.is_contiguous():
+        raise ValueError("work must be contiguous, of phi's dtype, with phi.numel() + 1 elements")
+    n = (C.c_int32 * 3)(int(phi.shape[2]), int(phi.shape[1]), int(phi.shape[0]))
+    hh = (C.c_double * 3)(*[float(x) for x in h])
+    res = C.c_double(0.0)
+    _check(load_library().dpd_phi_relax(_ptr(phi), _ptr(work), int(phi.element_size()), n, hh,
+                                        float(eps), float(dtau), int(iters),
+                                        C.byref(res) if residual else None,
+                                        _stream_handle(stream)))
+    return res.value if residual else None
 
 
 def dpd_pair_random(seed, k, replica, gi, gj, words=None, xi=None, stream=None):

@@ -1654,4 +1654,62 @@ int dpd_copy_probe(void *dst, const void *src, size_t bytes, void *hip_stream) {
   return e == hipSuccess ? DPD_OK : DPD_E_DEVICE;
 }
 
+int dpd_phi_relax(void *phi, void *work, int32_t dtype, const int32_t n[3], const double h[3],
+                  double eps, double dtau, int32_t iters, double *residual, void *hip_stream) {
+  if (!phi || !work || !n || !h) return fail(nullptr, DPD_E_INVAL, "NULL argument");
+  if (dtype != 4 && dtype != 8) return fail(nullptr, DPD_E_INVAL, "dtype must be 4 or 8");
+  for (int a = 0; a < 3; ++a) {
+    if (n[a] < 1) return fail(nullptr, DPD_E_INVAL, "grid sizes must be >= 1");
+    if (!(std::isfinite(h[a]) && h[a] > 0)) return fail(nullptr, DPD_E_INVAL, "h must be > 0");
+  }
+  if ((int64_t)n[0] * n[1] > INT32_MAX)
+    return fail(nullptr, DPD_E_INVAL, "n[0] n[1] must be < 2^31");
+  if (!(std::isfinite(eps) && eps > 0)) return fail(nullptr, DPD_E_INVAL, "eps must be > 0");
+  double stiff = 0;
+  for (int a = 0; a < 3; ++a) stiff += (eps / h[a]) * (eps / h[a]);
+  if (!(std::isfinite(dtau) && dtau > 0 && dtau <= 1.0 / (2.0 * stiff)))
+    return fail(nullptr, DPD_E_INVAL, "need 0 < dtau <= 1 / (2 sum (eps/h)^2)");
+  if (iters < 0) return fail(nullptr, DPD_E_INVAL, "iters must be >= 0");
+  if (dpd::phi_relax_blocks(n) > INT32_MAX) return fail(nullptr, DPD_E_INVAL, "grid too large");
+  hipStream_t s = (hipStream_t)hip_stream;
+  const size_t es = (size_t)dtype;
+  const size_t nodes = (size_t)n[0] * n[1] * n[2];
+  // Eq. 15 in the grid's units: lap' = eps^2 lap, grad' = eps grad
+  const double coef[8] = {eps * eps / (h[0] * h[0]), eps * eps / (h[1] * h[1]),
+                          eps * eps / (h[2] * h[2]), eps / (2 * h[0]), eps / (2 * h[1]),
+                          eps / (2 * h[2]), 1e-4, dtau};
+  void *res = (char *)work + nodes * es;
+  void *cur = phi, *nxt = work;
+  hipError_t e = hipSuccess;
+  for (int32_t it = 0; it < iters && e == hipSuccess; ++it) {
+    const bool last = residual && it == iters - 1;
+    if (last) e = dpd::launch_fill_zero(s, res, es);
+    if (e == hipSuccess)
+      e = dpd::launch_phi_relax(s, dtype == 8, cur, nxt, n, coef, last ? res : nullptr);
+    std::swap(cur, nxt);
+  }
+  if (e == hipSuccess && cur != phi) e = hipMemcpyAsync(phi, cur, nodes * es, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "dpd_phi_relax");
+  if (residual) {
+    *residual = 0.0;
+    if (iters > 0) {
+      uint64_t bits = 0;
+      e = hipMemcpyAsync(&bits, res, es, hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return hip_fail(nullptr, e, "dpd_phi_relax residual");
+      if (dtype == 8) {
+        double v;
+        memcpy(&v, &bits, 8);
+        *residual = v;
+      } else {
+        float v;
+        uint32_t b32 = (uint32_t)bits;
+        memcpy(&v, &b32, 4);
+        *residual = v;
+      }
+    }
+  }
+  return DPD_OK;
+}
+
 }  // extern "C"

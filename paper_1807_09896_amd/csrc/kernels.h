@@ -143,6 +143,16 @@ hipError_t launch_profile(hipStream_t s, const KGeom &G, int64_t nf, const float
                           const float4 *vel4, int axis, int nbins, double *out);
 
 hipError_t launch_fill_zero(hipStream_t s, void *p, size_t bytes);
+
+// One explicit Euler step of the phase-field relaxation (Eq. 15) from src to
+// dst (f64: double, else float; n[3] nodes, x fastest; n[0] * n[1] must fit
+// in int32).  coef = {eps^2/h_x^2, eps^2/h_y^2, eps^2/h_z^2, eps/(2 h_x),
+// eps/(2 h_y), eps/(2 h_z), delta^2, dtau}.  res (device, one word of the
+// element size, zeroed by the caller) receives max |rhs| as ordered bits,
+// or null.
+hipError_t launch_phi_relax(hipStream_t s, int f64, const void *src, void *dst,
+                            const int32_t n[3], const double coef[8], void *res);
+int64_t phi_relax_blocks(const int32_t n[3]);
 hipError_t launch_copy(hipStream_t s, void *dst, const void *src, size_t bytes);
 
 // ---- adjoint form (adjoint.hip) ----

@@ -111,3 +111,20 @@ def test_odd_in_phi():
     a, _ = pf.relax(phi0, (0.25, 0.3, 0.35), EPS, 0.02, 30)
     b, _ = pf.relax(-phi0, (0.25, 0.3, 0.35), EPS, 0.02, 30)
     assert np.array_equal(a, -b)
+
+
+def test_parity_inputs_are_well_conditioned():
+    """The GPU parity inputs: relative input perturbations of 1e-7 move the
+    relaxed field by at most 100 times that (no sliver thinner than the
+    interface, whose fate rounding would decide), so FP32 rounding of the
+    kernels stays within the parity tolerance."""
+    from pf_cases import CASES, case_input
+    rng = np.random.default_rng(1)
+    for i in range(len(CASES)):
+        phi0, h, iters = case_input(i)
+        dtau = 0.5 * pf.max_stable_dtau(h, EPS)
+        a, _ = pf.relax(phi0, h, EPS, dtau, iters)
+        for _ in range(2):
+            b, _ = pf.relax(phi0 * (1 + 1e-7 * rng.standard_normal(phi0.shape)), h, EPS, dtau, iters)
+            assert np.abs(a - b).max() < 100 * 1e-7, i
+        assert (np.abs(a) < 0.9).sum() > 0

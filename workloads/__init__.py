@@ -608,3 +608,39 @@ def _porous_system_torch(Lbox, rho, h, width, corr_len, porosity, wall_band, see
                   h=np.array([h, h, h]), params=params,
                   meta=dict(porosity=porosity, corr_len=corr_len, threshold=float(thr),
                             n_fluid=int(nf), n_wall=int(nw), generator="torch"))
+
+
+def step_phase_field(n, h, seed, min_len=6.0, margin=0.25):
+    """A -1 (solid) / +1 (fluid) step function on the node grid n = (nx, ny,
+    nz), spacings h, returned as an array (nz, ny, nx): the sign of
+    sum_a A_a cos(2 pi x_a / L_a + p_a) - t over the axes at least `min_len`
+    long (A_a, p_a seeded).  Such a field's critical values are the sums
+    +-A_x +-A_y +-A_z; the threshold t stays `margin` min(A) away from all of
+    them, so the level set has no near-degenerate saddle and every solid and
+    fluid feature is as wide as a sizeable part of its box, not a sliver of
+    a few nodes.  Axes shorter than `min_len` carry no variation; with none
+    long enough, the field is a seeded random step function (for grids
+    smaller than the interface itself)."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = (int(v) for v in n)
+    L = [nx * h[0], ny * h[1], nz * h[2]]
+    use = [a for a in range(3) if L[a] >= min_len]
+    if not use:
+        return np.where(rng.random((nz, ny, nx)) < 0.5, -1.0, 1.0)
+    A = {a: rng.uniform(0.6, 1.4) for a in use}
+    crit = [0.0]
+    for a in use:
+        crit = [c + s * A[a] for c in crit for s in (-1.0, 1.0)]
+    lo, hi = min(crit), max(crit)
+    gap = margin * min(A.values())
+    while True:
+        t = rng.uniform(0.5 * lo, 0.5 * hi)
+        if all(abs(t - c) >= gap for c in crit):
+            break
+    f = np.zeros((nz, ny, nx))
+    coords = [np.arange(nx) * h[0], np.arange(ny) * h[1], np.arange(nz) * h[2]]
+    shape = {0: (1, 1, nx), 1: (1, ny, 1), 2: (nz, 1, 1)}
+    for a in use:
+        p = rng.uniform(0, 2 * np.pi)
+        f = f + A[a] * np.cos(2 * np.pi * coords[a] / L[a] + p).reshape(shape[a])
+    return np.where(f > t, 1.0, -1.0)

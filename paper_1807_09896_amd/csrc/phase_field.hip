@@ -10,13 +10,15 @@
 // flat instead of pointing along rounding noise).
 //
 // Data flow: a block owns a 64 x 8 column of nodes and marches it through a
-// chunk of 32 z planes.  phi planes z-1 .. z+2 (with a two-node x/y halo)
-// live in an LDS ring of four, the normal planes z-1 .. z+1 (one-node halo)
-// in a ring of three; each z step loads one phi plane, computes one normal
-// plane and updates one plane.  Each node's normal is computed once per
-// block (plus the halo), and phi is read from HBM about once per node (the
-// x/y halo and the three planes before a chunk come from L2).  Tiles are
-// ordered so that neighbouring tiles run on the same XCD and share its L2.
+// chunk of 64 z planes.  phi planes (with a two-node x/y halo) live in an
+// LDS ring of five, the normal planes z-1 .. z+1 (one-node halo) in a ring
+// of three; each z step stores one phi plane into the ring, computes one
+// normal plane and updates one plane, with two barriers.  The global loads
+// of a plane are issued one step before its LDS store, so their latency
+// overlaps a step of work.  Each node's normal is computed once per block
+// (plus the halo), and phi is read from HBM about once per node (the x/y
+// halo and the planes before a chunk come from L2).  Tiles are ordered so
+// that neighbouring tiles run on the same XCD and share its L2.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -25,13 +27,16 @@
 namespace dpd {
 namespace {
 
-constexpr int kBX = 64, kBY = 8, kTZ = 32;
-constexpr int kThreads = kBX * kBY;
+constexpr int kBX = 64, kBY = 8, kTZ = 64;
+constexpr int kThreads = 256;
+constexpr int kRows = kBY * kBX / kThreads;   // nodes per thread in a plane (rows ty, ty + 4)
+constexpr int kRing = 5;                      // phi planes z-2 .. z+2 at step z
 constexpr int kPW = kBX + 4, kPH = kBY + 4;   // phi plane with a 2-node halo
 constexpr int kNW = kBX + 2, kNH = kBY + 2;   // normal plane with a 1-node halo
 constexpr int kPPlane = kPW * kPH;
 constexpr int kNPlane = kNW * kNH;
 constexpr int kLoadSlots = (kPPlane + kThreads - 1) / kThreads;
+constexpr int kNormSlots = (kNPlane + kThreads - 1) / kThreads;
 
 template <typename T>
 struct RelaxArgs {
@@ -53,8 +58,12 @@ __device__ __forceinline__ int wrap(int g, int n) {
   return g;
 }
 
-__device__ __forceinline__ float inv_sqrt(float v) { return rsqrtf(v); }
-__device__ __forceinline__ double inv_sqrt(double v) { return 1.0 / sqrt(v); }
+// float: the hardware square root and reciprocal square root (about 1 ulp);
+// the rsq argument is at least delta^2, the sqrt argument is a sum of squares
+__device__ __forceinline__ float fast_sqrt(float v) { return __builtin_amdgcn_sqrtf(v); }
+__device__ __forceinline__ float fast_rsqrt(float v) { return __builtin_amdgcn_rsqf(v); }
+__device__ __forceinline__ double fast_sqrt(double v) { return sqrt(v); }
+__device__ __forceinline__ double fast_rsqrt(double v) { return 1.0 / sqrt(v); }
 
 __device__ __forceinline__ void res_max(void *res, float v) {
   atomicMax((unsigned int *)res, __float_as_uint(v));
@@ -65,8 +74,8 @@ __device__ __forceinline__ void res_max(void *res, double v) {
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_phi_relax(RelaxArgs<T> a) {
-  __shared__ T sphi[4][kPPlane];
-  __shared__ T sn[3][3][kNPlane];   // [ring slot][component][node]
+  __shared__ T sphi[kRing * kPPlane];
+  __shared__ T sn[3 * 3 * kNPlane];   // [ring slot][component][node]
 
   // tile of this block: the blocks of one XCD (dispatch is round-robin over
   // the eight XCDs) take a contiguous range of tiles
@@ -80,7 +89,7 @@ __global__ __launch_bounds__(kThreads) void k_phi_relax(RelaxArgs<T> a) {
   const int tid = threadIdx.x;
   const size_t plane = (size_t)a.nx * (size_t)a.ny;
 
-  // this thread's share of a phi plane: LDS slot and wrapped in-plane offset
+  // this thread's share of a phi plane: LDS index and wrapped in-plane offset
   int lslot[kLoadSlots], loff[kLoadSlots];
 #pragma unroll
   for (int s = 0; s < kLoadSlots; ++s) {
@@ -93,68 +102,111 @@ __global__ __launch_bounds__(kThreads) void k_phi_relax(RelaxArgs<T> a) {
       loff[s] = wrap(y0 + ly - 2, a.ny) * a.nx + wrap(x0 + lx - 2, a.nx);
     }
   }
-  auto load_plane = [&](int z) {   // phi plane z into ring slot z mod 4
+  // this thread's normal nodes: index in the normal plane (or -1) and the
+  // matching centre in the phi plane
+  int nidx[kNormSlots], ncen[kNormSlots];
+#pragma unroll
+  for (int s = 0; s < kNormSlots; ++s) {
+    const int m = tid + s * kThreads;
+    nidx[s] = m < kNPlane ? m : -1;
+    const int ly = m / kNW, lx = m - ly * kNW;
+    ncen[s] = (ly + 1) * kPW + lx + 1;
+  }
+
+  T pre[kLoadSlots];
+  auto fetch = [&](int z) {        // global loads of phi plane z into registers
     const T *p = a.src + (size_t)wrap(z, a.nz) * plane;
-    T *d = sphi[z & 3];
 #pragma unroll
     for (int s = 0; s < kLoadSlots; ++s)
-      if (lslot[s] >= 0) d[lslot[s]] = p[loff[s]];
+      if (lslot[s] >= 0) pre[s] = p[loff[s]];
   };
-  auto normals = [&](int z) {      // unit normal on plane z into ring slot z mod 3
-    const T *pm = sphi[(z - 1) & 3], *p0 = sphi[z & 3], *pp = sphi[(z + 1) & 3];
-    T *n = &sn[(z + 3) % 3][0][0];
-    for (int m = tid; m < kNPlane; m += kThreads) {
-      const int ly = m / kNW, lx = m - ly * kNW;
-      const int c = (ly + 1) * kPW + lx + 1;
-      const T ux = a.gx * (p0[c + 1] - p0[c - 1]);
-      const T uy = a.gy * (p0[c + kPW] - p0[c - kPW]);
-      const T uz = a.gz * (pp[c] - pm[c]);
-      const T inv = inv_sqrt(fmax(ux * ux + uy * uy + uz * uz, a.delta2));
-      n[m] = ux * inv;
-      n[kNPlane + m] = uy * inv;
-      n[2 * kNPlane + m] = uz * inv;
+  auto store = [&](int base) {     // the fetched plane into the ring slot at base
+#pragma unroll
+    for (int s = 0; s < kLoadSlots; ++s)
+      if (lslot[s] >= 0) sphi[base + lslot[s]] = pre[s];
+  };
+  // unit normal on a plane from the phi planes below (pm), at (p0) and above
+  // (pp) it, into the normal ring slot at nb
+  auto normals = [&](int pm, int p0, int pp, int nb) {
+#pragma unroll
+    for (int s = 0; s < kNormSlots; ++s) {
+      if (nidx[s] < 0) continue;
+      const int c = ncen[s];
+      const T ux = a.gx * (sphi[p0 + c + 1] - sphi[p0 + c - 1]);
+      const T uy = a.gy * (sphi[p0 + c + kPW] - sphi[p0 + c - kPW]);
+      const T uz = a.gz * (sphi[pp + c] - sphi[pm + c]);
+      const T inv = fast_rsqrt(fmax(ux * ux + uy * uy + uz * uz, a.delta2));
+      T *n = &sn[nb + nidx[s]];
+      n[0] = ux * inv;
+      n[kNPlane] = uy * inv;
+      n[2 * kNPlane] = uz * inv;
     }
   };
 
-  const int tx = tid % kBX, ty = tid / kBX;
-  const int x = x0 + tx, y = y0 + ty;
-  const bool mine = x < a.nx && y < a.ny;
+  const int tx = tid % kBX, ty0 = tid / kBX;
+  const int x = x0 + tx;
   T rmax = T(0);
-  auto update = [&](int z) {
-    if (!mine) return;
-    const T *pm = sphi[(z - 1) & 3], *p0 = sphi[z & 3], *pp = sphi[(z + 1) & 3];
-    const int c = (ty + 2) * kPW + tx + 2;
-    const T ph = p0[c];
-    const T xm = p0[c - 1], xp = p0[c + 1], ym = p0[c - kPW], yp = p0[c + kPW];
-    const T zm = pm[c], zp = pp[c];
-    const T lap = a.cx * (xp - T(2) * ph + xm) + a.cy * (yp - T(2) * ph + ym) +
-                  a.cz * (zp - T(2) * ph + zm);
-    const T ux = a.gx * (xp - xm), uy = a.gy * (yp - ym), uz = a.gz * (zp - zm);
-    const T gm = sqrt(ux * ux + uy * uy + uz * uz);
-    const int cn = (ty + 1) * kNW + tx + 1;
-    const T *n0 = &sn[(z + 3) % 3][0][0];
-    const T *nm = &sn[(z + 2) % 3][2][0], *np = &sn[(z + 4) % 3][2][0];
-    const T kap = a.gx * (n0[cn + 1] - n0[cn - 1]) +
-                  a.gy * (n0[kNPlane + cn + kNW] - n0[kNPlane + cn - kNW]) +
-                  a.gz * (np[cn] - nm[cn]);
-    const T rhs = lap + ph * (T(1) - ph * ph) - kap * gm;
-    a.dst[(size_t)z * plane + (size_t)y * a.nx + x] = ph + a.dtau * rhs;
-    rmax = fmax(rmax, fabs(rhs));
+  // explicit Euler update of this thread's nodes of plane z; phi ring slots
+  // of planes z-1, z, z+1 at pm, p0, pp, normal slots of z-1, z, z+1 at
+  // nm, n0, np
+  auto update = [&](int z, int pm, int p0, int pp, int nm, int n0, int np) {
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      const int ty = ty0 + k * (kThreads / kBX);
+      const int y = y0 + ty;
+      if (x >= a.nx || y >= a.ny) continue;
+      const int c = (ty + 2) * kPW + tx + 2;
+      const T ph = sphi[p0 + c];
+      const T xm = sphi[p0 + c - 1], xp = sphi[p0 + c + 1];
+      const T ym = sphi[p0 + c - kPW], yp = sphi[p0 + c + kPW];
+      const T zm = sphi[pm + c], zp = sphi[pp + c];
+      const T lap = a.cx * (xp - T(2) * ph + xm) + a.cy * (yp - T(2) * ph + ym) +
+                    a.cz * (zp - T(2) * ph + zm);
+      const T ux = a.gx * (xp - xm), uy = a.gy * (yp - ym), uz = a.gz * (zp - zm);
+      const T gm = fast_sqrt(ux * ux + uy * uy + uz * uz);
+      const int cn = (ty + 1) * kNW + tx + 1;
+      const T kap = a.gx * (sn[n0 + cn + 1] - sn[n0 + cn - 1]) +
+                    a.gy * (sn[n0 + kNPlane + cn + kNW] - sn[n0 + kNPlane + cn - kNW]) +
+                    a.gz * (sn[np + 2 * kNPlane + cn] - sn[nm + 2 * kNPlane + cn]);
+      const T rhs = lap + ph * (T(1) - ph * ph) - kap * gm;
+      a.dst[(size_t)z * plane + (size_t)y * a.nx + x] = ph + a.dtau * rhs;
+      rmax = fmax(rmax, fabs(rhs));
+    }
   };
 
-  // prologue: phi planes z0-2 .. z0+1, normals on z0-1 and z0
-  for (int z = z0 - 2; z <= z0 + 1; ++z) load_plane(z);
+  // ring slots (element offsets): phi planes z-2 .. z+2 and normal planes
+  // z-1 .. z+1 at step z, rotated by one plane per step
+  int s0 = 0, s1 = kPPlane, s2 = 2 * kPPlane, s3 = 3 * kPPlane, s4 = 4 * kPPlane;
+  int nm = 0, n0 = 3 * kNPlane, np = 6 * kNPlane;
+
+  // prologue: phi planes z0-2 .. z0+1 stored, z0+2 in flight; normals on
+  // z0-1 and z0
+  fetch(z0 - 2);
+  store(s0);
+  fetch(z0 - 1);
+  store(s1);
+  fetch(z0);
+  store(s2);
+  fetch(z0 + 1);
+  store(s3);
+  fetch(z0 + 2);
   __syncthreads();
-  normals(z0 - 1);
-  normals(z0);
-  __syncthreads();
+  normals(s0, s1, s2, nm);
+  normals(s1, s2, s3, n0);
   for (int z = z0; z < z1; ++z) {
-    load_plane(z + 2);   // overwrites plane z-2, last read before the previous barrier
+    // phi: s0 = z-2 (free: last read by the update of z-2 and the normals
+    // of z-2, both before the previous step's barriers), s1 = z-1, s2 = z,
+    // s3 = z+1, s4 = z+2
+    store(s4);
+    if (z + 1 < z1) fetch(z + 3);
     __syncthreads();
-    normals(z + 1);      // overwrites normals of z-2, no longer read
+    normals(s2, s3, s4, np);   // overwrites normals of z-2, last read by the update of z-1
     __syncthreads();
-    update(z);
-    __syncthreads();     // plane z-1 is overwritten by the next load
+    update(z, s1, s2, s3, nm, n0, np);
+    const int f = s0;
+    s0 = s1; s1 = s2; s2 = s3; s3 = s4; s4 = f;
+    const int g = nm;
+    nm = n0; n0 = np; np = g;
   }
 
   if (a.res) {

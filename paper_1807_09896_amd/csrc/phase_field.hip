@@ -89,48 +89,49 @@ __global__ __launch_bounds__(kThreads) void k_phi_relax(RelaxArgs<T> a) {
   const int tid = threadIdx.x;
   const size_t plane = (size_t)a.nx * (size_t)a.ny;
 
-  // this thread's share of a phi plane: LDS index and wrapped in-plane offset
+  // this thread's share of a phi plane: LDS index and wrapped in-plane
+  // offset.  Only the last slot can fall past the plane; there it repeats
+  // the thread's previous slot (same address, same value), so the loads and
+  // stores need no guard.
+  static_assert(kPPlane > (kLoadSlots - 1) * kThreads, "only the last load slot is partial");
+  static_assert(kNPlane > (kNormSlots - 1) * kThreads, "only the last normal slot is partial");
   int lslot[kLoadSlots], loff[kLoadSlots];
 #pragma unroll
   for (int s = 0; s < kLoadSlots; ++s) {
-    const int m = tid + s * kThreads;
-    lslot[s] = -1;
-    loff[s] = 0;
-    if (m < kPPlane) {
-      const int ly = m / kPW, lx = m - ly * kPW;
-      lslot[s] = m;
-      loff[s] = wrap(y0 + ly - 2, a.ny) * a.nx + wrap(x0 + lx - 2, a.nx);
-    }
+    int m = tid + s * kThreads;
+    if (m >= kPPlane) m -= kThreads;
+    const int ly = m / kPW, lx = m - ly * kPW;
+    lslot[s] = m;
+    loff[s] = wrap(y0 + ly - 2, a.ny) * a.nx + wrap(x0 + lx - 2, a.nx);
   }
-  // this thread's normal nodes: index in the normal plane (or -1) and the
-  // matching centre in the phi plane
+  // this thread's normal nodes: index in the normal plane and the matching
+  // centre in the phi plane (the last slot only for tid < kNPlane - 512)
   int nidx[kNormSlots], ncen[kNormSlots];
 #pragma unroll
   for (int s = 0; s < kNormSlots; ++s) {
     const int m = tid + s * kThreads;
-    nidx[s] = m < kNPlane ? m : -1;
+    nidx[s] = m;
     const int ly = m / kNW, lx = m - ly * kNW;
     ncen[s] = (ly + 1) * kPW + lx + 1;
   }
+  const bool last_normal = tid + (kNormSlots - 1) * kThreads < kNPlane;
 
   T pre[kLoadSlots];
   auto fetch = [&](int z) {        // global loads of phi plane z into registers
     const T *p = a.src + (size_t)wrap(z, a.nz) * plane;
 #pragma unroll
-    for (int s = 0; s < kLoadSlots; ++s)
-      if (lslot[s] >= 0) pre[s] = p[loff[s]];
+    for (int s = 0; s < kLoadSlots; ++s) pre[s] = p[loff[s]];
   };
   auto store = [&](int base) {     // the fetched plane into the ring slot at base
 #pragma unroll
-    for (int s = 0; s < kLoadSlots; ++s)
-      if (lslot[s] >= 0) sphi[base + lslot[s]] = pre[s];
+    for (int s = 0; s < kLoadSlots; ++s) sphi[base + lslot[s]] = pre[s];
   };
   // unit normal on a plane from the phi planes below (pm), at (p0) and above
   // (pp) it, into the normal ring slot at nb
   auto normals = [&](int pm, int p0, int pp, int nb) {
 #pragma unroll
     for (int s = 0; s < kNormSlots; ++s) {
-      if (nidx[s] < 0) continue;
+      if (s == kNormSlots - 1 && !last_normal) continue;
       const int c = ncen[s];
       const T ux = a.gx * (sphi[p0 + c + 1] - sphi[p0 + c - 1]);
       const T uy = a.gy * (sphi[p0 + c + kPW] - sphi[p0 + c - kPW]);
@@ -145,6 +146,7 @@ __global__ __launch_bounds__(kThreads) void k_phi_relax(RelaxArgs<T> a) {
 
   const int tx = tid % kBX, ty0 = tid / kBX;
   const int x = x0 + tx;
+  const bool xin = x < a.nx;
   T rmax = T(0);
   // explicit Euler update of this thread's nodes of plane z; phi ring slots
   // of planes z-1, z, z+1 at pm, p0, pp, normal slots of z-1, z, z+1 at
@@ -152,9 +154,10 @@ __global__ __launch_bounds__(kThreads) void k_phi_relax(RelaxArgs<T> a) {
   auto update = [&](int z, int pm, int p0, int pp, int nm, int n0, int np) {
 #pragma unroll
     for (int k = 0; k < kRows; ++k) {
+      // nodes past a ragged grid edge are computed from the wrapped values
+      // in LDS like the others, but neither stored nor counted
       const int ty = ty0 + k * (kThreads / kBX);
       const int y = y0 + ty;
-      if (x >= a.nx || y >= a.ny) continue;
       const int c = (ty + 2) * kPW + tx + 2;
       const T ph = sphi[p0 + c];
       const T xm = sphi[p0 + c - 1], xp = sphi[p0 + c + 1];
@@ -169,8 +172,9 @@ __global__ __launch_bounds__(kThreads) void k_phi_relax(RelaxArgs<T> a) {
                     a.gy * (sn[n0 + kNPlane + cn + kNW] - sn[n0 + kNPlane + cn - kNW]) +
                     a.gz * (sn[np + 2 * kNPlane + cn] - sn[nm + 2 * kNPlane + cn]);
       const T rhs = lap + ph * (T(1) - ph * ph) - kap * gm;
-      a.dst[(size_t)z * plane + (size_t)y * a.nx + x] = ph + a.dtau * rhs;
-      rmax = fmax(rmax, fabs(rhs));
+      const bool in = xin && y < a.ny;
+      if (in) a.dst[(size_t)z * plane + (size_t)y * a.nx + x] = ph + a.dtau * rhs;
+      rmax = in ? fmax(rmax, fabs(rhs)) : rmax;
     }
   };
 

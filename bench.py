@@ -102,6 +102,9 @@ def main():
     ap.add_argument("--phase-field-iters", type=int, default=200,
                     help="relaxation steps of the phase-field leg (Eq. 15 on the workload's "
                          "grid from its step function); 0 skips it")
+    ap.add_argument("--stokes-steps", type=int, default=2000,
+                    help="steps of the cylinder-array leg (16 replica cells of Sec. III.B "
+                         "in one batch); 0 skips it")
     ap.add_argument("--adjoint-reps", type=int, default=3,
                     help="timed repetitions of the 200-step adjoint window (0 skips the leg)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -204,6 +207,10 @@ def main():
     if args.walls_steps > 0:
         walls = walls_leg(dpd, args.walls_steps)
 
+    stokes = None
+    if args.stokes_steps > 0:
+        stokes = stokes_leg(dpd, args.stokes_steps)
+
     cpu = None
     if args.cpu_steps > 0:
         import oracle
@@ -249,6 +256,7 @@ def main():
         "moving_walls": walls,
         "sph_force": sph,
         "phase_field": pfield,
+        "cylinder_array": stokes,
     }
     print(json.dumps(out), flush=True)
     sim.close()
@@ -296,6 +304,34 @@ def phase_field_leg(dpd, system, iters):
                          "bytes_per_launch": 2 * es * nodes, "avg_launch_ms": ms},
             "residual_after": res, "pseudo_time": (iters + 4) * dtau,
             "interface_fraction": frac_interface, "seconds": time.time() - t0}
+
+
+def stokes_leg(dpd, steps, replicas=16, solid_fraction=0.1):
+    """Stokes flow through a square array of cylinders (Sec. III.B): 16
+    replica cells (28 x 28 x 4, one cylinder of solid fraction 0.1 each,
+    density 4, kBT = 0.1, gamma = 45, g = 0.001) stepped as one batch with
+    graph replay."""
+    import torch
+    import workloads
+    cells = [workloads.cylinder_array_system(solid_fraction=solid_fraction, seed=300 + k,
+                                             params=workloads.stokes_params(g=0.001, seed=400 + k))
+             for k in range(replicas)]
+    n = sum(c.n for c in cells)
+    sim = dpd.Simulation(cells, graph=True)
+    sim.step(50)
+    sim.sync()
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - ta
+    sim.close()
+    log("cylinder-array leg: %d replicas, %d particles, %.4f ms/step, %.4e particle-steps/s"
+        % (replicas, n, dt * 1e3 / steps, n * steps / dt))
+    return {"workload": "cylinder_array", "replicas": replicas, "solid_fraction": solid_fraction,
+            "particles": n, "steps": steps, "ms_per_step": dt * 1e3 / steps,
+            "value": n * steps / dt, "unit": "particle-steps/s"}
 
 
 def sph_leg(dpd, system, steps, timing_steps, force_ms, ms_per_step):

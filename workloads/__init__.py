@@ -339,6 +339,45 @@ def sinusoid_cylinder_system(L=(40.0, 40.0, 80.0), rho=3.0, h=0.25, width=0.5,
                      (h, h, h), params, dict(base=base, amp=amp, radius=radius))
 
 
+def stokes_params(g=0.005, dt=0.01, seed=60):
+    """Sec. III.A-B's low-temperature fluid: kBT = 0.1, a_ff = a_fs = 1.875,
+    gamma = 45 (sigma = 3), body force g along x on the fluid."""
+    return default_params(a_ff=1.875, a_fs=1.875, gamma=45.0, kBT=0.1, dt=dt,
+                          g=(g, 0.0, 0.0), seed=seed)
+
+
+def cylinder_array_system(L=28.0, Lz=4.0, solid_fraction=0.1, rho=4.0, h=0.25, width=0.5,
+                          wall_band=1.5, seed=61, params=None, grid_dtype=np.float32,
+                          name="cylinder_array"):
+    """Stokes flow through a square array of parallel cylinders (Sec. III.B):
+    one cylinder of radius r = L sqrt(solid_fraction / pi) along z at the
+    centre of an L x L cell, periodic in x and y (the array), in a periodic
+    slab Lz thick; walls fill the cylinder within `wall_band` of its
+    surface; body force along x."""
+    L3 = np.asarray([L, L, Lz], dtype=np.float64)
+    r = L * math.sqrt(solid_fraction / math.pi)
+    n = _grid_nodes(L3, (h, h, h))
+    xs = np.arange(n[0]) * h
+    ys = np.arange(n[1]) * h
+
+    def dist(x, y):
+        dx = np.mod(np.asarray(x) - L / 2 + L / 2, L) - L / 2
+        dy = np.mod(np.asarray(y) - L / 2 + L / 2, L) - L / 2
+        return np.hypot(dx, dy) - r
+
+    dxy = dist(xs[None, :], ys[:, None])               # (ny, nx)
+    d = np.broadcast_to(dxy[None, :, :], (n[2], n[1], n[0]))
+    phi = _phi_from_distance(np.ascontiguousarray(d), width, grid_dtype)
+    rng = np.random.default_rng(seed)
+    cand = _uniform_candidates(rng, L3, rho)
+    dc = dist(cand[:, 0], cand[:, 1])
+    fl = (dc > 0) & _classify(phi, (h, h, h), cand, fluid=True)
+    wl = (dc < 0) & (dc > -wall_band) & _classify(phi, (h, h, h), cand, fluid=False)
+    params = params or stokes_params(seed=seed)
+    return _assemble(name, L3, cand[fl], cand[wl], params["kBT"], rng, phi,
+                     (h, h, h), params, dict(radius=r, solid_fraction=solid_fraction, cell=L))
+
+
 def sinusoid_slit_system(L=(20.0, 20.0, 20.0), rho=3.0, h=0.25, width=0.5,
                          base=3.0, amp=2.0, wall_band=1.5, seed=40, params=None,
                          grid_dtype=np.float32, name="sinusoid_slit"):

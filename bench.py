@@ -294,6 +294,13 @@ def phase_field_leg(dpd, system, iters):
     gbs = 2 * es * nodes / (ms * 1e-3) / 1e9
     frac_interface = float((phi.abs() < 0.9).float().mean())
     del phi, work
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "phi_relax_porous168_traffic.json")
+    if os.path.exists(tfile) and system.name == "porous_grf_168":
+        with open(tfile) as fh:
+            tr = json.load(fh)
+        if tr.get("kernel_source_hash") == kernel_source_hash(("phase_field.hip",)):
+            traffic = tr.get("bytes_per_launch")
     log("phase-field leg: %d nodes (%s), %.4f ms per step, %.1f GB/s (%.3f of HBM peak), "
         "residual after %d steps %.3e" % (nodes, "f%d" % (8 * es), ms, gbs, gbs / HBM_PEAK_GBS,
                                           iters + 4, res))
@@ -301,7 +308,8 @@ def phase_field_leg(dpd, system, iters):
             "eps": eps, "dtau": dtau, "ms_per_step": ms,
             "roofline": {"bound": "hbm", "kernel": "k_phi_relax", "achieved": gbs,
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-                         "bytes_per_launch": 2 * es * nodes, "avg_launch_ms": ms},
+                         "traffic": traffic, "bytes_per_launch": 2 * es * nodes,
+                         "avg_launch_ms": ms},
             "residual_after": res, "pseudo_time": (iters + 4) * dtau,
             "interface_fraction": frac_interface, "seconds": time.time() - t0}
 
@@ -505,10 +513,10 @@ def adjoint_leg(dpd, reps, steps=200, ckpt=20, nbins=40):
             "step_kernel_ms": {k: v[0] / max(v[1], 1) for k, v in kt.items() if v[1]}}
 
 
-def kernel_source_hash():
+def kernel_source_hash(files=("device.h", "kernels.hip")):
     import hashlib
     h = hashlib.sha256()
-    for f in ("device.h", "kernels.hip"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_1807_09896_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

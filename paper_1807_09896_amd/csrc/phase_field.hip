@@ -11,14 +11,17 @@
 //
 // Data flow: a block owns a 64 x 8 column of nodes and marches it through a
 // chunk of 64 z planes.  phi planes (with a two-node x/y halo) live in an
-// LDS ring of five, the normal planes z-1 .. z+1 (one-node halo) in a ring
-// of three; each z step stores one phi plane into the ring, computes one
-// normal plane and updates one plane, with two barriers.  The global loads
-// of a plane are issued one step before its LDS store, so their latency
-// overlaps a step of work.  Each node's normal is computed once per block
-// (plus the halo), and phi is read from HBM about once per node (the x/y
-// halo and the planes before a chunk come from L2).  Tiles are ordered so
-// that neighbouring tiles run on the same XCD and share its L2.
+// LDS ring of four, the normal planes z-1 .. z+1 (one-node halo) in a ring
+// of three.  Each z step stores one phi plane into the ring, prepares the
+// next plane (each thread's own nodes: the Laplacian and reaction terms and
+// |grad' phi| into registers, the unit normal into LDS; the halo normals by
+// the first threads) and updates the current plane from its registers and
+// the divergence of the normals, with two barriers.  The global loads of a
+// plane are issued one step before its LDS store, so their latency overlaps
+// a step of work.  Each node's stencil is read once, phi is read from HBM
+// about once per node (the x/y halo and the planes before a chunk come from
+// L2), and tiles are ordered so that neighbouring tiles run on the same XCD
+// and share its L2.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -30,13 +33,13 @@ namespace {
 constexpr int kBX = 64, kBY = 8, kTZ = 64;
 constexpr int kThreads = 256;
 constexpr int kRows = kBY * kBX / kThreads;   // nodes per thread in a plane (rows ty, ty + 4)
-constexpr int kRing = 5;                      // phi planes z-2 .. z+2 at step z
+constexpr int kRing = 4;                      // phi planes z-1 .. z+2 at step z
 constexpr int kPW = kBX + 4, kPH = kBY + 4;   // phi plane with a 2-node halo
 constexpr int kNW = kBX + 2, kNH = kBY + 2;   // normal plane with a 1-node halo
 constexpr int kPPlane = kPW * kPH;
 constexpr int kNPlane = kNW * kNH;
+constexpr int kHalo = kNPlane - kBX * kBY;    // normal nodes outside the tile
 constexpr int kLoadSlots = (kPPlane + kThreads - 1) / kThreads;
-constexpr int kNormSlots = (kNPlane + kThreads - 1) / kThreads;
 
 template <typename T>
 struct RelaxArgs {
@@ -72,6 +75,12 @@ __device__ __forceinline__ void res_max(void *res, double v) {
   atomicMax((unsigned long long *)res, (unsigned long long)__double_as_longlong(v));
 }
 
+// Per step z the block (1) stores phi plane z+2, fetched a step earlier, (2)
+// prepares plane z+1: for its own nodes the Laplacian term, |grad' phi| and
+// phi stay in registers and the unit normal goes to LDS; the 148 normal
+// nodes of the halo are computed by the first threads; (3) updates plane z
+// from the registers prepared a step earlier and the divergence of the
+// normals in LDS.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_phi_relax(RelaxArgs<T> a) {
   __shared__ T sphi[kRing * kPPlane];
@@ -94,7 +103,7 @@ __global__ __launch_bounds__(kThreads) void k_phi_relax(RelaxArgs<T> a) {
   // the thread's previous slot (same address, same value), so the loads and
   // stores need no guard.
   static_assert(kPPlane > (kLoadSlots - 1) * kThreads, "only the last load slot is partial");
-  static_assert(kNPlane > (kNormSlots - 1) * kThreads, "only the last normal slot is partial");
+  static_assert(kHalo <= kThreads, "one halo normal per thread at most");
   int lslot[kLoadSlots], loff[kLoadSlots];
 #pragma unroll
   for (int s = 0; s < kLoadSlots; ++s) {
@@ -104,17 +113,22 @@ __global__ __launch_bounds__(kThreads) void k_phi_relax(RelaxArgs<T> a) {
     lslot[s] = m;
     loff[s] = wrap(y0 + ly - 2, a.ny) * a.nx + wrap(x0 + lx - 2, a.nx);
   }
-  // this thread's normal nodes: index in the normal plane and the matching
-  // centre in the phi plane (the last slot only for tid < kNPlane - 512)
-  int nidx[kNormSlots], ncen[kNormSlots];
-#pragma unroll
-  for (int s = 0; s < kNormSlots; ++s) {
-    const int m = tid + s * kThreads;
-    nidx[s] = m;
-    const int ly = m / kNW, lx = m - ly * kNW;
-    ncen[s] = (ly + 1) * kPW + lx + 1;
+  // this thread's halo normal (tid < kHalo): the rows above and below the
+  // tile, then the columns left and right of it
+  const bool has_halo = tid < kHalo;
+  int hn = 0;
+  {
+    int lx, ly;
+    if (tid < kNW) {
+      ly = 0, lx = tid;
+    } else if (tid < 2 * kNW) {
+      ly = kNH - 1, lx = tid - kNW;
+    } else {
+      const int k = tid - 2 * kNW;          // 0 .. 2 kBY - 1
+      ly = 1 + (k >> 1), lx = (k & 1) ? kNW - 1 : 0;
+    }
+    hn = has_halo ? ly * kNW + lx : 0;
   }
-  const bool last_normal = tid + (kNormSlots - 1) * kThreads < kNPlane;
 
   T pre[kLoadSlots];
   auto fetch = [&](int z) {        // global loads of phi plane z into registers
@@ -126,38 +140,34 @@ __global__ __launch_bounds__(kThreads) void k_phi_relax(RelaxArgs<T> a) {
 #pragma unroll
     for (int s = 0; s < kLoadSlots; ++s) sphi[base + lslot[s]] = pre[s];
   };
-  // unit normal on a plane from the phi planes below (pm), at (p0) and above
-  // (pp) it, into the normal ring slot at nb
-  auto normals = [&](int pm, int p0, int pp, int nb) {
-#pragma unroll
-    for (int s = 0; s < kNormSlots; ++s) {
-      if (s == kNormSlots - 1 && !last_normal) continue;
-      const int c = ncen[s];
-      const T ux = a.gx * (sphi[p0 + c + 1] - sphi[p0 + c - 1]);
-      const T uy = a.gy * (sphi[p0 + c + kPW] - sphi[p0 + c - kPW]);
-      const T uz = a.gz * (sphi[pp + c] - sphi[pm + c]);
-      const T inv = fast_rsqrt(fmax(ux * ux + uy * uy + uz * uz, a.delta2));
-      T *n = &sn[nb + nidx[s]];
-      n[0] = ux * inv;
-      n[kNPlane] = uy * inv;
-      n[2 * kNPlane] = uz * inv;
-    }
+  // unit normal at normal-plane node m from the phi planes below (pm), at
+  // (p0) and above (pp); returns grad' phi
+  auto normal_at = [&](int pm, int p0, int pp, int nb, int m, T &ux, T &uy, T &uz) {
+    const int ly = m / kNW, lx = m - ly * kNW;
+    const int c = (ly + 1) * kPW + lx + 1;
+    ux = a.gx * (sphi[p0 + c + 1] - sphi[p0 + c - 1]);
+    uy = a.gy * (sphi[p0 + c + kPW] - sphi[p0 + c - kPW]);
+    uz = a.gz * (sphi[pp + c] - sphi[pm + c]);
+    const T s2 = ux * ux + uy * uy + uz * uz;
+    const T inv = fast_rsqrt(fmax(s2, a.delta2));
+    sn[nb + m] = ux * inv;
+    sn[nb + kNPlane + m] = uy * inv;
+    sn[nb + 2 * kNPlane + m] = uz * inv;
+    return s2;
   };
 
   const int tx = tid % kBX, ty0 = tid / kBX;
   const int x = x0 + tx;
   const bool xin = x < a.nx;
   T rmax = T(0);
-  // explicit Euler update of this thread's nodes of plane z; phi ring slots
-  // of planes z-1, z, z+1 at pm, p0, pp, normal slots of z-1, z, z+1 at
-  // nm, n0, np
-  auto update = [&](int z, int pm, int p0, int pp, int nm, int n0, int np) {
+  // prepared terms of this thread's nodes: phi, the Laplacian term plus the
+  // reaction term, and |grad' phi|
+  T cur_ph[kRows], cur_base[kRows], cur_gm[kRows];
+  T nxt_ph[kRows], nxt_base[kRows], nxt_gm[kRows];
+  auto prepare = [&](int pm, int p0, int pp, int nb) {
 #pragma unroll
     for (int k = 0; k < kRows; ++k) {
-      // nodes past a ragged grid edge are computed from the wrapped values
-      // in LDS like the others, but neither stored nor counted
       const int ty = ty0 + k * (kThreads / kBX);
-      const int y = y0 + ty;
       const int c = (ty + 2) * kPW + tx + 2;
       const T ph = sphi[p0 + c];
       const T xm = sphi[p0 + c - 1], xp = sphi[p0 + c + 1];
@@ -166,49 +176,85 @@ __global__ __launch_bounds__(kThreads) void k_phi_relax(RelaxArgs<T> a) {
       const T lap = a.cx * (xp - T(2) * ph + xm) + a.cy * (yp - T(2) * ph + ym) +
                     a.cz * (zp - T(2) * ph + zm);
       const T ux = a.gx * (xp - xm), uy = a.gy * (yp - ym), uz = a.gz * (zp - zm);
-      const T gm = fast_sqrt(ux * ux + uy * uy + uz * uz);
+      const T s2 = ux * ux + uy * uy + uz * uz;
+      const T inv = fast_rsqrt(fmax(s2, a.delta2));
+      const int m = (ty + 1) * kNW + tx + 1;
+      sn[nb + m] = ux * inv;
+      sn[nb + kNPlane + m] = uy * inv;
+      sn[nb + 2 * kNPlane + m] = uz * inv;
+      nxt_ph[k] = ph;
+      nxt_base[k] = lap + ph * (T(1) - ph * ph);
+      nxt_gm[k] = fast_sqrt(s2);
+    }
+    if (has_halo) {
+      T ux, uy, uz;
+      normal_at(pm, p0, pp, nb, hn, ux, uy, uz);
+    }
+  };
+  // explicit Euler update of this thread's nodes of plane z from the
+  // prepared terms and the normals of planes z-1, z, z+1 at nm, n0, np
+  auto update = [&](int z, int nm, int n0, int np) {
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      // nodes past a ragged grid edge are computed from the wrapped values
+      // in LDS like the others, but neither stored nor counted
+      const int ty = ty0 + k * (kThreads / kBX);
+      const int y = y0 + ty;
       const int cn = (ty + 1) * kNW + tx + 1;
       const T kap = a.gx * (sn[n0 + cn + 1] - sn[n0 + cn - 1]) +
                     a.gy * (sn[n0 + kNPlane + cn + kNW] - sn[n0 + kNPlane + cn - kNW]) +
                     a.gz * (sn[np + 2 * kNPlane + cn] - sn[nm + 2 * kNPlane + cn]);
-      const T rhs = lap + ph * (T(1) - ph * ph) - kap * gm;
+      const T rhs = cur_base[k] - kap * cur_gm[k];
       const bool in = xin && y < a.ny;
-      if (in) a.dst[(size_t)z * plane + (size_t)y * a.nx + x] = ph + a.dtau * rhs;
+      if (in) a.dst[(size_t)z * plane + (size_t)y * a.nx + x] = cur_ph[k] + a.dtau * rhs;
       rmax = in ? fmax(rmax, fabs(rhs)) : rmax;
     }
   };
 
-  // ring slots (element offsets): phi planes z-2 .. z+2 and normal planes
+  // ring slots (element offsets): phi planes z-1 .. z+2 and normal planes
   // z-1 .. z+1 at step z, rotated by one plane per step
-  int s0 = 0, s1 = kPPlane, s2 = 2 * kPPlane, s3 = 3 * kPPlane, s4 = 4 * kPPlane;
+  int s0 = 0, s1 = kPPlane, s2 = 2 * kPPlane, s3 = 3 * kPPlane;
   int nm = 0, n0 = 3 * kNPlane, np = 6 * kNPlane;
 
-  // prologue: phi planes z0-2 .. z0+1 stored, z0+2 in flight; normals on
-  // z0-1 and z0
+  // prologue: phi planes z0-2 .. z0+1 (the z0-2 plane in the slot that
+  // plane z0+2 takes next), z0+2 in flight; normals on z0-1 and z0, the
+  // prepared terms of z0
   fetch(z0 - 2);
-  store(s0);
-  fetch(z0 - 1);
-  store(s1);
-  fetch(z0);
-  store(s2);
-  fetch(z0 + 1);
   store(s3);
+  fetch(z0 - 1);
+  store(s0);
+  fetch(z0);
+  store(s1);
+  fetch(z0 + 1);
+  store(s2);
   fetch(z0 + 2);
   __syncthreads();
-  normals(s0, s1, s2, nm);
-  normals(s1, s2, s3, n0);
+  prepare(s3, s0, s1, nm);         // plane z0-1 (only its normals are used)
+  prepare(s0, s1, s2, n0);         // plane z0
+  __syncthreads();                 // plane z0-2 (slot s3) is overwritten next
+#pragma unroll
+  for (int k = 0; k < kRows; ++k) {
+    cur_ph[k] = nxt_ph[k];
+    cur_base[k] = nxt_base[k];
+    cur_gm[k] = nxt_gm[k];
+  }
   for (int z = z0; z < z1; ++z) {
-    // phi: s0 = z-2 (free: last read by the update of z-2 and the normals
-    // of z-2, both before the previous step's barriers), s1 = z-1, s2 = z,
-    // s3 = z+1, s4 = z+2
-    store(s4);
+    // phi: s0 = z-1, s1 = z, s2 = z+1, s3 = free (plane z-2, last read by the
+    // preparation of z-1 before the previous step's barriers)
+    store(s3);
     if (z + 1 < z1) fetch(z + 3);
     __syncthreads();
-    normals(s2, s3, s4, np);   // overwrites normals of z-2, last read by the update of z-1
+    prepare(s1, s2, s3, np);   // plane z+1; overwrites normals of z-2, last read by the update of z-1
     __syncthreads();
-    update(z, s1, s2, s3, nm, n0, np);
+    update(z, nm, n0, np);
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      cur_ph[k] = nxt_ph[k];
+      cur_base[k] = nxt_base[k];
+      cur_gm[k] = nxt_gm[k];
+    }
     const int f = s0;
-    s0 = s1; s1 = s2; s2 = s3; s3 = s4; s4 = f;
+    s0 = s1; s1 = s2; s2 = s3; s3 = f;
     const int g = nm;
     nm = n0; n0 = np; np = g;
   }

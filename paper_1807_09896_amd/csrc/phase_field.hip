@@ -76,15 +76,17 @@ __device__ __forceinline__ void res_max(void *res, double v) {
 }
 
 // Per step z the block (1) stores phi plane z+2, fetched a step earlier, (2)
-// prepares plane z+1: for its own nodes the Laplacian term, |grad' phi| and
-// phi stay in registers and the unit normal goes to LDS; the 148 normal
-// nodes of the halo are computed by the first threads; (3) updates plane z
-// from the registers prepared a step earlier and the divergence of the
-// normals in LDS.
+// prepares plane z+1: for its own nodes the Laplacian and reaction terms,
+// |grad' phi|, phi and the normal's z component stay in registers and the
+// normal's x and y components go to LDS; the 148 normal nodes of the halo
+// are computed by the first threads; (3) updates plane z from the registers
+// prepared a step earlier and the divergence of the normals.  The
+// divergence needs n_z only in a node's own column (planes z-1 and z+1), so
+// n_z never leaves the thread.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_phi_relax(RelaxArgs<T> a) {
   __shared__ T sphi[kRing * kPPlane];
-  __shared__ T sn[3 * 3 * kNPlane];   // [ring slot][component][node]
+  __shared__ T sn[2 * 2 * kNPlane];   // [ring slot][x, y component][node]
 
   // tile of this block: the blocks of one XCD (dispatch is round-robin over
   // the eight XCDs) take a contiguous range of tiles
@@ -114,9 +116,9 @@ __global__ __launch_bounds__(kThreads) void k_phi_relax(RelaxArgs<T> a) {
     loff[s] = wrap(y0 + ly - 2, a.ny) * a.nx + wrap(x0 + lx - 2, a.nx);
   }
   // this thread's halo normal (tid < kHalo): the rows above and below the
-  // tile, then the columns left and right of it
+  // tile, then the columns left and right of it; its phi-plane centre
   const bool has_halo = tid < kHalo;
-  int hn = 0;
+  int hn = 0, hc = 0;
   {
     int lx, ly;
     if (tid < kNW) {
@@ -124,10 +126,11 @@ __global__ __launch_bounds__(kThreads) void k_phi_relax(RelaxArgs<T> a) {
     } else if (tid < 2 * kNW) {
       ly = kNH - 1, lx = tid - kNW;
     } else {
-      const int k = tid - 2 * kNW;          // 0 .. 2 kBY - 1
+      const int k = tid - 2 * kNW;          // 0 .. 2 kBY - 1 for halo threads
       ly = 1 + (k >> 1), lx = (k & 1) ? kNW - 1 : 0;
     }
     hn = has_halo ? ly * kNW + lx : 0;
+    hc = has_halo ? (ly + 1) * kPW + lx + 1 : kPW + 1;
   }
 
   T pre[kLoadSlots];
@@ -140,39 +143,28 @@ __global__ __launch_bounds__(kThreads) void k_phi_relax(RelaxArgs<T> a) {
 #pragma unroll
     for (int s = 0; s < kLoadSlots; ++s) sphi[base + lslot[s]] = pre[s];
   };
-  // unit normal at normal-plane node m from the phi planes below (pm), at
-  // (p0) and above (pp); returns grad' phi
-  auto normal_at = [&](int pm, int p0, int pp, int nb, int m, T &ux, T &uy, T &uz) {
-    const int ly = m / kNW, lx = m - ly * kNW;
-    const int c = (ly + 1) * kPW + lx + 1;
-    ux = a.gx * (sphi[p0 + c + 1] - sphi[p0 + c - 1]);
-    uy = a.gy * (sphi[p0 + c + kPW] - sphi[p0 + c - kPW]);
-    uz = a.gz * (sphi[pp + c] - sphi[pm + c]);
-    const T s2 = ux * ux + uy * uy + uz * uz;
-    const T inv = fast_rsqrt(fmax(s2, a.delta2));
-    sn[nb + m] = ux * inv;
-    sn[nb + kNPlane + m] = uy * inv;
-    sn[nb + 2 * kNPlane + m] = uz * inv;
-    return s2;
-  };
 
   const int tx = tid % kBX, ty0 = tid / kBX;
   const int x = x0 + tx;
   const bool xin = x < a.nx;
   T rmax = T(0);
-  // prepared terms of this thread's nodes: phi, the Laplacian term plus the
-  // reaction term, and |grad' phi|
+  // per own node k: phi on the planes below, at and above the plane being
+  // prepared (om, o0, op), the prepared terms of the plane being updated
+  // (cur_*) and of the next one (nxt_*), n_z on planes z-1, z and z+1
+  T om[kRows], o0[kRows];
   T cur_ph[kRows], cur_base[kRows], cur_gm[kRows];
-  T nxt_ph[kRows], nxt_base[kRows], nxt_gm[kRows];
+  T nxt_base[kRows], nxt_gm[kRows];
+  T nz_m[kRows], nz_0[kRows], nz_p[kRows];
+#pragma unroll
+  for (int k = 0; k < kRows; ++k) nz_m[k] = nz_0[k] = nz_p[k] = T(0);
   auto prepare = [&](int pm, int p0, int pp, int nb) {
 #pragma unroll
     for (int k = 0; k < kRows; ++k) {
       const int ty = ty0 + k * (kThreads / kBX);
       const int c = (ty + 2) * kPW + tx + 2;
-      const T ph = sphi[p0 + c];
+      const T ph = o0[k], zm = om[k], zp = sphi[pp + c];
       const T xm = sphi[p0 + c - 1], xp = sphi[p0 + c + 1];
       const T ym = sphi[p0 + c - kPW], yp = sphi[p0 + c + kPW];
-      const T zm = sphi[pm + c], zp = sphi[pp + c];
       const T lap = a.cx * (xp - T(2) * ph + xm) + a.cy * (yp - T(2) * ph + ym) +
                     a.cz * (zp - T(2) * ph + zm);
       const T ux = a.gx * (xp - xm), uy = a.gy * (yp - ym), uz = a.gz * (zp - zm);
@@ -181,19 +173,27 @@ __global__ __launch_bounds__(kThreads) void k_phi_relax(RelaxArgs<T> a) {
       const int m = (ty + 1) * kNW + tx + 1;
       sn[nb + m] = ux * inv;
       sn[nb + kNPlane + m] = uy * inv;
-      sn[nb + 2 * kNPlane + m] = uz * inv;
-      nxt_ph[k] = ph;
+      nz_p[k] = uz * inv;
       nxt_base[k] = lap + ph * (T(1) - ph * ph);
       nxt_gm[k] = fast_sqrt(s2);
+      om[k] = ph;
+      o0[k] = zp;
     }
     if (has_halo) {
-      T ux, uy, uz;
-      normal_at(pm, p0, pp, nb, hn, ux, uy, uz);
+      // the halo needs n_x (columns) or n_y (rows) only; both are written
+      const int c = hc;
+      const T ux = a.gx * (sphi[p0 + c + 1] - sphi[p0 + c - 1]);
+      const T uy = a.gy * (sphi[p0 + c + kPW] - sphi[p0 + c - kPW]);
+      const T uz = a.gz * (sphi[pp + c] - sphi[pm + c]);
+      const T inv = fast_rsqrt(fmax(ux * ux + uy * uy + uz * uz, a.delta2));
+      sn[nb + hn] = ux * inv;
+      sn[nb + kNPlane + hn] = uy * inv;
     }
   };
   // explicit Euler update of this thread's nodes of plane z from the
-  // prepared terms and the normals of planes z-1, z, z+1 at nm, n0, np
-  auto update = [&](int z, int nm, int n0, int np) {
+  // prepared terms, the normals' x and y components of plane z at n0 and
+  // n_z of planes z-1 and z+1
+  auto update = [&](int z, int n0) {
 #pragma unroll
     for (int k = 0; k < kRows; ++k) {
       // nodes past a ragged grid edge are computed from the wrapped values
@@ -203,22 +203,32 @@ __global__ __launch_bounds__(kThreads) void k_phi_relax(RelaxArgs<T> a) {
       const int cn = (ty + 1) * kNW + tx + 1;
       const T kap = a.gx * (sn[n0 + cn + 1] - sn[n0 + cn - 1]) +
                     a.gy * (sn[n0 + kNPlane + cn + kNW] - sn[n0 + kNPlane + cn - kNW]) +
-                    a.gz * (sn[np + 2 * kNPlane + cn] - sn[nm + 2 * kNPlane + cn]);
+                    a.gz * (nz_p[k] - nz_m[k]);
       const T rhs = cur_base[k] - kap * cur_gm[k];
       const bool in = xin && y < a.ny;
       if (in) a.dst[(size_t)z * plane + (size_t)y * a.nx + x] = cur_ph[k] + a.dtau * rhs;
       rmax = in ? fmax(rmax, fabs(rhs)) : rmax;
     }
   };
+  auto advance = [&]() {           // the prepared plane becomes the current one
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      cur_ph[k] = om[k];
+      cur_base[k] = nxt_base[k];
+      cur_gm[k] = nxt_gm[k];
+      nz_m[k] = nz_0[k];
+      nz_0[k] = nz_p[k];
+    }
+  };
 
-  // ring slots (element offsets): phi planes z-1 .. z+2 and normal planes
-  // z-1 .. z+1 at step z, rotated by one plane per step
+  // ring slots (element offsets): phi planes z-1 .. z+2 at step z (s3 free),
+  // normal x/y planes z (nc) and z+1 (nn)
   int s0 = 0, s1 = kPPlane, s2 = 2 * kPPlane, s3 = 3 * kPPlane;
-  int nm = 0, n0 = 3 * kNPlane, np = 6 * kNPlane;
+  int nc = 0, nn = 2 * kNPlane;
 
-  // prologue: phi planes z0-2 .. z0+1 (the z0-2 plane in the slot that
-  // plane z0+2 takes next), z0+2 in flight; normals on z0-1 and z0, the
-  // prepared terms of z0
+  // prologue: phi planes z0-2 .. z0+1 (z0-2 in the slot that plane z0+2
+  // takes next), z0+2 in flight; the thread's own phi on z0-2 and z0-1;
+  // planes z0-1 and z0 prepared
   fetch(z0 - 2);
   store(s3);
   fetch(z0 - 1);
@@ -229,34 +239,31 @@ __global__ __launch_bounds__(kThreads) void k_phi_relax(RelaxArgs<T> a) {
   store(s2);
   fetch(z0 + 2);
   __syncthreads();
-  prepare(s3, s0, s1, nm);         // plane z0-1 (only its normals are used)
-  prepare(s0, s1, s2, n0);         // plane z0
-  __syncthreads();                 // plane z0-2 (slot s3) is overwritten next
 #pragma unroll
   for (int k = 0; k < kRows; ++k) {
-    cur_ph[k] = nxt_ph[k];
-    cur_base[k] = nxt_base[k];
-    cur_gm[k] = nxt_gm[k];
+    const int c = (ty0 + k * (kThreads / kBX) + 2) * kPW + tx + 2;
+    om[k] = sphi[s3 + c];
+    o0[k] = sphi[s0 + c];
   }
+  prepare(s3, s0, s1, nn);         // plane z0-1: its n_z is used, its n_x, n_y are not
+  advance();
+  prepare(s0, s1, s2, nc);         // plane z0
+  advance();
+  __syncthreads();                 // plane z0-2 (slot s3) is overwritten next
   for (int z = z0; z < z1; ++z) {
     // phi: s0 = z-1, s1 = z, s2 = z+1, s3 = free (plane z-2, last read by the
     // preparation of z-1 before the previous step's barriers)
     store(s3);
     if (z + 1 < z1) fetch(z + 3);
     __syncthreads();
-    prepare(s1, s2, s3, np);   // plane z+1; overwrites normals of z-2, last read by the update of z-1
+    prepare(s1, s2, s3, nn);   // plane z+1 into the normal slot of z-1, last read by the update of z-1
     __syncthreads();
-    update(z, nm, n0, np);
-#pragma unroll
-    for (int k = 0; k < kRows; ++k) {
-      cur_ph[k] = nxt_ph[k];
-      cur_base[k] = nxt_base[k];
-      cur_gm[k] = nxt_gm[k];
-    }
+    update(z, nc);
+    advance();
     const int f = s0;
     s0 = s1; s1 = s2; s2 = s3; s3 = f;
-    const int g = nm;
-    nm = n0; n0 = np; np = g;
+    const int g = nc;
+    nc = nn; nn = g;
   }
 
   if (a.res) {

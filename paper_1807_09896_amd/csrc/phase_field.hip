@@ -30,8 +30,8 @@
 namespace dpd {
 namespace {
 
-constexpr int kBX = 64, kBY = 8, kTZ = 64;
-constexpr int kThreads = 256;
+constexpr int kBX = 64, kBY = 16, kTZ = 64;
+constexpr int kThreads = 512;
 constexpr int kRows = kBY * kBX / kThreads;   // nodes per thread in a plane (rows ty, ty + 4)
 constexpr int kRing = 4;                      // phi planes z-1 .. z+2 at step z
 constexpr int kPW = kBX + 4, kPH = kBY + 4;   // phi plane with a 2-node halo

@@ -16,7 +16,7 @@
 // next plane (each thread's own nodes: the Laplacian and reaction terms and
 // |grad' phi| into registers, the unit normal into LDS; the halo normals by
 // the first threads) and updates the current plane from its registers and
-// the divergence of the normals, with two barriers.  The global loads of a
+// the divergence of the normals, with one barrier.  The global loads of a
 // plane are issued one step before its LDS store, so their latency overlaps
 // a step of work.  Each node's stencil is read once, phi is read from HBM
 // about once per node (the x/y halo and the planes before a chunk come from
@@ -256,8 +256,11 @@ __global__ __launch_bounds__(kThreads) void k_phi_relax(RelaxArgs<T> a) {
     store(s3);
     if (z + 1 < z1) fetch(z + 3);
     __syncthreads();
-    prepare(s1, s2, s3, nn);   // plane z+1 into the normal slot of z-1, last read by the update of z-1
-    __syncthreads();
+    // plane z+1 into the normal slot of z-1, last read by the update of z-1
+    // (before this step's barrier); the update of z reads only the normals
+    // of z, written before this step's barrier, and registers, so no second
+    // barrier is needed
+    prepare(s1, s2, s3, nn);
     update(z, nc);
     advance();
     const int f = s0;

@@ -358,6 +358,29 @@ int dpd_pair_random(uint64_t seed, uint64_t k, uint32_t replica, const uint32_t 
  * hardware byte counters are calibrated against. */
 int dpd_copy_probe(void *dst, const void *src, size_t bytes, void *hip_stream);
 
+/* ---- Snapshots (checkpoint and restart of a run) ----
+ * The complete dynamic state of a context: every box's particles in the
+ * library's internal cell-sorted order (positions with gids, velocities
+ * with the last step's event codes, the forces carried into the next step,
+ * wall positions and velocities), the force evaluation index k, the step
+ * and event counters.  A context restored from a snapshot continues
+ * bit-identically to the one it was taken from (dpd_set_state, which takes
+ * gid-ordered rows, re-sorts and so continues only to within rounding).
+ * Parameters, phase fields and launch shapes are the context's own and are
+ * not in the snapshot. */
+
+/* Bytes of a snapshot of ctx (a host buffer of this size holds one), or
+ * DPD_E_INVAL for NULL. */
+int64_t dpd_snapshot_size(const dpd_ctx *ctx);
+
+/* dir 0: write ctx's state into blob (host memory, dpd_snapshot_size bytes,
+ * owned by the caller); synchronises the stream first.  dir 1: restore
+ * ctx's state from blob; the context must have been created from the same
+ * boxes (same particle counts, cells and phase-field grids, same resting
+ * wall particles), else DPD_E_INVAL and the context is unchanged.  Captured
+ * step graphs are dropped on restore.  Synchronises. */
+int dpd_snapshot_io(dpd_ctx *ctx, int32_t dir, void *blob);
+
 /* ---- Phase-field relaxation (Sec. II.B, Eq. 13-15) ----
  * Integrates d phi / d t' = lap' phi + phi (1 - phi^2) - kappa |grad' phi|
  * with kappa = div'(grad' phi / |grad' phi|) and grad' = eps grad (Eq. 15)

@@ -136,6 +136,16 @@ class Simulation:
         if r == 0:
             self.params = dict(params)
 
+    def snapshot(self):
+        """The complete dynamic state as bytes (checkpoint); restore() of it
+        continues bit-identically."""
+        blob = np.empty(binding.dpd_snapshot_size(self.ctx), dtype=np.uint8)
+        binding.dpd_snapshot_io(self.ctx, 0, blob)
+        return blob
+
+    def restore(self, blob):
+        binding.dpd_snapshot_io(self.ctx, 1, np.ascontiguousarray(blob, dtype=np.uint8))
+
     def set_phi(self, phi, r=0):
         binding.dpd_set_phi(self.ctx, r, phi)
 

@@ -39,7 +39,8 @@ EXPORTED = ["dpd_create", "dpd_step", "dpd_forces", "dpd_get_state", "dpd_set_st
             "dpd_pair_random", "dpd_batch_create", "dpd_replica_count", "dpd_replica_forces",
             "dpd_replica_state", "dpd_replica_set_state", "dpd_replica_pairs",
             "dpd_replica_profile", "dpd_use_graph", "dpd_autotune", "dpd_set_params",
-            "dpd_set_phi", "dpd_window_forward", "dpd_backward", "dpd_phi_relax"]
+            "dpd_set_phi", "dpd_window_forward", "dpd_backward", "dpd_phi_relax",
+            "dpd_snapshot_size", "dpd_snapshot_io"]
 
 
 class DPDError(RuntimeError):
@@ -119,6 +120,10 @@ def load_library(path: str = LIB_PATH):
     L.dpd_destroy.restype = None
     L.dpd_copy_probe.argtypes = [P, P, C.c_size_t, P]
     L.dpd_copy_probe.restype = C.c_int
+    L.dpd_snapshot_size.argtypes = [P]
+    L.dpd_snapshot_size.restype = C.c_int64
+    L.dpd_snapshot_io.argtypes = [P, C.c_int32, P]
+    L.dpd_snapshot_io.restype = C.c_int
     L.dpd_phi_relax.argtypes = [P, P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                 C.c_double, C.c_double, C.c_int32, C.POINTER(C.c_double), P]
     L.dpd_phi_relax.restype = C.c_int
@@ -417,6 +422,21 @@ def dpd_destroy(ctx):
 
 def dpd_copy_probe(dst, src, nbytes, stream=None):
     _check(load_library().dpd_copy_probe(_ptr(dst), _ptr(src), int(nbytes), _stream_handle(stream)))
+
+
+def dpd_snapshot_size(ctx):
+    n = load_library().dpd_snapshot_size(ctx)
+    if n < 0:
+        _check(int(n), ctx)
+    return int(n)
+
+
+def dpd_snapshot_io(ctx, dir_, blob):
+    """dir_ 0 writes the context state into blob (a writable host uint8
+    numpy array of dpd_snapshot_size bytes), 1 restores it from blob."""
+    if blob.dtype != np.uint8 or not blob.flags["C_CONTIGUOUS"] or blob.nbytes < dpd_snapshot_size(ctx):
+        raise ValueError("blob must be a contiguous uint8 array of dpd_snapshot_size bytes")
+    _check(load_library().dpd_snapshot_io(ctx, int(dir_), C.c_void_p(blob.ctypes.data)), ctx)
 
 
 def dpd_phi_relax(phi, work, h, eps, dtau, iters, residual=True, stream=None):

@@ -1654,6 +1654,131 @@ int dpd_copy_probe(void *dst, const void *src, size_t bytes, void *hip_stream) {
   return e == hipSuccess ? DPD_OK : DPD_E_DEVICE;
 }
 
+// ---- Snapshots ----
+// Blob: header, then the cell-sorted device arrays of the current state:
+// positions of fluid and walls (NF + NW float4, gid bits in w), fluid
+// velocities with the last event code (NF float4), fluid forces (NF float4)
+// and wall velocities (NW float4).
+namespace {
+struct SnapHeader {
+  char magic[8];
+  uint32_t version, R;
+  int64_t NF, NW, NCELL, NGRID;
+  uint64_t k;
+  int64_t steps;
+  uint64_t wall_hash;   // FNV-1a of the wall positions (resting walls must match)
+  Status status;
+};
+constexpr char kSnapMagic[8] = {'D', 'P', 'D', 'S', 'N', 'A', 'P', '1'};
+constexpr uint32_t kSnapVersion = 1;
+
+uint64_t fnv1a(const void *p, size_t n) {
+  const unsigned char *b = (const unsigned char *)p;
+  uint64_t h = 1469598103934665603ull;
+  for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  return h;
+}
+
+size_t snap_bytes(const dpd_ctx *c) {
+  return sizeof(SnapHeader) + (size_t)c->R * 4 * sizeof(int64_t) +
+         16 * (size_t)(2 * c->NF + 2 * c->NW + c->NF);
+}
+}  // namespace
+
+int64_t dpd_snapshot_size(const dpd_ctx *c) {
+  if (!c) return DPD_E_INVAL;
+  return (int64_t)snap_bytes(c);
+}
+
+int dpd_snapshot_io(dpd_ctx *c, int32_t dir, void *blob) {
+  if (!c) return DPD_E_INVAL;
+  if (!blob) return fail(c, DPD_E_INVAL, "snapshot blob is NULL");
+  if (dir != 0 && dir != 1) return fail(c, DPD_E_INVAL, "dir must be 0 (save) or 1 (restore)");
+  const int a = c->cur;
+  char *p = (char *)blob;
+  SnapHeader *hd = (SnapHeader *)p;
+  int64_t *layout = (int64_t *)(p + sizeof(SnapHeader));
+  char *arr = p + sizeof(SnapHeader) + (size_t)c->R * 4 * sizeof(int64_t);
+  const size_t bpos = 16 * (size_t)(c->NF + c->NW), bf = 16 * (size_t)c->NF,
+               bw = 16 * (size_t)c->NW;
+  char *apos = arr, *avel = arr + bpos, *afrc = avel + bf, *awv = afrc + bf;
+  // the walls as they are in the context now (for the hash)
+  std::vector<float4> walls((size_t)c->NW);
+  if (c->NW)
+    HIP_TRY(c, hipMemcpyAsync(walls.data(), c->pos[a] + c->NF, bw, hipMemcpyDeviceToHost,
+                              c->stream));
+  if (dir == 0) {
+    Status st;
+    int rc = read_status(c, st);   // synchronises
+    if (rc) return rc;
+    memcpy(hd->magic, kSnapMagic, 8);
+    hd->version = kSnapVersion;
+    hd->R = (uint32_t)c->R;
+    hd->NF = c->NF;
+    hd->NW = c->NW;
+    hd->NCELL = c->NCELL;
+    hd->NGRID = c->NGRID;
+    hd->k = c->k;
+    hd->steps = c->steps;
+    hd->wall_hash = fnv1a(walls.data(), bw);
+    hd->status = st;
+    for (int r = 0; r < c->R; ++r) {
+      layout[4 * r + 0] = c->rep[r].nf;
+      layout[4 * r + 1] = c->rep[r].nw;
+      layout[4 * r + 2] = c->rep[r].ncell;
+      layout[4 * r + 3] = c->rep[r].moving ? 1 : 0;
+    }
+    HIP_TRY(c, hipMemcpyAsync(apos, c->pos[a], bpos, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(avel, c->vel[a], bf, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(afrc, c->frc[a], bf, hipMemcpyDeviceToHost, c->stream));
+    if (c->NW)
+      HIP_TRY(c, hipMemcpyAsync(awv, c->vt + c->NF, bw, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return DPD_OK;
+  }
+  // restore: the blob must describe this context's layout
+  if (memcmp(hd->magic, kSnapMagic, 8) != 0 || hd->version != kSnapVersion)
+    return fail(c, DPD_E_INVAL, "not a snapshot of this library version");
+  if (hd->R != (uint32_t)c->R || hd->NF != c->NF || hd->NW != c->NW || hd->NCELL != c->NCELL ||
+      hd->NGRID != c->NGRID)
+    return fail(c, DPD_E_INVAL, "snapshot of a context with another layout");
+  bool any_moving = false;
+  for (int r = 0; r < c->R; ++r) {
+    const Replica &q = c->rep[r];
+    if (layout[4 * r + 0] != q.nf || layout[4 * r + 1] != q.nw ||
+        layout[4 * r + 2] != q.ncell || layout[4 * r + 3] != (q.moving ? 1 : 0))
+      return fail(c, DPD_E_INVAL, "snapshot of a context with other boxes");
+    any_moving = any_moving || q.moving;
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  // resting walls never move: the snapshot's must be this context's
+  if (!any_moving && c->NW && fnv1a(walls.data(), bw) != hd->wall_hash)
+    return fail(c, DPD_E_INVAL, "snapshot of a context with other wall particles");
+  drop_graphs(c);
+  HIP_TRY(c, hipMemcpyAsync(c->pos[a], apos, bpos, hipMemcpyHostToDevice, c->stream));
+  if (c->NW)
+    HIP_TRY(c, hipMemcpyAsync(c->pos[1 - a] + c->NF, apos + bf, bw, hipMemcpyHostToDevice,
+                              c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->vel[a], avel, bf, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->frc[a], afrc, bf, hipMemcpyHostToDevice, c->stream));
+  if (c->NW)
+    HIP_TRY(c, hipMemcpyAsync(c->vt + c->NF, awv, bw, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->status, &hd->status, sizeof(Status), hipMemcpyHostToDevice,
+                            c->stream));
+  c->k = hd->k;
+  c->steps = hd->steps;
+  HIP_TRY(c, hipMemcpyAsync(c->dk, &c->k, 8, hipMemcpyHostToDevice, c->stream));
+  // moving walls: their cell runs follow the restored positions (the sort
+  // within cells keeps the restored order)
+  if (c->moving) {
+    int rc = wall_pass(c, c->stream, 0);
+    if (rc) return rc;
+  }
+  c->gen += 1;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return latched_error(c);
+}
+
 int dpd_phi_relax(void *phi, void *work, int32_t dtype, const int32_t n[3], const double h[3],
                   double eps, double dtau, int32_t iters, double *residual, void *hip_stream) {
   if (!phi || !work || !n || !h) return fail(nullptr, DPD_E_INVAL, "NULL argument");

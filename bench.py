@@ -86,6 +86,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="porous168",
                     choices=["porous168", "porous128", "channel", "slab"])
+    ap.add_argument("--graph", action="store_true",
+                    help="replay each step of the main run as a captured HIP graph")
     ap.add_argument("--timing-steps", type=int, default=20,
                     help="steps of the per-kernel HIP-event pass")
     ap.add_argument("--cpu-steps", type=int, default=2,
@@ -127,7 +129,7 @@ def main():
     log("workload %s: %d particles (%d fluid, %d wall), phi %s %s, generated in %.1fs"
         % (system.name, system.n, system.n_fluid, system.n_wall, system.phi.shape,
            system.phi.dtype, time.time() - t0))
-    sim = dpd.Simulation(system)
+    sim = dpd.Simulation(system, graph=args.graph)
     cnt0 = sim.counters()
     log("created:", cnt0)
 
@@ -243,7 +245,8 @@ def main():
         "config": {"workload": system.name, "particles": system.n, "fluid": nf, "wall": nw,
                    "box": [float(x) for x in system.L], "density": 4.0 if "porous" in system.name else 3.0,
                    "phi_grid": list(system.phi.shape), "phi_dtype": str(system.phi.dtype),
-                   "dt": system.params["dt"], "parallelism": "single GPU"},
+                   "dt": system.params["dt"], "graph": bool(args.graph),
+                   "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "kernel": "pair_force", "achieved": achieved_tops,
                      "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved_tops / VALU_PEAK_TOPS,
                      "traffic": traffic, "avg_launch_ms": force_ms,

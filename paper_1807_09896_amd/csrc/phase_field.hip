@@ -134,8 +134,8 @@ __global__ __launch_bounds__(kThreads) void k_phi_relax(RelaxArgs<T> a) {
   }
 
   T pre[kLoadSlots];
-  auto fetch = [&](int z) {        // global loads of phi plane z into registers
-    const T *p = a.src + (size_t)wrap(z, a.nz) * plane;
+  auto fetch = [&](int zw) {       // global loads of phi plane zw (wrapped) into registers
+    const T *p = a.src + (size_t)zw * plane;
 #pragma unroll
     for (int s = 0; s < kLoadSlots; ++s) pre[s] = p[loff[s]];
   };
@@ -193,7 +193,7 @@ __global__ __launch_bounds__(kThreads) void k_phi_relax(RelaxArgs<T> a) {
   // explicit Euler update of this thread's nodes of plane z from the
   // prepared terms, the normals' x and y components of plane z at n0 and
   // n_z of planes z-1 and z+1
-  auto update = [&](int z, int n0) {
+  auto update = [&](T *zdst, int n0) {
 #pragma unroll
     for (int k = 0; k < kRows; ++k) {
       // nodes past a ragged grid edge are computed from the wrapped values
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(kThreads) void k_phi_relax(RelaxArgs<T> a) {
                     a.gz * (nz_p[k] - nz_m[k]);
       const T rhs = cur_base[k] - kap * cur_gm[k];
       const bool in = xin && y < a.ny;
-      if (in) a.dst[(size_t)z * plane + (size_t)y * a.nx + x] = cur_ph[k] + a.dtau * rhs;
+      if (in) zdst[(size_t)y * a.nx + x] = cur_ph[k] + a.dtau * rhs;
       rmax = in ? fmax(rmax, fabs(rhs)) : rmax;
     }
   };
@@ -229,15 +229,16 @@ __global__ __launch_bounds__(kThreads) void k_phi_relax(RelaxArgs<T> a) {
   // prologue: phi planes z0-2 .. z0+1 (z0-2 in the slot that plane z0+2
   // takes next), z0+2 in flight; the thread's own phi on z0-2 and z0-1;
   // planes z0-1 and z0 prepared
-  fetch(z0 - 2);
+  fetch(wrap(z0 - 2, a.nz));
   store(s3);
-  fetch(z0 - 1);
+  fetch(wrap(z0 - 1, a.nz));
   store(s0);
-  fetch(z0);
+  fetch(wrap(z0, a.nz));
   store(s1);
-  fetch(z0 + 1);
+  fetch(wrap(z0 + 1, a.nz));
   store(s2);
-  fetch(z0 + 2);
+  int zf = wrap(z0 + 2, a.nz);     // wrapped index of the plane in flight
+  fetch(zf);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kRows; ++k) {
@@ -250,18 +251,20 @@ __global__ __launch_bounds__(kThreads) void k_phi_relax(RelaxArgs<T> a) {
   prepare(s0, s1, s2, nc);         // plane z0
   advance();
   __syncthreads();                 // plane z0-2 (slot s3) is overwritten next
-  for (int z = z0; z < z1; ++z) {
+  T *zdst = a.dst + (size_t)z0 * plane;
+  for (int z = z0; z < z1; ++z, zdst += plane) {
     // phi: s0 = z-1, s1 = z, s2 = z+1, s3 = free (plane z-2, last read by the
     // preparation of z-1 before the previous step's barriers)
     store(s3);
-    if (z + 1 < z1) fetch(z + 3);
+    zf = zf + 1 == a.nz ? 0 : zf + 1;   // plane z+3
+    if (z + 1 < z1) fetch(zf);
     __syncthreads();
     // plane z+1 into the normal slot of z-1, last read by the update of z-1
     // (before this step's barrier); the update of z reads only the normals
     // of z, written before this step's barrier, and registers, so no second
     // barrier is needed
     prepare(s1, s2, s3, nn);
-    update(z, nc);
+    update(zdst, nc);
     advance();
     const int f = s0;
     s0 = s1; s1 = s2; s2 = s3; s3 = f;

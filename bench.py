@@ -90,7 +90,7 @@ def main():
                     help="replay each step of the main run as a captured HIP graph")
     ap.add_argument("--timing-steps", type=int, default=20,
                     help="steps of the per-kernel HIP-event pass")
-    ap.add_argument("--cpu-steps", type=int, default=2,
+    ap.add_argument("--cpu-steps", type=int, default=3,
                     help="oracle steps of the CPU baseline (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=100,
                     help="steps of the 256-replica batch leg and of its sequential "

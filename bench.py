@@ -86,6 +86,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="porous168",
                     choices=["porous168", "porous128", "channel", "slab"])
+    ap.add_argument("--autotune", action="store_true",
+                    help="let the library's autotuner pick the launch shapes of the main run")
     ap.add_argument("--graph", action="store_true",
                     help="replay each step of the main run as a captured HIP graph")
     ap.add_argument("--timing-steps", type=int, default=20,
@@ -132,6 +134,11 @@ def main():
     sim = dpd.Simulation(system, graph=args.graph)
     cnt0 = sim.counters()
     log("created:", cnt0)
+    shape = None
+    if args.autotune:
+        shape, trials = sim.autotune(5)
+        log("autotuned shape (particles/thread, force block) = %s; trial ms/step %s"
+            % (shape, ["%.3f" % t for t in trials]))
 
     sim.step(args.warmup)
     sim.sync()
@@ -246,6 +253,7 @@ def main():
                    "box": [float(x) for x in system.L], "density": 4.0 if "porous" in system.name else 3.0,
                    "phi_grid": list(system.phi.shape), "phi_dtype": str(system.phi.dtype),
                    "dt": system.params["dt"], "graph": bool(args.graph),
+                   "launch_shape": list(shape) if shape else None,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "kernel": "pair_force", "achieved": achieved_tops,
                      "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved_tops / VALU_PEAK_TOPS,

@@ -345,6 +345,36 @@ def test_edge_cases(dpd, oracle_lib):
     sim.close()
 
 
+def test_particle_on_the_interface_and_non_finite_state(dpd, oracle_lib):
+    """A fluid particle exactly on the phi = 0 plane (a grid node of the
+    slab interface, where phi interpolates to zero) is accepted (Sec. II.C:
+    a bounce needs phi < 0) and, sent into the wall, bounces back with the
+    oracle's event and position; a NaN velocity set into a running context
+    is reported as DPD_E_UNSTABLE at the next synchronisation."""
+    s = workloads.tiny_slab_system()
+    i = int(np.nonzero(s.type == 0)[0][5])
+    pos, vel = s.pos.copy(), s.vel.copy()
+    lo = s.meta["lo"]
+    pos[i] = np.asarray([1.0, 1.0, lo], np.float32)
+    vel[i] = np.asarray([0.3, 0.0, -2.0], np.float32)
+    s.pos, s.vel = pos, vel
+    assert trilinear_f64(s.phi, s.h, pos[i:i + 1].astype(np.float64))[0] == 0.0
+    n_ev = _one_step_compare(dpd, oracle_lib, s)
+    assert n_ev >= 1
+    sim = dpd.Simulation(workloads.tiny_slab_system())
+    sim.step(2)
+    st = {k: v.cpu().numpy() for k, v in sim.state().items()}
+    f = sim.forces().cpu().numpy()
+    v = st["vel"].copy()
+    v[np.nonzero(workloads.tiny_slab_system().type == 0)[0][0]] = np.nan
+    c = sim.counters()
+    sim.set_state(st["pos"], v, f, c["k"])
+    sim.step(1)
+    with pytest.raises(dpd.DPDError, match="DPD_E_UNSTABLE"):
+        sim.sync()
+    sim.close()
+
+
 def test_random_stream_matches_oracle(dpd, oracle_lib):
     """The GPU's Philox4x32-10 words equal the oracle's bit for bit, and its
     FP32 Box-Muller xi (hardware log2, sqrt and cos) stays within 3e-5 of the

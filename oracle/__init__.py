@@ -22,16 +22,20 @@ _SRC = os.path.join(_HERE, "dpd_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 
-def build_oracle(force: bool = True) -> str:
+def build_oracle(force: bool = True, sanitize: bool = False, path: str | None = None) -> str:
     """Compile the oracle with gcc (no contraction, so FP32 decisions follow
-    the written op order)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
+    the written op order).  sanitize=True builds it with the undefined-
+    behaviour sanitizer, aborting on the first report, into `path`."""
+    out = path or _LIB
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        tmp = out + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-ffp-contract=off",
                "-fno-fast-math", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+        if sanitize:
+            cmd[1:1] = ["-g", "-fsanitize=undefined", "-fno-sanitize-recover=all"]
         subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, out)
+    return out
 
 
 class Geom(C.Structure):
@@ -55,9 +59,12 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build_oracle(force=False)
-        L = C.CDLL(_LIB)
+        path = os.environ.get("DPD_ORACLE_LIB")   # another build, e.g. the sanitized one
+        if not path:
+            if not os.path.exists(_LIB):
+                build_oracle(force=False)
+            path = _LIB
+        L = C.CDLL(path)
         P = C.c_void_p
         L.orc_philox4x32_10.argtypes = [P, P, P]
         L.orc_uniform_pair.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint32, P]

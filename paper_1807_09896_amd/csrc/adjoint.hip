@@ -269,9 +269,9 @@ __global__ __launch_bounds__(BS) void k_force_vjp(
         const float4 vtj = vt4[j];
         const bool fluid_j = (int64_t)j < NF;
         const float4 Fj = fluid_j ? fbar[j] : make_float4(0.f, 0.f, 0.f, 0.f);
-        const float dx = min_image(pi.x - pj.x, G.L[0]);
-        const float dy = min_image(pi.y - pj.y, G.L[1]);
-        const float dz = min_image(pi.z - pj.z, G.L[2]);
+        const float dx = sep(pi.x, pj.x, G.L[0]);
+        const float dy = sep(pi.y, pj.y, G.L[1]);
+        const float dz = sep(pi.z, pj.z, G.L[2]);
         const float r2 = dx * dx + dy * dy + dz * dz;
         const float rinv = rsqrtf(r2);
         const float r = r2 * rinv;

@@ -284,6 +284,18 @@ __device__ __forceinline__ T phi_at(const T *__restrict__ grid, const KGeom &G, 
   return phi_interp(grid, G, grid_locate<T>(G, x, y, z));
 }
 
+// Minimum-image separation x_i - x_j of two coordinates in [0, L) of a
+// pair within the cutoff.  Across the periodic edge the coordinate near L is
+// shifted by L first, which is exact (it lies within a factor two of L), so
+// the separation carries one rounding of a number below rc rather than the
+// rounding of x_i - x_j ~ L (half an ulp of L: 7.6e-6 at L = 168).
+__device__ __forceinline__ float sep(float xi, float xj, float L) {
+  const float d = xi - xj, h = 0.5f * L;
+  const float a = d > h ? xi - L : xi;
+  const float b = d < -h ? xj - L : xj;
+  return a - b;
+}
+
 // Minimum-image component (|d| < L/2 for every pair within the cutoff).
 __device__ __forceinline__ float min_image(float d, float L) {
   return d > 0.5f * L ? d - L : (d < -0.5f * L ? d + L : d);

@@ -701,9 +701,9 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_
       const uint32_t qn = q + BS * 4u;
       const int jn = qn < tail ? *(const int *)(lds + qn) : pad;
       const float4 pjn = posr[jn], vtjn = vtr[jn];
-      const float dx = min_image(pi.x - pj.x, G.L[0]);
-      const float dy = min_image(pi.y - pj.y, G.L[1]);
-      const float dz = min_image(pi.z - pj.z, G.L[2]);
+      const float dx = sep(pi.x, pj.x, G.L[0]);
+      const float dy = sep(pi.y, pj.y, G.L[1]);
+      const float dz = sep(pi.z, pj.z, G.L[2]);
       const float r2 = dx * dx + dy * dy + dz * dz;
       const bool wall = (int64_t)j >= NF;
       const float a = wall ? P.a_fw : P.a_ff;

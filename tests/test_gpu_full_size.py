@@ -1,7 +1,8 @@
-"""The headline workload at full size, in the launch configuration the
-benchmark times: the porous medium of 168^3 at density 4 (8.49M fluid and
-wall particles, a 672^3 float32 phase field), every particle against the
-FP64 oracle.
+"""The benchmark's workloads at full size, in the launch configuration it
+times, every particle against the FP64 oracle: the headline porous medium
+of 168^3 at density 4 (8.49M fluid and wall particles, a 672^3 float32
+phase field), the same with the attractive-repulsive force, and the
+1.1M-particle Couette channel with a sliding plate and specular reflection.
 
 Bars: initial forces within 2e-5 F_scale; after one step from a common
 FP32 snapshot (the same positions, velocities and carried force on both
@@ -37,9 +38,34 @@ def dpd():
     return dpd
 
 
-def test_headline_workload_one_step(dpd, oracle_lib):
-    s = workloads.porous_system(Lbox=168.0, name="porous_grf_168", device="cuda")
-    say("porous 168: %d particles (%d fluid)" % (s.n, s.n_fluid))
+def _headline():
+    return workloads.porous_system(Lbox=168.0, name="porous_grf_168", device="cuda")
+
+
+def _headline_sph():
+    """The benchmark's attractive-repulsive leg: the headline workload with
+    Sec. IV's fluid (kBT 0.5, the Eq. 22-24 strengths and ranges, dt 0.005)."""
+    s = _headline()
+    s.params = dict(s.params, sph=workloads.sph_force(), kBT=0.5, dt=0.005)
+    return s
+
+
+def _couette_specular():
+    """The benchmark's moving-wall leg: the 192 x 192 x 10 Couette channel,
+    upper plate sliding at U = 1, specular reflection."""
+    s = workloads.couette_system(L=(192.0, 192.0, 10.0), U=1.0, seed=80)
+    s.params = dict(s.params, specular=True)
+    return s
+
+
+WORKLOADS = {"headline": _headline, "headline_sph": _headline_sph,
+             "couette_specular": _couette_specular}
+
+
+@pytest.mark.parametrize("name", list(WORKLOADS))
+def test_full_size_one_step(dpd, oracle_lib, name):
+    s = WORKLOADS[name]()
+    say("%s: %d particles (%d fluid)" % (name, s.n, s.n_fluid))
     o = oracle_lib.Oracle(s)
     sim = dpd.Simulation(s)
     fluid = by_gid(o, s.type) == 0

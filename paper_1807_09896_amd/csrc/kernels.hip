@@ -193,12 +193,40 @@ __global__ void k_scatter(int64_t n, const int32_t *__restrict__ cell_of,
   idx[start[cell_of[p]] + rank_of[p]] = (int32_t)p;
 }
 
+// A cell's run of up to K storage indices (the common case: about four per
+// cell at density 4), loaded into registers with independent loads and sorted by a
+// fixed insertion network of compare-exchanges, the slots past the run padded
+// with a key above every index; written back to idx and, if out, to out.
+template <int K>
+__device__ __forceinline__ void sort_run_regs(int32_t *__restrict__ idx, int a, int n,
+                                              int32_t *__restrict__ out) {
+  uint32_t v[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) v[i] = i < n ? (uint32_t)idx[a + i] : 0xffffffffu;
+#pragma unroll
+  for (int i = 1; i < K; ++i)
+#pragma unroll
+    for (int j = i; j > 0; --j) {
+      const uint32_t lo = min(v[j - 1], v[j]), hi = max(v[j - 1], v[j]);
+      v[j - 1] = lo;
+      v[j] = hi;
+    }
+#pragma unroll
+  for (int i = 0; i < K; ++i)
+    if (i < n) {
+      idx[a + i] = (int32_t)v[i];
+      if (out) out[i] = (int32_t)v[i];
+    }
+}
+
 // Atomic ranks arrive in any order: sort each cell's run by storage index so
 // that the cell list, and every sum over it, is deterministic.  With key4 the
 // run is sorted by the gid bits of key4[i].w instead, which makes the order
 // independent of how the particles were stored before (used when a state is
 // loaded from outside).  With idx_all the sorted run is also written to the
 // fluid part of the merged run.
+// Runs of up to 16 are sorted in registers (sort_run_regs); longer runs, and
+// the gid order, by an insertion sort in memory.
 template <bool BY_GID>
 __global__ void k_sort_cells(int64_t ncell, const int32_t *__restrict__ start,
                              int32_t *__restrict__ idx, const float4 *__restrict__ key4,
@@ -207,6 +235,16 @@ __global__ void k_sort_cells(int64_t ncell, const int32_t *__restrict__ start,
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncell) return;
   const int a = start[c], b = start[c + 1];
+  if (!BY_GID && b - a <= 16) {
+    int32_t *out = idx_all ? idx_all + fluid_off[c] : nullptr;
+    if (b - a <= 4)
+      sort_run_regs<4>(idx, a, b - a, out);
+    else if (b - a <= 8)
+      sort_run_regs<8>(idx, a, b - a, out);
+    else
+      sort_run_regs<16>(idx, a, b - a, out);
+    return;
+  }
   for (int i = a + 1; i < b; ++i) {
     const int v = idx[i];
     const uint32_t kv = BY_GID ? __float_as_uint(key4[v].w) : (uint32_t)v;

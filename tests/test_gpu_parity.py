@@ -72,6 +72,10 @@ SYSTEMS = {
     "curved": _small_curved,
     "stress": _stress_system,
     "bulk": lambda: workloads.bulk_system(L=(5.0, 4.0, 3.0), params=workloads.default_params(seed=8)),
+    # density 24: cells of up to about 30 particles, so that the per-cell
+    # sort takes every run length (the register networks and the long runs)
+    "dense": lambda: workloads.bulk_system(L=(5.0, 4.0, 3.0), rho=24.0,
+                                           params=workloads.default_params(seed=21)),
 }
 
 
@@ -186,7 +190,7 @@ def _one_step_compare(dpd, oracle_lib, s, nsteps_before=0, sim=None, r=0):
     return n_events
 
 
-@pytest.mark.parametrize("name", ["tiny", "slab_f64grid", "curved", "stress"])
+@pytest.mark.parametrize("name", ["tiny", "slab_f64grid", "curved", "stress", "dense"])
 def test_one_step_parity(dpd, oracle_lib, name):
     s = SYSTEMS[name]()
     say("one-step", name, s.n)

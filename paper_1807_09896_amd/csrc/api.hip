@@ -338,9 +338,12 @@ int bin_all(dpd_ctx *c, hipStream_t s) {
   return DPD_OK;
 }
 
-// key4: sort each cell by gid (a state loaded from outside) instead of by
-// storage index.
-int scan_scatter_sort(dpd_ctx *c, hipStream_t s, const float4 *key4 = nullptr) {
+// Cell list of the fluid at its current positions and the merged per-cell
+// runs.  key4: sort each cell by gid (a state loaded from outside) instead of
+// by storage index; bump: the force evaluation index advances in the same
+// launches.
+int scan_scatter_sort(dpd_ctx *c, hipStream_t s, const float4 *key4 = nullptr,
+                      unsigned long long *bump = nullptr) {
   HIP_TRY(c, timed(c, s, K_SCAN_REDUCE, [&] {
             return dpd::launch_scan_reduce(s, c->NCELL, c->count, c->bsum);
           }));
@@ -350,14 +353,12 @@ int scan_scatter_sort(dpd_ctx *c, hipStream_t s, const float4 *key4 = nullptr) {
                                          c->start_all, c->fluid_off);
           }));
   HIP_TRY(c, timed(c, s, K_SCATTER, [&] {
-            return dpd::launch_scatter(s, c->NF, c->cell_of, c->rank_of, c->cstart, c->idx);
+            return dpd::launch_scatter(s, c->NF, c->cell_of, c->rank_of, c->cstart, c->idx,
+                                       c->NW, c->wcell, c->wcstart, c->start_all, c->idx_all,
+                                       bump);
           }));
   HIP_TRY(c, timed(c, s, K_SORT, [&] {
             return dpd::launch_sort_cells(s, c->NCELL, c->cstart, c->idx, key4, c->fluid_off,
-                                          c->idx_all);
-          }));
-  HIP_TRY(c, timed(c, s, K_OTHER, [&] {
-            return dpd::launch_fill_walls(s, c->NW, c->NF, c->wcell, c->wcstart, c->start_all,
                                           c->idx_all);
           }));
   return DPD_OK;
@@ -448,9 +449,8 @@ int enqueue_step(dpd_ctx *c, hipStream_t s) {
     int rc = wall_pass(c, s, 1);
     if (rc) return rc;
   }
-  int rc = scan_scatter_sort(c, s);
+  int rc = scan_scatter_sort(c, s, nullptr, c->dk);
   if (rc) return rc;
-  HIP_TRY(c, timed(c, s, K_OTHER, [&] { return dpd::launch_bump_k(s, c->dk); }));
   return force_pass(c, s, 0);
 }
 

@@ -41,15 +41,17 @@ hipError_t launch_scan_down(hipStream_t s, int64_t ncell, int32_t *count, int32_
 
 // idx[start[cell_of[p]] + rank_of[p]] = p, then each cell's run sorted by p
 // (by the gid bits of key4[p].w when key4 is given), and copied to the fluid
-// part of the merged run when idx_all is given.
+// part of the merged run when idx_all is given.  The scatter also writes the
+// wall part of the merged runs when idx_all is given (walls cell-sorted,
+// stored at index n + w) and, with dk, advances the force evaluation index.
 hipError_t launch_scatter(hipStream_t s, int64_t n, const int32_t *cell_of,
-                          const int32_t *rank_of, const int32_t *start, int32_t *idx);
+                          const int32_t *rank_of, const int32_t *start, int32_t *idx,
+                          int64_t nw = 0, const int32_t *wcell = nullptr,
+                          const int32_t *wstart = nullptr, const int32_t *start_all = nullptr,
+                          int32_t *idx_all = nullptr, unsigned long long *dk = nullptr);
 hipError_t launch_sort_cells(hipStream_t s, int64_t ncell, const int32_t *start, int32_t *idx,
                              const float4 *key4, const int32_t *fluid_off, int32_t *idx_all);
 
-// Wall part of the merged per-cell runs (walls stored at index nf + w).
-hipError_t launch_fill_walls(hipStream_t s, int64_t nw, int64_t nf, const int32_t *wcell,
-                             const int32_t *wstart, const int32_t *start_all, int32_t *idx_all);
 
 // Write the pad entry (far-away position, zero velocity) at pos4[0], vt4[0];
 // with slack given, the kIdxSlack spare run entries name it.
@@ -113,9 +115,6 @@ hipError_t launch_force(hipStream_t s, int block, const Box *boxes, const Tile *
                         const int32_t *start_all,
                         float4 *pos_out, float4 *vel_out, float4 *frc_out,
                         const unsigned long long *dk, Status *st, int sph);
-
-// *dk += 1 (the force evaluation index, on the device).
-hipError_t launch_bump_k(hipStream_t s, unsigned long long *dk);
 
 // Interacting pairs (gid_i, gid_j) from each fluid particle of one box
 // (slots [first, first + nf), cells from cell_off).

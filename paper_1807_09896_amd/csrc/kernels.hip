@@ -13,6 +13,8 @@
 // then fluid) serves the neighbour search without a fluid/wall branch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device.h"
 #include "kernels.h"
 
@@ -185,12 +187,27 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(
   }
 }
 
+// idx[start[cell_of[p]] + rank_of[p]] = p for the n entries.  Threads n ..
+// n + nw - 1 write the wall part of the merged runs (wall w, cell-sorted in
+// cell wcell[w], is index n + w of the position arrays), and with dk the
+// first thread advances the force evaluation index, so that one launch does
+// the work of three.
 __global__ void k_scatter(int64_t n, const int32_t *__restrict__ cell_of,
                           const int32_t *__restrict__ rank_of, const int32_t *__restrict__ start,
-                          int32_t *__restrict__ idx) {
+                          int32_t *__restrict__ idx, int64_t nw, const int32_t *__restrict__ wcell,
+                          const int32_t *__restrict__ wstart,
+                          const int32_t *__restrict__ start_all, int32_t *__restrict__ idx_all,
+                          unsigned long long *__restrict__ dk) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  idx[start[cell_of[p]] + rank_of[p]] = (int32_t)p;
+  if (dk && p == 0) *dk += 1ull;
+  if (p < n) {
+    idx[start[cell_of[p]] + rank_of[p]] = (int32_t)p;
+    return;
+  }
+  const int64_t w = p - n;
+  if (w >= nw) return;
+  const int c = wcell[w];
+  idx_all[start_all[c] + ((int)w - wstart[c])] = (int32_t)(n + w);
 }
 
 // A cell's run of up to K storage indices (the common case: about four per
@@ -260,20 +277,6 @@ __global__ void k_sort_cells(int64_t ncell, const int32_t *__restrict__ start,
     for (int i = a; i < b; ++i) idx_all[o + (i - a)] = idx[i];
   }
 }
-
-// Wall part of the merged runs: wall w (cell-sorted, cell wcell[w]) is index
-// nf + w of the position arrays.
-__global__ void k_fill_walls(int64_t nw, int64_t nf, const int32_t *__restrict__ wcell,
-                             const int32_t *__restrict__ wstart,
-                             const int32_t *__restrict__ start_all, int32_t *__restrict__ idx_all) {
-  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (w >= nw) return;
-  const int c = wcell[w];
-  idx_all[start_all[c] + ((int)w - wstart[c])] = (int32_t)(nf + w);
-}
-
-// k += 1: the force evaluation index of the next force pass.
-__global__ void k_bump(unsigned long long *dk) { *dk += 1ull; }
 
 // The pad entry after fluid and walls: a position far outside the box, so
 // that it never tests as a neighbour; the spare run-array entries after the
@@ -1040,9 +1043,16 @@ hipError_t launch_scan_down(hipStream_t s, int64_t ncell, int32_t *count, int32_
 }
 
 hipError_t launch_scatter(hipStream_t s, int64_t n, const int32_t *cell_of,
-                          const int32_t *rank_of, const int32_t *start, int32_t *idx) {
-  if (n <= 0) return hipSuccess;
-  k_scatter<<<grid_for(n), kBlock, 0, s>>>(n, cell_of, rank_of, start, idx);
+                          const int32_t *rank_of, const int32_t *start, int32_t *idx,
+                          int64_t nw, const int32_t *wcell, const int32_t *wstart,
+                          const int32_t *start_all, int32_t *idx_all,
+                          unsigned long long *dk) {
+  if (!idx_all) nw = 0;
+  if (nw > 0 && (!wcell || !wstart || !start_all)) return hipErrorInvalidValue;
+  const int64_t total = std::max<int64_t>(n + nw, dk ? 1 : 0);
+  if (total <= 0) return hipSuccess;
+  k_scatter<<<grid_for(total), kBlock, 0, s>>>(n, cell_of, rank_of, start, idx, nw, wcell, wstart,
+                                               start_all, idx_all, dk);
   return hipGetLastError();
 }
 
@@ -1057,13 +1067,6 @@ hipError_t launch_sort_cells(hipStream_t s, int64_t ncell, const int32_t *start,
   return hipGetLastError();
 }
 
-hipError_t launch_fill_walls(hipStream_t s, int64_t nw, int64_t nf, const int32_t *wcell,
-                             const int32_t *wstart, const int32_t *start_all, int32_t *idx_all) {
-  if (nw <= 0) return hipSuccess;
-  k_fill_walls<<<grid_for(nw), kBlock, 0, s>>>(nw, nf, wcell, wstart, start_all, idx_all);
-  return hipGetLastError();
-}
-
 hipError_t launch_wall_move(hipStream_t s, const KGeom &G, float hdt, float dt, int64_t nw,
                             const float4 *walls_in, const float4 *vt_in, float4 *walls_out) {
   if (nw <= 0) return hipSuccess;
@@ -1074,11 +1077,6 @@ hipError_t launch_wall_move(hipStream_t s, const KGeom &G, float hdt, float dt, 
 hipError_t launch_import_walls(hipStream_t s, int64_t nw, float4 *walls, const float *pos) {
   if (nw <= 0) return hipSuccess;
   k_import_walls<<<grid_for(nw), kBlock, 0, s>>>(nw, walls, pos);
-  return hipGetLastError();
-}
-
-hipError_t launch_bump_k(hipStream_t s, unsigned long long *dk) {
-  k_bump<<<1, 1, 0, s>>>(dk);
   return hipGetLastError();
 }
 

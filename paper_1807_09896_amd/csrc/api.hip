@@ -35,6 +35,8 @@ thread_local std::string g_create_error = "no error";
 
 enum Kernel { K_INTEGRATE = 0, K_SCAN_REDUCE, K_SCAN_TOP, K_SCAN_DOWN, K_SCATTER, K_SORT,
               K_FORCE, K_OTHER };
+// "scan_top" records no launches (each scan_down block adds up the block
+// sums before it); the slot keeps the numbering of the others.
 const char *kKernelNames[DPD_NUM_KERNELS] = {"integrate_reflect_bin", "scan_reduce", "scan_top",
                                              "scan_down", "scatter", "sort_cells", "pair_force",
                                              "other"};
@@ -347,7 +349,6 @@ int scan_scatter_sort(dpd_ctx *c, hipStream_t s, const float4 *key4 = nullptr,
   HIP_TRY(c, timed(c, s, K_SCAN_REDUCE, [&] {
             return dpd::launch_scan_reduce(s, c->NCELL, c->count, c->bsum);
           }));
-  HIP_TRY(c, timed(c, s, K_SCAN_TOP, [&] { return dpd::launch_scan_top(s, c->nscan, c->bsum); }));
   HIP_TRY(c, timed(c, s, K_SCAN_DOWN, [&] {
             return dpd::launch_scan_down(s, c->NCELL, c->count, c->cstart, c->bsum, c->wcstart,
                                          c->start_all, c->fluid_off);
@@ -408,7 +409,6 @@ int wall_pass(dpd_ctx *c, hipStream_t s, int move) {
   HIP_TRY(c, timed(c, s, K_SCAN_REDUCE, [&] {
             return dpd::launch_scan_reduce(s, c->NCELL, c->wcount, c->bsum);
           }));
-  HIP_TRY(c, timed(c, s, K_SCAN_TOP, [&] { return dpd::launch_scan_top(s, c->nscan, c->bsum); }));
   HIP_TRY(c, timed(c, s, K_SCAN_DOWN, [&] {
             return dpd::launch_scan_down(s, c->NCELL, c->wcount, c->wcstart, c->bsum, nullptr,
                                          nullptr, nullptr);
@@ -864,7 +864,6 @@ int create_impl(int32_t nbox, const dpd_box *boxes, const dpd_particles *parts,
       for (void *q : {(void *)dpos, (void *)dvel, (void *)dgid, (void *)drows}) dfree(c, q);
     }
     chk(dpd::launch_scan_reduce(c->stream, NCELL, c->count, c->bsum), "scan");
-    chk(dpd::launch_scan_top(c->stream, c->nscan, c->bsum), "scan");
     chk(dpd::launch_scan_down(c->stream, NCELL, c->count, c->wcstart, c->bsum, nullptr, nullptr,
                               nullptr),
         "scan");

@@ -31,10 +31,9 @@ hipError_t launch_bin(hipStream_t s, const KGeom &G, int64_t cell_off, int64_t n
                       const float4 *pos4, int32_t *cell_of, int32_t *rank_of, int32_t *count);
 
 // Exclusive scan of count[0..ncell) into start[0..ncell] (start[ncell] =
-// total), count reset to 0, in three launches: per-block sums, a scan of
-// the block sums, and the per-block scans with their offsets.
+// total), count reset to 0, in two launches: per-block sums, then the
+// per-block scans, each block adding the sum of the block sums before it.
 hipError_t launch_scan_reduce(hipStream_t s, int64_t ncell, const int32_t *count, int32_t *bsum);
-hipError_t launch_scan_top(hipStream_t s, int nblocks, int32_t *bsum);
 hipError_t launch_scan_down(hipStream_t s, int64_t ncell, int32_t *count, int32_t *start,
                             const int32_t *bsum, const int32_t *wstart, int32_t *start_all,
                             int32_t *fluid_off);

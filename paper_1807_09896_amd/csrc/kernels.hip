@@ -117,21 +117,20 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(int64_t n,
   if (threadIdx.x == 0) bsum[blockIdx.x] = lds[0];
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_top(int nb, int32_t *__restrict__ bsum) {
-  __shared__ int lds[kScanThreads];
-  int carry = 0;
-  for (int base = 0; base < nb; base += kScanThreads) {
-    const int i = base + threadIdx.x;
-    const int v = i < nb ? bsum[i] : 0;
-    int total;
-    const int ex = block_exclusive_scan(v, lds, total);
-    if (i < nb) bsum[i] = carry + ex;
-    carry += total;
-  }
+// Sum of v over the block (kScanThreads threads, four wavefronts).
+__device__ __forceinline__ int block_sum(int v, int *lds) {
+  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int t = 0;
+  for (int w = 0; w < kScanThreads / 64; ++w) t += lds[w];
+  __syncthreads();
+  return t;
 }
 
 // Each thread owns kScanItems consecutive cells; the block's cells are read
-// through LDS so that global loads and stores stay coalesced.  With wall
+// through LDS so that global loads and stores stay coalesced.  The block's
+// offset is the sum of the block sums bsum[0 .. blockIdx) of k_scan_reduce.  With wall
 // offsets wstart (exclusive scan of the static wall counts) it also writes
 // the merged runs: start_all[c] = start[c] + wstart[c] begins cell c's run of
 // walls then fluid, fluid_off[c] = start_all[c] + (walls in c) its fluid part.
@@ -142,6 +141,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(
   __shared__ int tile[kScanChunk + kScanChunk / 32];
   __shared__ int lds[kScanThreads];
   const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  int prior = 0;
+  for (int j = (int)threadIdx.x; j < (int)blockIdx.x; j += kScanThreads) prior += bsum[j];
+  const int offset = block_sum(prior, lds);
   for (int k = 0; k < kScanItems; ++k) {
     const int local = k * kScanThreads + threadIdx.x;
     const int64_t i = base + local;
@@ -160,7 +162,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(
     run += tile[local + local / 32];
   }
   int total;
-  int ex = block_exclusive_scan(run, lds, total) + bsum[blockIdx.x];
+  int ex = block_exclusive_scan(run, lds, total) + offset;
   for (int k = 0; k < kScanItems; ++k) {
     const int local = first + k;
     const int v = tile[local + local / 32];
@@ -182,8 +184,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(
     }
   }
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kScanThreads - 1) {
-    start[n] = bsum[blockIdx.x] + total;
-    if (wstart) start_all[n] = bsum[blockIdx.x] + total + wstart[n];
+    start[n] = offset + total;
+    if (wstart) start_all[n] = offset + total + wstart[n];
   }
 }
 
@@ -1026,11 +1028,6 @@ hipError_t launch_bin(hipStream_t s, const KGeom &G, int64_t cell_off, int64_t n
 
 hipError_t launch_scan_reduce(hipStream_t s, int64_t ncell, const int32_t *count, int32_t *bsum) {
   k_scan_reduce<<<scan_blocks(ncell), kScanThreads, 0, s>>>(ncell, count, bsum);
-  return hipGetLastError();
-}
-
-hipError_t launch_scan_top(hipStream_t s, int nblocks, int32_t *bsum) {
-  k_scan_top<<<1, kScanThreads, 0, s>>>(nblocks, bsum);
   return hipGetLastError();
 }
 

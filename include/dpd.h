@@ -228,7 +228,9 @@ int dpd_counters(dpd_ctx *ctx, int64_t *out);
  * starts recording (dpd_step then times each kernel launch), 0 stops.
  * When out is not NULL it receives, for the kernels named by
  * dpd_kernel_name(0..DPD_NUM_KERNELS-1), the summed milliseconds in out_ms
- * and the number of timed launches in out_launches.  Synchronises. */
+ * and the number of timed launches in out_launches ("scan_top" has none: each
+ * block of "scan_down" adds up the block sums before it; "scatter" also writes
+ * the wall part of the merged cell runs).  Synchronises. */
 #define DPD_NUM_KERNELS 8
 int dpd_kernel_times(dpd_ctx *ctx, int32_t enable, double *out_ms, int64_t *out_launches);
 const char *dpd_kernel_name(int32_t i);

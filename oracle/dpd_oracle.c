@@ -394,19 +394,29 @@ static void free_cells(orc_cells *C)
     free(C->cell); free(C->start); free(C->list);
 }
 
+/* Separation of one FP32 coordinate pair along an axis for image shift s of
+ * j (-1, 0, +1): the FP32 rounding of the exact minimum-image difference
+ * x_i - x_j - s L.  The coordinate that lies in the last cell (x_i for
+ * s = +1, x_j for s = -1) is first lowered by L, which is exact because it
+ * lies in [L/2, L) (Sterbenz), so the one subtraction that follows is the
+ * only rounding. */
+static float sep32(float xi, float xj, int s, float L)
+{
+    float a = s > 0 ? xi - L : xi;
+    float b = s < 0 ? xj - L : xj;
+    return a - b;
+}
+
 /* FP32 pair decision on shadow positions: with j seen from i's neighbour
- * cell at image shift s (per axis -1, 0, +1),
- *   dx = fl(fl(x_i - s L) - x_j),  r2 = fma(dz, dz, fma(dy, dy, fl(dx^2)))
+ * cell at image shift s (per axis -1, 0, +1), d = sep32 per axis,
+ *   r2 = fma(dz, dz, fma(dy, dy, fl(dx^2)))
  * (each fma rounded once), and the pair is in range iff r2 < fl32(rc^2). */
 static int pair_in_range32(const orc_geom *G, const float *xi, const float *xj,
                            const int s[3], float rc2)
 {
-    float ax = xi[0] - (float)s[0] * G->L32[0];
-    float ay = xi[1] - (float)s[1] * G->L32[1];
-    float az = xi[2] - (float)s[2] * G->L32[2];
-    float dx = ax - xj[0];
-    float dy = ay - xj[1];
-    float dz = az - xj[2];
+    float dx = sep32(xi[0], xj[0], s[0], G->L32[0]);
+    float dy = sep32(xi[1], xj[1], s[1], G->L32[1]);
+    float dz = sep32(xi[2], xj[2], s[2], G->L32[2]);
     float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
     return r2 < rc2;
 }

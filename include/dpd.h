@@ -204,8 +204,10 @@ int dpd_set_state(dpd_ctx *ctx, const float *pos, const float *vel,
 
 /* Interacting pairs at the current positions, as seen from each fluid
  * particle i: every (gid_i, gid_j) with j != i in the 27 cells around i and
- * fl32(dx^2 + dy^2 + dz^2) < fl32(rc^2) (dx = fl(x_i - fl(x_j + s L)), s the
- * image shift of the neighbour cell).  Fluid-fluid pairs appear in both
+ * r2 = fma(dz, dz, fma(dy, dy, fl(dx^2))) < fl32(rc^2), where dx is the FP32
+ * rounding of the exact minimum-image difference x_i - x_j - s L (s the image
+ * shift of the neighbour cell; the coordinate in the last cell is lowered by
+ * L, exactly, before the one rounding subtraction).  Fluid-fluid pairs appear in both
  * orders, fluid-wall pairs once.  pairs is a device buffer of cap x 2 uint32
  * (unordered); *count (host) receives the total, which may exceed cap (only
  * cap pairs are written then).  Synchronises the stream. */

@@ -231,7 +231,7 @@ __global__ __launch_bounds__(BS) void k_force_vjp(
     NeighbourRows rows;
     rows.init(cx, cy, cz);
     int t = 0, t_end = 0;
-    float ax = pi.x, ay = pi.y, az = pi.z;
+    SepAxis ax = sep_axis(pi.x, 0.f), ay = sep_axis(pi.y, 0.f), az = sep_axis(pi.z, 0.f);
     bool done = false;
     while (!done) {
       int cnt = 0;
@@ -242,9 +242,9 @@ __global__ __launch_bounds__(BS) void k_force_vjp(
             done = true;
             break;
           }
-          ax = sub_nc(pi.x, sx);
-          ay = sub_nc(pi.y, sy);
-          az = sub_nc(pi.z, sz);
+          ax = sep_axis(pi.x, sx);
+          ay = sep_axis(pi.y, sy);
+          az = sep_axis(pi.z, sz);
           continue;
         }
         int jb[kBatchA];
@@ -255,7 +255,7 @@ __global__ __launch_bounds__(BS) void k_force_vjp(
         for (int u = 0; u < kBatchA; ++u) pb[u] = pos4[jb[u]];
 #pragma unroll
         for (int u = 0; u < kBatchA; ++u) {
-          const float r2 = pair_r2(sub_nc(ax, pb[u].x), sub_nc(ay, pb[u].y), sub_nc(az, pb[u].z));
+          const float r2 = pair_r2(sep_d(ax, pb[u].x), sep_d(ay, pb[u].y), sep_d(az, pb[u].z));
           if (r2 < P.rc2 && r2 > 0.0f) {
             mine[cnt * BS] = (uint32_t)jb[u];
             ++cnt;

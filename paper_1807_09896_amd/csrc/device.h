@@ -164,8 +164,9 @@ __device__ __forceinline__ float drift1(float x, float v, float f, float hdt, fl
   return wrap1(y, L);
 }
 
-// Pair decision: r2 = fma(dz, dz, fma(dy, dy, fl(dx^2))) with
-// d = fl(x_i' - x_j), x_i' = fl(x_i - s L) taken once per neighbour cell.
+// Pair decision: r2 = fma(dz, dz, fma(dy, dy, fl(dx^2))), in range iff
+// r2 < fl32(rc^2), with d per axis the FP32 rounding of the exact
+// minimum-image difference x_i - x_j - s L (SepAxis below).
 __device__ __forceinline__ float pair_r2(float dx, float dy, float dz) {
 #pragma clang fp contract(off)
   return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
@@ -179,6 +180,26 @@ __device__ __forceinline__ float sub_nc(float a, float b) {
 __device__ __forceinline__ float add_nc(float a, float b) {
 #pragma clang fp contract(off)
   return a + b;
+}
+
+// Separation along one axis in decision form, for the candidates of a
+// neighbour run seen at image shift sL (-L, 0 or +L): the coordinate that
+// lies in the last cell (x_i for +L, x_j for -L) is lowered by L first,
+// which is exact because it lies in [L/2, L), so d = fl(a - fl(x_j - b)) is
+// the exact difference x_i - x_j - s L rounded once (fl(x_j - 0) = x_j).
+struct SepAxis {
+  float a, b;
+};
+
+__device__ __forceinline__ SepAxis sep_axis(float xi, float sL) {
+  SepAxis r;
+  r.a = sL > 0.f ? sub_nc(xi, sL) : xi;
+  r.b = sL < 0.f ? -sL : 0.f;
+  return r;
+}
+
+__device__ __forceinline__ float sep_d(const SepAxis &s, float xj) {
+  return sub_nc(s.a, sub_nc(xj, s.b));
 }
 
 // ---------------------------------------------------------------------------

@@ -763,14 +763,15 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_
   // the row wraps; a lane moves to B on its own).  Entries past the lane's
   // run are read (other cells' entries, or the pad) but never listed.
   // Phase B runs when a lane's list could overflow in the next pass.
-  auto walk = [&](int t, int t_end, int tb, int tb_end, float ax, float axb, float ay,
-                  float az) {
+  auto walk = [&](int t, int t_end, int tb, int tb_end, SepAxis ax, SepAxis axb, SepAxis ay,
+                  SepAxis az) {
     {
       const bool sw = t >= t_end;
       t = sw ? tb : t;
       t_end = sw ? tb_end : t_end;
       tb = sw ? tb_end : tb;
-      ax = sw ? axb : ax;
+      ax.a = sw ? axb.a : ax.a;
+      ax.b = sw ? axb.b : ax.b;
     }
     for (;;) {
       while (wave_any(t < t_end) && !wave_any(tail > full)) {
@@ -782,8 +783,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_
         for (int u = 0; u < kBatch; ++u) pb[u] = posr[jb[u]];
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
-          const float r2 =
-              pair_r2(sub_nc(ax, pb[u].x), sub_nc(ay, pb[u].y), sub_nc(az, pb[u].z));
+          const float r2 = pair_r2(sep_d(ax, pb[u].x), sep_d(ay, pb[u].y), sep_d(az, pb[u].z));
           // r2 > 0 drops i itself (and coincident particles, whose force is 0)
           const bool hit = r2 < P.rc2 && r2 > 0.0f && u < rem;
           *(int *)(lds + tail) = jb[u];
@@ -794,7 +794,8 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_
         t = sw ? tb : t;
         t_end = sw ? tb_end : t_end;
         tb = sw ? tb_end : tb;
-        ax = sw ? axb : ax;
+        ax.a = sw ? axb.a : ax.a;
+        ax.b = sw ? axb.b : ax.b;
       }
       if (!wave_any(t < t_end)) break;
       flush();
@@ -807,13 +808,13 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_
     float sz = 0.f;
     if (qz < 0) { qz += nz; sz = -G.L[2]; }
     else if (qz >= nz) { qz -= nz; sz = G.L[2]; }
-    const float az = sub_nc(pi.z, sz);
+    const SepAxis az = sep_axis(pi.z, sz);
     for (int oy = -1; oy <= 1; ++oy) {
       int qy = cy + oy;
       float sy = 0.f;
       if (qy < 0) { qy += ny; sy = -G.L[1]; }
       else if (qy >= ny) { qy -= ny; sy = G.L[1]; }
-      const float ay = sub_nc(pi.y, sy);
+      const SepAxis ay = sep_axis(pi.y, sy);
       // the row's x-neighbours [cx-1, cx+1] as run A, plus run B where the
       // row wraps (cell nx-1 seen across the left edge, then cells 0 and 1;
       // or cells nx-2 and nx-1, then cell 0 seen across the right edge)
@@ -831,7 +832,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_
         tb_end = left ? w[2] : (right ? w[1] : 0);
       }
       const float sxa = left ? -G.L[0] : 0.f, sxb = right ? G.L[0] : 0.f;
-      const float ax = sub_nc(pi.x, sxa), axb = sub_nc(pi.x, sxb);
+      const SepAxis ax = sep_axis(pi.x, sxa), axb = sep_axis(pi.x, sxb);
       walk(ta, ta_end, tb, tb_end, ax, axb, ay, az);
     }
   }
@@ -870,13 +871,14 @@ __device__ __forceinline__ int pairs_of(const KGeom &G, const KParams &P, int co
   const uint32_t gi = __float_as_uint(pi.w);
   for (int code = 0; code < 27; ++code) {
     const NCell nc = neighbour_cell(G, cx, cy, cz, code);
-    const float ax = sub_nc(pi.x, nc.sx), ay = sub_nc(pi.y, nc.sy), az = sub_nc(pi.z, nc.sz);
+    const SepAxis ax = sep_axis(pi.x, nc.sx), ay = sep_axis(pi.y, nc.sy),
+                  az = sep_axis(pi.z, nc.sz);
     const int t0 = start_all[co + nc.c], t1 = start_all[co + nc.c + 1];
     for (int t = t0; t < t1; ++t) {
       const int j = idx_all[t];
       if (j == i) continue;
       const float4 pj = pos4[j];
-      if (pair_r2(sub_nc(ax, pj.x), sub_nc(ay, pj.y), sub_nc(az, pj.z)) < P.rc2) {
+      if (pair_r2(sep_d(ax, pj.x), sep_d(ay, pj.y), sep_d(az, pj.z)) < P.rc2) {
         if (out && base + n < cap) {
           out[2 * (base + n)] = gi;
           out[2 * (base + n) + 1] = __float_as_uint(pj.w);

@@ -22,17 +22,21 @@ _SRC = os.path.join(_HERE, "dpd_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 
-def build_oracle(force: bool = True, sanitize: bool = False, path: str | None = None) -> str:
+def build_oracle(force: bool = True, sanitize=False, path: str | None = None) -> str:
     """Compile the oracle with gcc (no contraction, so FP32 decisions follow
-    the written op order).  sanitize=True builds it with the undefined-
-    behaviour sanitizer, aborting on the first report, into `path`."""
+    the written op order).  sanitize=True or "undefined" builds it with the
+    undefined-behaviour sanitizer, "address" with the address sanitizer
+    (a process that loads it must preload libasan), both aborting on the
+    first report, into `path`."""
     out = path or _LIB
     if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
         tmp = out + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-ffp-contract=off",
                "-fno-fast-math", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
         if sanitize:
-            cmd[1:1] = ["-g", "-fsanitize=undefined", "-fno-sanitize-recover=all"]
+            kind = "undefined" if sanitize is True else str(sanitize)
+            cmd[1:1] = ["-g", "-fno-omit-frame-pointer", "-fsanitize=" + kind,
+                        "-fno-sanitize-recover=all"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, out)
     return out

@@ -9,10 +9,12 @@
 // max(|grad' phi|, delta), delta = 0.01 (n goes linearly to zero where phi is
 // flat instead of pointing along rounding noise).
 //
-// Data flow: a block owns a 64 x 8 column of nodes and marches it through a
+// Data flow: a block owns a 64 x 16 column of nodes and marches it through a
 // chunk of 64 z planes.  phi planes (with a two-node x/y halo) live in an
-// LDS ring of four, the normal planes z-1 .. z+1 (one-node halo) in a ring
-// of three.  Each z step stores one phi plane into the ring, prepares the
+// LDS ring of four; the x and y components of the normal (one-node halo) in
+// a ring of two planes, its z component in the owning thread's registers
+// (the divergence needs n_z only in the node's own column).  Each z step
+// stores one phi plane into the ring, prepares the
 // next plane (each thread's own nodes: the Laplacian and reaction terms and
 // |grad' phi| into registers, the unit normal into LDS; the halo normals by
 // the first threads) and updates the current plane from its registers and

@@ -5,7 +5,7 @@ node within 1e-5 of the FP64 oracle in float32 and within 1e-12 in float64,
 and the reported residual (max |d phi / d t'| of the last step) within
 1e-5 / 1e-12 relative.  The tolerances are the unit roundoff (6e-8, 1.1e-16)
 times the amplification of input rounding by the relaxation itself, which
-the CPU tests bound by 100 for these inputs, with margin.  Shapes span several 64 x 8 x 32 tiles with ragged
+the CPU tests bound by 100 for these inputs, with margin.  Shapes span several 64 x 16 x 64 tiles with ragged
 ends, and degenerate grids (one node wide, 1 x 2 x 3); zero, odd and even
 step counts; invalid arguments rejected; a sphere keeps its radius over a
 long relaxation (the counter term); at the size of the porous workload's

@@ -27,12 +27,13 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one lane-op per
-# lane per clock (no packed FP32, integer and FP32 alike).
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# Per-unit VALU work of the pair-force kernel (lane-ops): an interacting pair
-# costs ~40 for the force, ~100 for Philox4x32-10 and ~20 for Box-Muller; a
-# candidate pair test ~10.
+# Per-unit VALU work of the pair force (full-rate instruction slots per
+# lane, a model): an interacting pair costs ~40 for the force, ~100 for
+# Philox4x32-10 (its ten 32 x 32 -> 64-bit multiplies issue at a quarter of
+# the full rate) and ~20 for Box-Muller; a candidate test ~10.  The unit is
+# the Newton-3 pair (each fluid-fluid pair once, each fluid-wall pair once)
+# and the half-shell candidate (each fluid-fluid candidate once, each
+# fluid-wall candidate once).
 OPS_PER_PAIR = 160
 OPS_PER_CANDIDATE = 10
 
@@ -55,28 +56,70 @@ def make_workload(name):
 
 
 def algorithmic_counts(sim, system):
-    """Interacting pairs (from the library's own pair count) and candidate
-    pairs (sum over fluid particles of the particles in their 27 cells)."""
+    """Interacting pairs from the library's own pair list, split into
+    fluid-fluid (each counted once) and fluid-wall, and half-shell candidate
+    pairs from the cell occupancy: each fluid-fluid candidate in the 27 cells
+    around a fluid particle once, each fluid-wall candidate once."""
     import numpy as np
+    import torch
     from paper_1807_09896_amd import binding
-    pairs = binding.dpd_neighbor_pairs(sim.ctx, None, 0)
-    st = sim.state()
-    cell = st["cell_of"].cpu().numpy()
+    total = binding.dpd_neighbor_pairs(sim.ctx, None, 0)
+    buf = torch.empty((total, 2), dtype=torch.int32, device="cuda")
+    got = binding.dpd_neighbor_pairs(sim.ctx, buf, total)
+    assert got == total
     typ = np.empty_like(system.type)
     typ[system.gid] = system.type
+    wall_of_gid = torch.from_numpy((typ != 0).astype(np.int8)).to("cuda")
+    fw = int(wall_of_gid[buf[:, 1].long()].sum())
+    del buf
+    ff_directed = total - fw
+    st = sim.state()
+    cell = st["cell_of"].cpu().numpy()
     L = system.L
     rc = system.params["rc"]
     nc = [int(math.floor(x / rc)) for x in L]
     ncell = nc[0] * nc[1] * nc[2]
-    nf_c = np.bincount(cell[typ == 0], minlength=ncell).reshape(nc[2], nc[1], nc[0])
-    all_c = np.bincount(cell, minlength=ncell).reshape(nc[2], nc[1], nc[0]).astype(np.int64)
-    S = np.zeros_like(all_c)
+    shape = (nc[2], nc[1], nc[0])
+    nf_c = np.bincount(cell[typ == 0], minlength=ncell).reshape(shape).astype(np.int64)
+    nw_c = np.bincount(cell[typ != 0], minlength=ncell).reshape(shape).astype(np.int64)
+    Sf = np.zeros_like(nf_c)
+    Sw = np.zeros_like(nw_c)
     for dz in (-1, 0, 1):
         for dy in (-1, 0, 1):
             for dx in (-1, 0, 1):
-                S += np.roll(all_c, (dz, dy, dx), axis=(0, 1, 2))
-    cands = int((nf_c.astype(np.int64) * S).sum() - nf_c.sum())
-    return pairs, cands, ncell
+                Sf += np.roll(nf_c, (dz, dy, dx), axis=(0, 1, 2))
+                Sw += np.roll(nw_c, (dz, dy, dx), axis=(0, 1, 2))
+    ff_cands = int((nf_c * (Sf - 1)).sum()) // 2
+    fw_cands = int((nf_c * Sw).sum())
+    return dict(pairs_ff=ff_directed // 2, pairs_fw=fw, pairs_directed=total,
+                candidates_ff_half=ff_cands, candidates_fw=fw_cands,
+                candidates_full=2 * ff_cands + fw_cands, cells=ncell)
+
+
+def valu_peak(ms_target=20.0):
+    """Issue rate of the vector ALU, measured: the library's calibration
+    kernel runs 64 x iters v_fmac_f32 per lane on 16 wavefronts per SIMD
+    (every SIMD of the chip busy); lane-op slots per second."""
+    import torch
+    from paper_1807_09896_amd import binding
+    props = torch.cuda.get_device_properties(0)
+    waves = props.multi_processor_count * 4 * 16
+    out = torch.empty(waves * 64, dtype=torch.float32, device="cuda")
+    binding.dpd_valu_probe(0, waves, 10, out)
+    iters = 400
+    best = 0.0
+    for _ in range(3):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        binding.dpd_valu_probe(0, waves, iters, out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = max(best, waves * 64.0 * 64 * iters / (ms * 1e-3))
+        if ms < ms_target:
+            iters = int(iters * ms_target / max(ms, 1e-3))
+    return best
 
 
 def main():
@@ -162,17 +205,33 @@ def main():
         if c:
             log("  %-24s %9.4f ms/launch x %d" % (k, ms / c, c))
     f_ms, f_n = kt["pair_force"]
-    force_ms = f_ms / max(f_n, 1)
-    pairs, cands, ncell = algorithmic_counts(sim, system)
+    # a step launches the pair force once per kernel kind that has work
+    force_launches_per_step = max(1, round(f_n / max(args.timing_steps, 1)))
+    force_ms = f_ms / max(args.timing_steps, 1)
+    cnt = algorithmic_counts(sim, system)
+    ncell = cnt["cells"]
     lookups = lk1["phi_lookups"]
-    ops = pairs * OPS_PER_PAIR + cands * OPS_PER_CANDIDATE
-    achieved_tops = ops / (force_ms * 1e-3) / 1e12
+    pairs_unique = cnt["pairs_ff"] + cnt["pairs_fw"]
+    cands_half = cnt["candidates_ff_half"] + cnt["candidates_fw"]
+    ops = pairs_unique * OPS_PER_PAIR + cands_half * OPS_PER_CANDIDATE
+    valu = valu_peak()
+    achieved_valu = ops / (force_ms * 1e-3)
     nf, nw = system.n_fluid, system.n_wall
     b_alg = nf * (72 + 16 + 28 + 12 + 1) + 16 * nw + 8 * ncell + (
         64 if system.phi.dtype == np.float64 else 32) * lookups
     step_gbs = b_alg / (ms_per_step * 1e-3) / 1e9
-    log("pairs %d (%.2f per fluid), candidates %d, phi lookups/step %.0f, B_alg %.1f MB"
-        % (pairs, pairs / max(nf, 1), cands, lookups, b_alg / 1e6))
+    # the pair force's own algorithmic bytes: positions, predicted velocities
+    # and gids of fluid and walls read once, the state written once in cell
+    # order (r, v, f: 48 B per fluid particle), the merged cell runs read once
+    force_bytes = nf * (32 + 48) + 32 * nw + 4 * (nf + nw) + 8 * ncell
+    force_gbs = force_bytes / (force_ms * 1e-3) / 1e9
+    log("pairs: %d fluid-fluid (each once), %d fluid-wall (%.2f per fluid particle); "
+        "half-shell candidates %d; phi lookups/step %.0f; B_alg %.1f MB"
+        % (cnt["pairs_ff"], cnt["pairs_fw"], pairs_unique / max(nf, 1), cands_half, lookups,
+           b_alg / 1e6))
+    log("step: %.1f GB/s of algorithmic traffic = %.4f of HBM peak; pair_force %.4f ms per step, "
+        "%.3e VALU slots/s by the model = %.3f of the measured VALU issue rate %.3e/s"
+        % (step_gbs, step_gbs / HBM_PEAK_GBS, force_ms, achieved_valu, achieved_valu / valu, valu))
 
     if args.copy_probe_mb > 0:
         from paper_1807_09896_amd import binding
@@ -185,13 +244,14 @@ def main():
         del a, b
 
     prof_dir = os.path.join(ROOT, "profiles")
-    traffic = None
-    tfile = os.path.join(prof_dir, "pair_force_%s_traffic.json" % args.workload)
+    traffic = force_traffic = None
+    tfile = os.path.join(prof_dir, "step_%s_traffic.json" % args.workload)
     if os.path.exists(tfile):
         with open(tfile) as fh:
             tr = json.load(fh)
         if tr.get("kernel_source_hash") == kernel_source_hash():
-            traffic = tr.get("bytes_per_launch")
+            traffic = tr.get("bytes_per_step")
+            force_traffic = tr.get("pair_force_bytes_per_step")
 
     pfield = None
     if args.phase_field_iters > 0:
@@ -231,7 +291,7 @@ def main():
         o.step(args.cpu_steps)
         tcs = time.perf_counter() - tc
         cpu = {"value": system.n * args.cpu_steps / tcs, "unit": "particle-steps/s",
-               "cores": oracle.num_threads(), "kind": "oracle",
+               "cores": oracle.num_threads(), "cpu_model": cpu_model(), "kind": "oracle",
                "sample": "%d full steps of the same %d-particle workload (FP64 C oracle, "
                          "OpenMP over particles), %.1f s" % (args.cpu_steps, system.n, tcs)}
         log("cpu baseline %.4e particle-steps/s in %.1fs" % (cpu["value"], tcs))
@@ -255,12 +315,20 @@ def main():
                    "dt": system.params["dt"], "graph": bool(args.graph),
                    "launch_shape": list(shape) if shape else None,
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "alu", "kernel": "pair_force", "achieved": achieved_tops,
-                     "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved_tops / VALU_PEAK_TOPS,
-                     "traffic": traffic, "avg_launch_ms": force_ms,
-                     "ops_per_launch": ops, "pairs": pairs, "candidates": cands},
-        "step_hbm": {"algorithmic_bytes": b_alg, "achieved_GBs": step_gbs,
-                     "peak_GBs": HBM_PEAK_GBS, "frac": step_gbs / HBM_PEAK_GBS},
+        "roofline": {"bound": "hbm", "kernel": "step (integrate + cell list + pair_force)",
+                     "achieved": step_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": step_gbs / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes": b_alg, "avg_step_ms": ms_per_step},
+        "pair_force": {"avg_ms_per_step": force_ms, "launches_per_step": force_launches_per_step,
+                       "pairs_ff": cnt["pairs_ff"], "pairs_fw": cnt["pairs_fw"],
+                       "candidates_ff_half": cnt["candidates_ff_half"],
+                       "candidates_fw": cnt["candidates_fw"],
+                       "valu": {"bound": "valu", "achieved": achieved_valu, "peak": valu,
+                                "unit": "VALU slots/s", "frac": achieved_valu / valu,
+                                "model_ops_per_step": ops,
+                                "peak_from": "dpd_valu_probe v_fmac_f32, measured in this run"},
+                       "hbm": {"algorithmic_bytes": force_bytes, "achieved_GBs": force_gbs,
+                               "frac": force_gbs / HBM_PEAK_GBS, "traffic": force_traffic}},
         "cpu_baseline": cpu,
         "batch": batch,
         "adjoint": adjoint,
@@ -524,6 +592,35 @@ def adjoint_leg(dpd, reps, steps=200, ckpt=20, nbins=40):
             "step_kernel_ms": {k: v[0] / max(v[1], 1) for k, v in kt.items() if v[1]}}
 
 
+def cpu_model():
+    """Model name of the host CPU (first 'model name' of /proc/cpuinfo) and
+    the number of logical CPUs."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return "%s (%d logical CPUs)" % (name, os.cpu_count() or 0)
+
+
+def reap_children():
+    """End any child process this run started (none is expected: the legs
+    use threads), so that nothing outlives the benchmark."""
+    try:
+        import psutil
+    except ImportError:
+        return
+    kids = psutil.Process().children(recursive=True)
+    for k in kids:
+        log("ending child process %d (%s)" % (k.pid, " ".join(k.cmdline()[:3])))
+        k.terminate()
+    psutil.wait_procs(kids, timeout=5)
+
+
 def kernel_source_hash(files=("device.h", "kernels.hip")):
     import hashlib
     h = hashlib.sha256()
@@ -535,3 +632,4 @@ def kernel_source_hash(files=("device.h", "kernels.hip")):
 
 if __name__ == "__main__":
     main()
+    reap_children()

@@ -362,6 +362,16 @@ int dpd_pair_random(uint64_t seed, uint64_t k, uint32_t replica, const uint32_t 
  * hardware byte counters are calibrated against. */
 int dpd_copy_probe(void *dst, const void *src, size_t bytes, void *hip_stream);
 
+/* VALU calibration kernel of known instruction count, on hip_stream: `waves`
+ * wavefronts (a multiple of 4; 256 threads per block) each execute exactly
+ * iters x 64 VALU instructions of one kind on eight independent register
+ * chains: kind 0 v_fmac_f32, 1 v_mad_u64_u32 (the 32 x 32 -> 64-bit
+ * multiply of Philox4x32-10), 2 v_xor_b32, 3 v_log_f32; each thread then
+ * writes one float to out (device, waves x 64 floats).  The reference for
+ * the issue rate of the vector ALU, as dpd_copy_probe is for HBM bytes.
+ * DPD_E_INVAL for a bad kind, waves <= 0, iters < 0 or out NULL. */
+int dpd_valu_probe(int32_t kind, int64_t waves, int32_t iters, float *out, void *hip_stream);
+
 /* ---- Snapshots (checkpoint and restart of a run) ----
  * The complete dynamic state of a context: every box's particles in the
  * library's internal cell-sorted order (positions with gids, velocities

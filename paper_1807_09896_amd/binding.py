@@ -40,7 +40,7 @@ EXPORTED = ["dpd_create", "dpd_step", "dpd_forces", "dpd_get_state", "dpd_set_st
             "dpd_replica_state", "dpd_replica_set_state", "dpd_replica_pairs",
             "dpd_replica_profile", "dpd_use_graph", "dpd_autotune", "dpd_set_params",
             "dpd_set_phi", "dpd_window_forward", "dpd_backward", "dpd_phi_relax",
-            "dpd_snapshot_size", "dpd_snapshot_io"]
+            "dpd_snapshot_size", "dpd_snapshot_io", "dpd_valu_probe"]
 
 
 class DPDError(RuntimeError):
@@ -127,6 +127,8 @@ def load_library(path: str = LIB_PATH):
     L.dpd_phi_relax.argtypes = [P, P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                 C.c_double, C.c_double, C.c_int32, C.POINTER(C.c_double), P]
     L.dpd_phi_relax.restype = C.c_int
+    L.dpd_valu_probe.argtypes = [C.c_int32, C.c_int64, C.c_int32, P, P]
+    L.dpd_valu_probe.restype = C.c_int
     L.dpd_pair_random.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, P, P, C.c_int64, P, P, P]
     L.dpd_pair_random.restype = C.c_int
     L.dpd_batch_create.argtypes = [C.c_int32, P, P, P, P, P, P, C.POINTER(P)]
@@ -457,6 +459,15 @@ def dpd_phi_relax(phi, work, h, eps, dtau, iters, residual=True, stream=None):
                                         C.byref(res) if residual else None,
                                         _stream_handle(stream)))
     return res.value if residual else None
+
+
+def dpd_valu_probe(kind, waves, iters, out, stream=None):
+    """Run the VALU calibration kernel (see include/dpd.h); out: float32
+    device tensor of waves * 64 elements."""
+    if out.numel() < waves * 64:
+        raise ValueError("out needs waves * 64 elements")
+    _check(load_library().dpd_valu_probe(int(kind), int(waves), int(iters), _ptr(out),
+                                         _stream_handle(stream)))
 
 
 def dpd_pair_random(seed, k, replica, gi, gj, words=None, xi=None, stream=None):

@@ -1653,6 +1653,13 @@ int dpd_copy_probe(void *dst, const void *src, size_t bytes, void *hip_stream) {
   return e == hipSuccess ? DPD_OK : DPD_E_DEVICE;
 }
 
+int dpd_valu_probe(int32_t kind, int64_t waves, int32_t iters, float *out, void *hip_stream) {
+  if (kind < 0 || kind > 3 || waves <= 0 || iters < 0 || !out) return DPD_E_INVAL;
+  if (waves * 64 / 256 > INT32_MAX) return DPD_E_INVAL;
+  hipError_t e = dpd::launch_valu_probe((hipStream_t)hip_stream, kind, waves, iters, out);
+  return e == hipSuccess ? DPD_OK : DPD_E_DEVICE;
+}
+
 // ---- Snapshots ----
 // Blob: header, then the cell-sorted device arrays of the current state:
 // positions of fluid and walls (NF + NW float4, gid bits in w), fluid

@@ -191,4 +191,9 @@ hipError_t launch_integrate_vjp(hipStream_t s, const Box *boxes, int64_t nf, con
 hipError_t launch_reduce_partials(hipStream_t s, int nb_f, const double *part_f, int nb_g,
                                   const double *part_g, double *out);
 
+// VALU calibration: `waves` wavefronts each run `iters` x 64 VALU
+// instructions of one kind (0: v_fmac_f32, 1: v_mad_u64_u32, 2: v_xor_b32,
+// 3: v_log_f32) on independent registers; out receives one float per thread.
+hipError_t launch_valu_probe(hipStream_t s, int kind, int64_t waves, int iters, float *out);
+
 }  // namespace dpd

@@ -61,6 +61,56 @@ __global__ void k_copy16(float4 *__restrict__ dst, const float4 *__restrict__ sr
   for (; i < n16; i += stride) dst[i] = src[i];
 }
 
+// VALU calibration: every thread runs `iters` x 64 VALU instructions of one
+// kind on 8 independent register chains (inline assembly, so the count is
+// exact), then stores one value so that nothing is dead.  Kinds: 0
+// v_fmac_f32, 1 v_mad_u64_u32 (the 32 x 32 -> 64-bit multiply of Philox),
+// 2 v_xor_b32, 3 v_log_f32 (a transcendental).
+#define DPD_PROBE8(INS) INS(0) INS(1) INS(2) INS(3) INS(4) INS(5) INS(6) INS(7)
+template <int KIND>
+__global__ __launch_bounds__(256) void k_valu_probe(int iters, float *out) {
+  const uint32_t t = threadIdx.x + blockIdx.x * blockDim.x;
+  float f[8];
+  uint32_t u[8];
+  uint64_t w[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    f[k] = (float)(t + k) * 1e-3f + 1.0f;
+    u[k] = t * 2654435761u + (uint32_t)k;
+    w[k] = (uint64_t)u[k] << 7;
+  }
+  const float fb = 1.0000001f, fc = 1e-7f;
+  const uint32_t ub = 0x9E3779B9u;
+  uint64_t cy = 0;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int rep = 0; rep < 8; ++rep) {
+      if (KIND == 0) {
+#define DPD_FMA(k) asm volatile("v_fmac_f32 %0, %1, %2" : "+v"(f[k]) : "v"(fb), "v"(fc));
+        DPD_PROBE8(DPD_FMA)
+#undef DPD_FMA
+      } else if (KIND == 1) {
+#define DPD_MAD(k) asm volatile("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(w[k]), "=s"(cy) : "v"(u[k]), "v"(ub));
+        DPD_PROBE8(DPD_MAD)
+#undef DPD_MAD
+      } else if (KIND == 2) {
+#define DPD_XOR(k) asm volatile("v_xor_b32 %0, %1, %0" : "+v"(u[k]) : "v"(ub));
+        DPD_PROBE8(DPD_XOR)
+#undef DPD_XOR
+      } else {
+#define DPD_LOG(k) asm volatile("v_log_f32 %0, %0" : "+v"(f[k]));
+        DPD_PROBE8(DPD_LOG)
+#undef DPD_LOG
+      }
+    }
+  }
+  float acc = 0.f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) acc += f[k] + (float)u[k] + (float)(uint32_t)w[k];
+  out[t] = acc + (float)(uint32_t)cy;
+}
+#undef DPD_PROBE8
+
 __global__ void k_copy1(uint8_t *__restrict__ dst, const uint8_t *__restrict__ src, size_t n) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = src[i];
@@ -1244,6 +1294,15 @@ hipError_t launch_fill_zero(hipStream_t s, void *p, size_t bytes) {
   unsigned blocks = (unsigned)((words + kBlock - 1) / kBlock);
   if (blocks > 4096) blocks = 4096;
   k_fill_zero<<<blocks, kBlock, 0, s>>>((uint32_t *)p, words);
+  return hipGetLastError();
+}
+
+hipError_t launch_valu_probe(hipStream_t s, int kind, int64_t waves, int iters, float *out) {
+  const unsigned blocks = (unsigned)((waves * 64 + 255) / 256);
+  if (kind == 0) k_valu_probe<0><<<blocks, 256, 0, s>>>(iters, out);
+  else if (kind == 1) k_valu_probe<1><<<blocks, 256, 0, s>>>(iters, out);
+  else if (kind == 2) k_valu_probe<2><<<blocks, 256, 0, s>>>(iters, out);
+  else k_valu_probe<3><<<blocks, 256, 0, s>>>(iters, out);
   return hipGetLastError();
 }
 

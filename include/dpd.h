@@ -423,6 +423,21 @@ int dpd_snapshot_io(dpd_ctx *ctx, int32_t dir, void *blob);
 int dpd_phi_relax(void *phi, void *work, int32_t dtype, const int32_t n[3], const double h[3],
                   double eps, double dtau, int32_t iters, double *residual, void *hip_stream);
 
+/* The relaxation of dpd_phi_relax with no workspace argument and no device
+ * allocation, for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc).  The
+ * ping-pong buffer and the residual word live in a static device array of
+ * the library, 64 MiB + 256 bytes, held by each GPU the library runs on
+ * until the process ends; grids of at most 16,777,216 float32 or 8,388,608
+ * float64 nodes, larger ones DPD_E_INVAL (use dpd_phi_relax).  Results are
+ * identical to dpd_phi_relax's.  All calls on one GPU share that array:
+ * calls that overlap on one GPU (other streams, other threads) race, and
+ * must be serialised by the caller.  Other arguments, errors and the
+ * residual as for dpd_phi_relax. */
+int dpd_phi_relax_static(void *phi, int32_t dtype, const int32_t n[3], const double h[3],
+                         double eps, double dtau, int32_t iters, double *residual,
+                         void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -40,7 +40,7 @@ EXPORTED = ["dpd_create", "dpd_step", "dpd_forces", "dpd_get_state", "dpd_set_st
             "dpd_replica_state", "dpd_replica_set_state", "dpd_replica_pairs",
             "dpd_replica_profile", "dpd_use_graph", "dpd_autotune", "dpd_set_params",
             "dpd_set_phi", "dpd_window_forward", "dpd_backward", "dpd_phi_relax",
-            "dpd_snapshot_size", "dpd_snapshot_io", "dpd_valu_probe"]
+            "dpd_snapshot_size", "dpd_snapshot_io", "dpd_valu_probe", "dpd_phi_relax_static"]
 
 
 class DPDError(RuntimeError):
@@ -127,6 +127,10 @@ def load_library(path: str = LIB_PATH):
     L.dpd_phi_relax.argtypes = [P, P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                 C.c_double, C.c_double, C.c_int32, C.POINTER(C.c_double), P]
     L.dpd_phi_relax.restype = C.c_int
+    L.dpd_phi_relax_static.argtypes = [P, C.c_int32, C.POINTER(C.c_int32),
+                                       C.POINTER(C.c_double), C.c_double, C.c_double, C.c_int32,
+                                       C.POINTER(C.c_double), P]
+    L.dpd_phi_relax_static.restype = C.c_int
     L.dpd_valu_probe.argtypes = [C.c_int32, C.c_int64, C.c_int32, P, P]
     L.dpd_valu_probe.restype = C.c_int
     L.dpd_pair_random.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, P, P, C.c_int64, P, P, P]
@@ -458,6 +462,22 @@ def dpd_phi_relax(phi, work, h, eps, dtau, iters, residual=True, stream=None):
                                         float(eps), float(dtau), int(iters),
                                         C.byref(res) if residual else None,
                                         _stream_handle(stream)))
+    return res.value if residual else None
+
+
+def dpd_phi_relax_static(phi, h, eps, dtau, iters, residual=True, stream=None):
+    """dpd_phi_relax without a workspace: the library's static device scratch
+    holds the ping-pong buffer (grids up to 64 MiB)."""
+    import torch
+    if phi.dim() != 3 or not phi.is_contiguous() or phi.dtype not in (torch.float32, torch.float64):
+        raise ValueError("phi must be a contiguous (nz, ny, nx) float32 or float64 tensor")
+    n = (C.c_int32 * 3)(int(phi.shape[2]), int(phi.shape[1]), int(phi.shape[0]))
+    hh = (C.c_double * 3)(*[float(x) for x in h])
+    res = C.c_double(0.0)
+    _check(load_library().dpd_phi_relax_static(_ptr(phi), int(phi.element_size()), n, hh,
+                                               float(eps), float(dtau), int(iters),
+                                               C.byref(res) if residual else None,
+                                               _stream_handle(stream)))
     return res.value if residual else None
 
 

@@ -1787,7 +1787,18 @@ int dpd_snapshot_io(dpd_ctx *c, int32_t dir, void *blob) {
 
 int dpd_phi_relax(void *phi, void *work, int32_t dtype, const int32_t n[3], const double h[3],
                   double eps, double dtau, int32_t iters, double *residual, void *hip_stream) {
-  if (!phi || !work || !n || !h) return fail(nullptr, DPD_E_INVAL, "NULL argument");
+  return dpd::phi_relax_run(phi, work, dtype, n, h, eps, dtau, iters, residual, hip_stream);
+}
+
+}  // extern "C"
+
+int dpd::fail_global(int code, const char *msg) { return fail(nullptr, code, msg); }
+
+// Argument checks and launches of dpd_phi_relax (also the body of the
+// allocation-free variant, which passes its static scratch as `work`).
+int dpd::phi_relax_check(const void *phi, int32_t dtype, const int32_t n[3], const double h[3],
+                         double eps, double dtau, int32_t iters) {
+  if (!phi || !n || !h) return fail(nullptr, DPD_E_INVAL, "NULL argument");
   if (dtype != 4 && dtype != 8) return fail(nullptr, DPD_E_INVAL, "dtype must be 4 or 8");
   for (int a = 0; a < 3; ++a) {
     if (n[a] < 1) return fail(nullptr, DPD_E_INVAL, "grid sizes must be >= 1");
@@ -1802,6 +1813,15 @@ int dpd_phi_relax(void *phi, void *work, int32_t dtype, const int32_t n[3], cons
     return fail(nullptr, DPD_E_INVAL, "need 0 < dtau <= 1 / (2 sum (eps/h)^2)");
   if (iters < 0) return fail(nullptr, DPD_E_INVAL, "iters must be >= 0");
   if (dpd::phi_relax_blocks(n) > INT32_MAX) return fail(nullptr, DPD_E_INVAL, "grid too large");
+  return DPD_OK;
+}
+
+int dpd::phi_relax_run(void *phi, void *work, int32_t dtype, const int32_t n[3],
+                       const double h[3], double eps, double dtau, int32_t iters,
+                       double *residual, void *hip_stream) {
+  const int chk = phi_relax_check(phi, dtype, n, h, eps, dtau, iters);
+  if (chk) return chk;
+  if (!work) return fail(nullptr, DPD_E_INVAL, "NULL argument");
   hipStream_t s = (hipStream_t)hip_stream;
   const size_t es = (size_t)dtype;
   const size_t nodes = (size_t)n[0] * n[1] * n[2];
@@ -1842,5 +1862,3 @@ int dpd_phi_relax(void *phi, void *work, int32_t dtype, const int32_t n[3], cons
   }
   return DPD_OK;
 }
-
-}  // extern "C"

@@ -191,6 +191,17 @@ hipError_t launch_integrate_vjp(hipStream_t s, const Box *boxes, int64_t nf, con
 hipError_t launch_reduce_partials(hipStream_t s, int nb_f, const double *part_f, int nb_g,
                                   const double *part_g, double *out);
 
+// Argument checks of dpd_phi_relax (DPD_OK or a DPD_E_* code, with the
+// message kept for dpd_last_error(NULL)), and the relaxation itself with
+// `work` as the ping-pong buffer (n[0] n[1] n[2] values) followed by the
+// residual word.  Defined with the C ABI in api.hip.
+int phi_relax_check(const void *phi, int32_t dtype, const int32_t n[3], const double h[3],
+                    double eps, double dtau, int32_t iters);
+int phi_relax_run(void *phi, void *work, int32_t dtype, const int32_t n[3], const double h[3],
+                  double eps, double dtau, int32_t iters, double *residual, void *hip_stream);
+// Record a failure message for dpd_last_error(NULL); returns code.
+int fail_global(int code, const char *msg);
+
 // VALU calibration: `waves` wavefronts each run `iters` x 64 VALU
 // instructions of one kind (0: v_fmac_f32, 1: v_mad_u64_u32, 2: v_xor_b32,
 // 3: v_log_f32) on independent registers; out receives one float per thread.

@@ -18,7 +18,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdpdphi.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["kernels.hip", "adjoint.hip", "phase_field.hip", "api.hip", "noalloc.hip"]
+SOURCES = ["kernels.hip", "force_brick.hip", "adjoint.hip", "phase_field.hip", "api.hip",
+           "noalloc.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

@@ -54,6 +54,7 @@ struct Replica {
   double L[3] = {0, 0, 0}, h[3] = {0, 0, 0};
   double rc = 0;
   bool moving = false;   // some wall particle has a nonzero velocity
+  bool brick = false;    // pair forces by the LDS-staged brick kernel
   KGeom G{};
   KParams P{};
   int64_t flagged_cubes = 0;
@@ -99,6 +100,12 @@ struct dpd_ctx {
   Tile *itiles = nullptr, *ftiles = nullptr;
   int n_itiles = 0, n_ftiles = 0;
   int itiles_cap = 0, ftiles_cap = 0;
+  // pair forces: bricks of the boxes that take the LDS-staged kernel, and
+  // tiles of fluid slots of the others (the per-particle kernel)
+  dpd::Brick *bricks = nullptr;
+  int nbricks = 0;
+  Tile *otiles = nullptr;
+  int n_otiles = 0, otiles_cap = 0;
 
   float4 *pos[2] = {nullptr, nullptr}, *vel[2] = {nullptr, nullptr}, *frc[2] = {nullptr, nullptr};
   float4 *vt = nullptr;
@@ -291,11 +298,14 @@ bool finite3(const float *p) {
   return std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]);
 }
 
-// Tile tables: runs of consecutive particles of one box, `size` per tile.
-int build_tiles(dpd_ctx *c, int size, Tile **dst, int *n, int *cap) {
+// Tile tables: runs of consecutive particles of one box, `size` per tile
+// (without_bricks: only the boxes whose pair forces take the per-particle
+// kernel).
+int build_tiles(dpd_ctx *c, int size, Tile **dst, int *n, int *cap, bool without_bricks = false) {
   std::vector<Tile> t;
   for (int r = 0; r < c->R; ++r) {
     const Replica &p = c->rep[r];
+    if (without_bricks && p.brick) continue;
     for (int64_t f = 0; f < p.nf; f += size) {
       Tile x;
       x.box = r;
@@ -325,7 +335,67 @@ int set_shapes(dpd_ctx *c, int ppt, int fblock) {
   drop_graphs(c);
   int rc = build_tiles(c, 256 * ppt, &c->itiles, &c->n_itiles, &c->itiles_cap);
   if (!rc) rc = build_tiles(c, fblock, &c->ftiles, &c->n_ftiles, &c->ftiles_cap);
+  if (!rc) rc = build_tiles(c, fblock, &c->otiles, &c->n_otiles, &c->otiles_cap, true);
   return rc;
+}
+
+// Cuts of one axis of n cells into bricks of at most B cells.  The brick at
+// the high edge holds at most (n - 3) / 2 cells, so that every column its
+// halo stages without wrapping lies at x >= L/2 and moves by -L exactly
+// (Sterbenz); every axis needs at least two bricks.  Empty when the axis is
+// too short (n < 5): such boxes take the per-particle kernel.
+std::vector<std::pair<int, int>> axis_bricks(int n, int B) {
+  std::vector<std::pair<int, int>> v;
+  const int last = std::min(B, (n - 3) / 2);
+  if (n < 5 || last < 1) return v;
+  const int rest = n - last;
+  for (int x = 0; x < rest; x += B) v.push_back({x, std::min(B, rest - x)});
+  v.push_back({rest, last});
+  return v;
+}
+
+// Brick table of every box that can be cut (x fastest, then y, then z, so
+// that consecutive blocks work on neighbouring bricks), and the flag of the
+// boxes that cannot.  The per-particle kernel is the default;
+// DPD_PAIR_KERNEL=bricks in the environment at create selects the brick
+// kernel for every box that can be cut.
+int build_bricks(dpd_ctx *c) {
+  const char *env = std::getenv("DPD_PAIR_KERNEL");
+  const bool cells_only = !(env && std::strcmp(env, "bricks") == 0);
+  std::vector<dpd::Brick> t;
+  for (int r = 0; r < c->R; ++r) {
+    Replica &p = c->rep[r];
+    p.brick = false;
+    if (cells_only || p.nf == 0) continue;
+    const auto bx = axis_bricks(p.nc[0], dpd::kBrickX), by = axis_bricks(p.nc[1], dpd::kBrickY),
+               bz = axis_bricks(p.nc[2], dpd::kBrickZ);
+    if (bx.empty() || by.empty() || bz.empty()) continue;
+    p.brick = true;
+    for (const auto &z : bz)
+      for (const auto &y : by)
+        for (const auto &x : bx) {
+          dpd::Brick b;
+          b.box = r;
+          b.x0 = x.first;
+          b.sx = x.second;
+          b.y0 = y.first;
+          b.sy = y.second;
+          b.z0 = z.first;
+          b.sz = z.second;
+          b.pad = 0;
+          t.push_back(b);
+        }
+  }
+  if (c->bricks) dfree(c, c->bricks);
+  c->bricks = nullptr;
+  c->nbricks = (int)t.size();
+  if (t.empty()) return DPD_OK;
+  c->bricks = (dpd::Brick *)dalloc(c, sizeof(dpd::Brick) * t.size());
+  if (!c->bricks) return fail(c, DPD_E_NOMEM, "brick table allocation failed");
+  HIP_TRY(c, hipMemcpyAsync(c->bricks, t.data(), sizeof(dpd::Brick) * t.size(),
+                            hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return DPD_OK;
 }
 
 // Bin the current fluid positions of every box (counting-sort pass 1).
@@ -368,13 +438,22 @@ int scan_scatter_sort(dpd_ctx *c, hipStream_t s, const float4 *key4 = nullptr,
 // Forces at the current state in sorted order; init = 1 keeps velocities.
 int force_pass(dpd_ctx *c, hipStream_t s, int init) {
   const int a = c->cur, b = 1 - c->cur;
-  HIP_TRY(c, timed(c, s, K_FORCE, [&] {
-            return dpd::launch_force(s, c->fblock, c->boxes, c->ftiles, c->n_ftiles, c->NF,
-                                     (int32_t)(c->NF + c->NW), (int32_t)c->NCELL, init, c->pos[a],
-                                     c->vt, c->vel[a],
-                                     c->frc[a], c->idx, c->idx_all, c->start_all, c->pos[b],
-                                     c->vel[b], c->frc[b], c->dk, c->status, c->sph ? 1 : 0);
-          }));
+  if (c->n_otiles > 0)
+    HIP_TRY(c, timed(c, s, K_FORCE, [&] {
+              return dpd::launch_force(s, c->fblock, c->boxes, c->otiles, c->n_otiles, c->NF,
+                                       (int32_t)(c->NF + c->NW), (int32_t)c->NCELL, init,
+                                       c->pos[a], c->vt, c->vel[a], c->frc[a], c->idx,
+                                       c->idx_all, c->start_all, c->pos[b], c->vel[b], c->frc[b],
+                                       c->dk, c->status, c->sph ? 1 : 0);
+            }));
+  if (c->nbricks > 0)
+    HIP_TRY(c, timed(c, s, K_FORCE, [&] {
+              return dpd::launch_force_brick(s, c->boxes, c->bricks, c->nbricks, c->NF,
+                                             (int32_t)(c->NF + c->NW), init, c->pos[a], c->vt,
+                                             c->vel[a], c->frc[a], c->idx_all, c->start_all,
+                                             c->fluid_off, c->cstart, c->pos[b], c->vel[b],
+                                             c->frc[b], c->dk, c->status, c->sph ? 1 : 0);
+            }));
   c->cur = b;
   return DPD_OK;
 }
@@ -950,7 +1029,8 @@ int create_impl(int32_t nbox, const dpd_box *boxes, const dpd_particles *parts,
         "upload boxes");
     if (rc) return bail(rc);
   }
-  rc = set_shapes(c, 2, 256);
+  rc = build_bricks(c);
+  if (!rc) rc = set_shapes(c, 2, 256);
   if (rc) return bail(rc);
   c->cur = 0;
   c->k = 0;
@@ -1792,10 +1872,10 @@ int dpd_phi_relax(void *phi, void *work, int32_t dtype, const int32_t n[3], cons
 
 }  // extern "C"
 
-int dpd::fail_global(int code, const char *msg) { return fail(nullptr, code, msg); }
-
 // Argument checks and launches of dpd_phi_relax (also the body of the
 // allocation-free variant, which passes its static scratch as `work`).
+int dpd::fail_global(int code, const char *msg) { return fail(nullptr, code, msg); }
+
 int dpd::phi_relax_check(const void *phi, int32_t dtype, const int32_t n[3], const double h[3],
                          double eps, double dtau, int32_t iters) {
   if (!phi || !n || !h) return fail(nullptr, DPD_E_INVAL, "NULL argument");

@@ -78,6 +78,17 @@ struct Tile {
   int32_t pad;
 };
 
+// A brick of cells of one box, the work of one block of the LDS-staged pair
+// kernel: home cells [x0, x0 + sx) x [y0, y0 + sy) x [z0, z0 + sz), at most
+// kBrickX x kBrickY x kBrickZ.
+constexpr int kBrickX = 8, kBrickY = 4, kBrickZ = 4;
+struct Brick {
+  int32_t box;
+  int32_t x0, y0, z0;
+  int32_t sx, sy, sz;
+  int32_t pad;
+};
+
 // Device status counters, read back by the host at sync points.
 struct Status {
   unsigned long long bounce;     // bounce-backs by Eq. 17 (code 1)

@@ -115,6 +115,18 @@ hipError_t launch_force(hipStream_t s, int block, const Box *boxes, const Tile *
                         float4 *pos_out, float4 *vel_out, float4 *frc_out,
                         const unsigned long long *dk, Status *st, int sph);
 
+// The same pair forces, body force and velocity update for the boxes cut
+// into bricks: one block per brick stages the brick's cells and a one-cell
+// halo in LDS (force_brick.hip).  cstart: fluid slot start of each cell;
+// fluid_off: start of each cell's fluid part in the merged run.
+hipError_t launch_force_brick(hipStream_t s, const Box *boxes, const Brick *bricks, int nbricks,
+                              int64_t NF, int32_t pad, int init, const float4 *pos4,
+                              const float4 *vt4, const float4 *vel4, const float4 *frc4,
+                              const int32_t *idx_all, const int32_t *start_all,
+                              const int32_t *fluid_off, const int32_t *cstart, float4 *pos_out,
+                              float4 *vel_out, float4 *frc_out, const unsigned long long *dk,
+                              Status *st, int sph);
+
 // Interacting pairs (gid_i, gid_j) from each fluid particle of one box
 // (slots [first, first + nf), cells from cell_off).
 hipError_t launch_pairs(hipStream_t s, const KGeom &G, const KParams &P, int64_t cell_off,

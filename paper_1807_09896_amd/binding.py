@@ -40,7 +40,8 @@ EXPORTED = ["dpd_create", "dpd_step", "dpd_forces", "dpd_get_state", "dpd_set_st
             "dpd_replica_state", "dpd_replica_set_state", "dpd_replica_pairs",
             "dpd_replica_profile", "dpd_use_graph", "dpd_autotune", "dpd_set_params",
             "dpd_set_phi", "dpd_window_forward", "dpd_backward", "dpd_phi_relax",
-            "dpd_snapshot_size", "dpd_snapshot_io", "dpd_valu_probe", "dpd_phi_relax_static"]
+            "dpd_snapshot_size", "dpd_snapshot_io", "dpd_valu_probe", "dpd_phi_relax_static",
+            "dpd_window_trace"]
 
 
 class DPDError(RuntimeError):
@@ -131,6 +132,8 @@ def load_library(path: str = LIB_PATH):
                                        C.POINTER(C.c_double), C.c_double, C.c_double, C.c_int32,
                                        C.POINTER(C.c_double), P]
     L.dpd_phi_relax_static.restype = C.c_int
+    L.dpd_window_trace.argtypes = [P, P, P]
+    L.dpd_window_trace.restype = C.c_int
     L.dpd_valu_probe.argtypes = [C.c_int32, C.c_int64, C.c_int32, P, P]
     L.dpd_valu_probe.restype = C.c_int
     L.dpd_pair_random.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, P, P, C.c_int64, P, P, P]
@@ -479,6 +482,12 @@ def dpd_phi_relax_static(phi, h, eps, dtau, iters, residual=True, stream=None):
                                                C.byref(res) if residual else None,
                                                _stream_handle(stream)))
     return res.value if residual else None
+
+
+def dpd_window_trace(ctx, pos_log=None, ev_log=None):
+    """Positions (steps, n, 3 float32) and event codes (steps, n int32) after
+    every step of the recorded window, in gid order (device tensors)."""
+    _check(load_library().dpd_window_trace(ctx, _ptr(pos_log), _ptr(ev_log)), ctx)
 
 
 def dpd_valu_probe(kind, waves, iters, out, stream=None):

@@ -1277,6 +1277,56 @@ int backward_impl(dpd_ctx *c, const double *dldp, double *grads, double *dphi) {
   return latched_error(c);
 }
 
+// The recorded window's trajectory again, segment by segment from its
+// checkpoints as the backward sweep recomputes it: after step t (0-based),
+// positions and event codes of every particle in gid order into
+// pos_log + 3 n t and ev_log + n t (walls repeat their positions, events 0).
+// The context's state, k and counters are left as they were.
+int trace_impl(dpd_ctx *c, float *pos_log, int32_t *ev_log) {
+  Window &W = c->win;
+  const int64_t NF = c->NF;
+  const Replica &p = c->rep[0];
+  hipStream_t s = c->stream;
+  const int cur0 = c->cur;
+  const uint64_t k_save = c->k;
+  const int64_t steps_save = c->steps;
+  int rc = save_state(c, W.save);
+  if (rc) return rc;
+  HIP_TRY(c, hipMemcpyAsync(W.status_save, c->status, sizeof(Status), hipMemcpyDeviceToDevice, s));
+  const bool timing = c->timing;
+  c->timing = false;
+  for (int seg = 0; seg < W.nck && !rc; ++seg) {
+    const int t0 = seg * W.ckpt, t1 = std::min(W.steps, t0 + W.ckpt);
+    rc = load_state(c, W.ck + (size_t)seg * 3 * NF);
+    if (rc) break;
+    c->k = W.k0 + (uint64_t)t0;
+    HIP_TRY(c, dpd::launch_set_u64(s, c->dk, c->k));
+    for (int t = t0; t < t1 && !rc; ++t) {
+      rc = one_step(c);
+      if (rc) break;
+      float *pl = pos_log ? pos_log + (size_t)3 * p.n * t : nullptr;
+      int32_t *el = ev_log ? ev_log + (size_t)p.n * t : nullptr;
+      HIP_TRY(c, dpd::launch_export(s, p.G, p.nf, c->pos[c->cur] + p.fo, c->vel[c->cur] + p.fo,
+                                    c->frc[c->cur] + p.fo, 0, pl, nullptr, nullptr, el,
+                                    nullptr));
+      HIP_TRY(c, dpd::launch_export(s, p.G, p.nw, c->pos[c->cur] + c->NF + p.wo,
+                                    c->vt + c->NF + p.wo, nullptr, 1, pl, nullptr, nullptr, el,
+                                    nullptr));
+    }
+  }
+  c->timing = timing;
+  c->cur = cur0;
+  c->k = k_save;
+  c->steps = steps_save;
+  int r2 = load_state(c, W.save);
+  if (!rc) rc = r2;
+  HIP_TRY(c, hipMemcpyAsync(c->status, W.status_save, sizeof(Status), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(c, dpd::launch_set_u64(s, c->dk, c->k));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  if (rc) return rc;
+  return latched_error(c);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1703,6 +1753,14 @@ int dpd_backward(dpd_ctx *c, const double *dL_dprofile, double *grads, double *d
     return fail(c, DPD_E_STATE, "parameters, phi or state changed since the window was recorded");
   if (!dL_dprofile) return fail(c, DPD_E_INVAL, "dL_dprofile is NULL");
   return backward_impl(c, dL_dprofile, grads, dL_dphi);
+}
+
+int dpd_window_trace(dpd_ctx *c, float *pos_log, int32_t *ev_log) {
+  if (!c) return DPD_E_INVAL;
+  if (!c->win.valid) return fail(c, DPD_E_STATE, "trace needs a recorded window");
+  if (c->win.gen != c->gen)
+    return fail(c, DPD_E_STATE, "parameters, phi or state changed since the window was recorded");
+  return trace_impl(c, pos_log, ev_log);
 }
 
 int dpd_sync(dpd_ctx *c) {

@@ -81,7 +81,7 @@ struct Tile {
 // A brick of cells of one box, the work of one block of the LDS-staged pair
 // kernel: home cells [x0, x0 + sx) x [y0, y0 + sy) x [z0, z0 + sz), at most
 // kBrickX x kBrickY x kBrickZ.
-constexpr int kBrickX = 8, kBrickY = 4, kBrickZ = 4;
+constexpr int kBrickX = 4, kBrickY = 4, kBrickZ = 4;
 struct Brick {
   int32_t box;
   int32_t x0, y0, z0;

@@ -44,21 +44,23 @@ namespace {
 constexpr int kBT = 256;                 // threads per block
 constexpr int kWaves = kBT / 64;
 constexpr int kHCmax = (kBrickX + 2) * (kBrickY + 2) * (kBrickZ + 2);
-constexpr int kHomeCells = kBrickX * kBrickY * kBrickZ;
-constexpr int kCap = 1536;               // staged particles
-constexpr int kHomeCap = 704;            // home fluid particles
-constexpr int kQ = 512;                  // per-wavefront ring of kept pairs
-constexpr int kStack = 24;               // sub-bricks pending
-constexpr int kPassB = 4;                // candidates per lane and pass
+constexpr int kCap = 1152;               // staged particles
+constexpr int kHomeCap = 384;            // home fluid particles
+constexpr int kQ = 256;                  // per-wavefront ring of kept pairs
+constexpr int kStack = 16;               // sub-bricks pending
+constexpr int kPass = 4;                 // candidates per lane and pass
 constexpr int kStagePer = (kCap + kBT - 1) / kBT;
+constexpr int kHomePer = (kHomeCap + kBT - 1) / kBT;
 constexpr float kFix = 4294967296.0f;     // 2^32
 constexpr float kFixInv = 2.3283064365386963e-10f;   // 2^-32
 
 struct BrickShared {
-  float4 P[kCap];                     // staged positions (brick frame), gid bits in w
+  // staged particles: position in the brick frame, w = home slot (int bits)
+  // of a home fluid particle or -1; kPass spare entries so that a pass may
+  // read past the end of a run
+  float4 P[kCap + kPass];
+  uint32_t gid[kCap];
   int32_t J[kCap];                    // storage index: fluid i, or NF + w for walls
-  int16_t Sl[kCap];                   // home slot of a home fluid particle, else -1
-  int16_t ecell[kCap];                // haloed cell of each staged particle
   unsigned long long acc[3 * kHomeCap];   // fixed-point force sums
   int16_t hl[kHomeCap];               // staged index of home slot h
   int16_t hc[kHomeCap];               // haloed cell of home slot h
@@ -66,8 +68,12 @@ struct BrickShared {
   int32_t cs[kHCmax + 1];             // staged start of each haloed cell's run
   int32_t hstart[kHCmax + 1];         // home-slot start of each haloed cell
   int32_t run[kHCmax];                // merged-run start (start_all) of each haloed cell
+  int32_t fslot[kHCmax];              // fluid slot start (cstart) of each home cell
   int16_t nwall[kHCmax];              // walls at the head of each haloed cell's run
-  uint32_t queue[kWaves][kQ];
+  union {
+    int16_t ecell[kCap];              // haloed cell of each staged particle (staging)
+    uint32_t queue[kWaves][kQ + 64];  // kept pairs (walk); the last 64: discarded appends
+  } u;
   int32_t wsum[2][kWaves];
   int32_t stack[kStack][6];
 };
@@ -81,14 +87,13 @@ __device__ __forceinline__ void block_scan2(int32_t *a, int32_t *b, int n, int32
   int sa = 0, sb = 0;
   int va[kPer], vb[kPer];
 #pragma unroll
-  for (int u = 0; u < kPer; ++u) {
-    const int i = first + u;
-    va[u] = i < n ? a[i] : 0;
-    vb[u] = i < n ? b[i] : 0;
-    sa += va[u];
-    sb += vb[u];
+  for (int k = 0; k < kPer; ++k) {
+    const int i = first + k;
+    va[k] = i < n ? a[i] : 0;
+    vb[k] = i < n ? b[i] : 0;
+    sa += va[k];
+    sb += vb[k];
   }
-  // inclusive wavefront scan of the per-thread sums
   int ia = sa, ib = sb;
   for (int off = 1; off < 64; off <<= 1) {
     const int xa = __shfl_up(ia, off, 64), xb = __shfl_up(ib, off, 64);
@@ -113,14 +118,14 @@ __device__ __forceinline__ void block_scan2(int32_t *a, int32_t *b, int n, int32
   }
   int ea = oa + ia - sa, eb = ob + ib - sb;
 #pragma unroll
-  for (int u = 0; u < kPer; ++u) {
-    const int i = first + u;
+  for (int k = 0; k < kPer; ++k) {
+    const int i = first + k;
     if (i < n) {
       a[i] = ea;
       b[i] = eb;
     }
-    ea += va[u];
-    eb += vb[u];
+    ea += va[k];
+    eb += vb[k];
   }
   if (t == 0) {
     a[n] = ta;
@@ -188,7 +193,8 @@ __global__ __launch_bounds__(kBT) void k_force_brick(
   const unsigned long long kk = *dk;
   const uint32_t klo = (uint32_t)kk;
   const uint32_t khi = ((uint32_t)(kk >> 32) & 0xFFFFu) | (P.replica << 16);
-  const Records16 posr(pos4, pad + 1), vtr(vt4, pad + 1);
+  const Records16 posr(pos4, pad + 1), vtr(vt4, pad + 1), velr(vel4, (int)NF),
+      frcr(frc4, (int)NF);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   bool bad = false;      // a non-finite or out-of-range pair force (this thread)
   bool dense = false;    // a single cell whose neighbourhood exceeds LDS
@@ -213,7 +219,8 @@ __global__ __launch_bounds__(kBT) void k_force_brick(
     // moves by -L)
     const bool hix = x0 + sx == nx, hiy = y0 + sy == ny, hiz = z0 + sz == nz;
 
-    // counts of each haloed cell's run, and of the fluid of home cells
+    // counts of each haloed cell's run and of the fluid of home cells, and
+    // the fluid slot start of home cells (one level of global loads)
     for (int c = tid; c < HC; c += kBT) {
       const int a = c % HX, bb = (c / HX) % HY, cc = c / (HX * HY);
       int gx = x0 - 1 + a, gy = y0 - 1 + bb, gz = z0 - 1 + cc;
@@ -221,12 +228,14 @@ __global__ __launch_bounds__(kBT) void k_force_brick(
       gy += gy < 0 ? ny : (gy >= ny ? -ny : 0);
       gz += gz < 0 ? nz : (gz >= nz ? -nz : 0);
       const int gc = co + (gz * ny + gy) * nx + gx;
-      const int r0 = start_all[gc], r1 = start_all[gc + 1], f0 = fluid_off[gc];
       const bool home = a >= 1 && a <= sx && bb >= 1 && bb <= sy && cc >= 1 && cc <= sz;
+      const int r0 = start_all[gc], r1 = start_all[gc + 1], f0 = fluid_off[gc];
+      const int fs = home ? cstart[gc] : 0;
       S.run[c] = r0;
       S.nwall[c] = (int16_t)(f0 - r0);
       S.cs[c] = r1 - r0;
       S.hstart[c] = home ? r1 - f0 : 0;
+      S.fslot[c] = fs;
     }
     __syncthreads();
     block_scan2(S.cs, S.hstart, HC, S.wsum);
@@ -261,39 +270,40 @@ __global__ __launch_bounds__(kBT) void k_force_brick(
     // the haloed cell of every staged particle
     for (int c = tid; c < HC; c += kBT) {
       const int k0 = S.cs[c], k1 = S.cs[c + 1];
-      for (int k = k0; k < k1; ++k) S.ecell[k] = (int16_t)c;
+      for (int k = k0; k < k1; ++k) S.u.ecell[k] = (int16_t)c;
     }
     __syncthreads();
 
-    // stage positions in the brick frame, storage indices, no home slot yet
+    // stage positions in the brick frame (w = -1 for now), gids, storage indices
     {
       int tk[kStagePer], jk[kStagePer];
       float shx[kStagePer], shy[kStagePer], shz[kStagePer];
 #pragma unroll
-      for (int u = 0; u < kStagePer; ++u) {
-        const int k = tid + u * kBT;
-        tk[u] = -1;
-        shx[u] = shy[u] = shz[u] = 0.f;
+      for (int m = 0; m < kStagePer; ++m) {
+        const int k = tid + m * kBT;
+        tk[m] = -1;
+        shx[m] = shy[m] = shz[m] = 0.f;
         if (k < N) {
-          const int c = S.ecell[k];
+          const int c = S.u.ecell[k];
           const int a = c % HX, bb = (c / HX) % HY, cc = c / (HX * HY);
-          tk[u] = S.run[c] + (k - S.cs[c]);
+          tk[m] = S.run[c] + (k - S.cs[c]);
           const int gx = x0 - 1 + a, gy = y0 - 1 + bb, gz = z0 - 1 + cc;
-          shx[u] = (hix ? gx < nx : gx < 0) ? G.L[0] : 0.f;
-          shy[u] = (hiy ? gy < ny : gy < 0) ? G.L[1] : 0.f;
-          shz[u] = (hiz ? gz < nz : gz < 0) ? G.L[2] : 0.f;
+          shx[m] = (hix ? gx < nx : gx < 0) ? G.L[0] : 0.f;
+          shy[m] = (hiy ? gy < ny : gy < 0) ? G.L[1] : 0.f;
+          shz[m] = (hiz ? gz < nz : gz < 0) ? G.L[2] : 0.f;
         }
       }
 #pragma unroll
-      for (int u = 0; u < kStagePer; ++u) jk[u] = tk[u] >= 0 ? idx_all[tk[u]] : pad;
+      for (int m = 0; m < kStagePer; ++m) jk[m] = tk[m] >= 0 ? idx_all[tk[m]] : pad;
 #pragma unroll
-      for (int u = 0; u < kStagePer; ++u) {
-        const float4 p = posr[jk[u]];
-        const int k = tid + u * kBT;
-        if (tk[u] >= 0) {
-          S.P[k] = make_float4(sub_nc(p.x, shx[u]), sub_nc(p.y, shy[u]), sub_nc(p.z, shz[u]), p.w);
-          S.J[k] = jk[u];
-          S.Sl[k] = -1;
+      for (int m = 0; m < kStagePer; ++m) {
+        const float4 p = posr[jk[m]];
+        const int k = tid + m * kBT;
+        if (tk[m] >= 0) {
+          S.P[k] = make_float4(sub_nc(p.x, shx[m]), sub_nc(p.y, shy[m]), sub_nc(p.z, shz[m]),
+                               __int_as_float(-1));
+          S.gid[k] = __float_as_uint(p.w);
+          S.J[k] = jk[m];
         }
       }
     }
@@ -304,12 +314,10 @@ __global__ __launch_bounds__(kBT) void k_force_brick(
       const int a = 1 + hcl % sx, bb = 1 + (hcl / sx) % sy, cc = 1 + hcl / (sx * sy);
       const int c = (cc * HY + bb) * HX + a;
       const int h0 = S.hstart[c], nh = S.hstart[c + 1] - h0;
-      if (nh == 0) continue;
       const int k0 = S.cs[c] + S.nwall[c];
-      const int gc = co + ((z0 + cc - 1) * ny + (y0 + bb - 1)) * nx + (x0 + a - 1);
-      const int s0 = cstart[gc];
+      const int s0 = S.fslot[c];
       for (int e = 0; e < nh; ++e) {
-        S.Sl[k0 + e] = (int16_t)(h0 + e);
+        S.P[k0 + e].w = __int_as_float(h0 + e);
         S.hl[h0 + e] = (int16_t)(k0 + e);
         S.hc[h0 + e] = (int16_t)c;
         S.hs[h0 + e] = s0 + e;
@@ -320,32 +328,44 @@ __global__ __launch_bounds__(kBT) void k_force_brick(
     }
     __syncthreads();
 
+    // this thread's home particles: their state is fetched now and used
+    // after the walk
+    int hi_[kHomePer];
+    float4 vo[kHomePer], fo[kHomePer], vti[kHomePer], po[kHomePer];
+#pragma unroll
+    for (int m = 0; m < kHomePer; ++m) {
+      const int h = tid + m * kBT;
+      hi_[m] = h < H ? S.J[S.hl[h]] : 0;
+    }
+#pragma unroll
+    for (int m = 0; m < kHomePer; ++m) {
+      po[m] = posr[hi_[m]];
+      vo[m] = velr[hi_[m]];
+      vti[m] = vtr[hi_[m]];
+      fo[m] = INIT ? make_float4(0.f, 0.f, 0.f, 0.f) : frcr[hi_[m]];
+    }
+
     // candidate walk and pair rounds, per wavefront
     {
-      uint32_t *const q = S.queue[wave];
+      uint32_t *const q = S.u.queue[wave];
       uint32_t qh = 0, qt = 0;   // ring head and tail (wavefront-uniform)
       // one round: lane l evaluates queued pair qh + l (if any)
       auto round = [&](int count) {
-        float4 pi = make_float4(0.f, 0.f, 0.f, 0.f), pj = pi, vi = pi, vj = pi;
-        int ki = 0, kj = 0;
         const bool act = lane < count;
-        if (act) {
-          const uint32_t e = q[(qh + lane) & (kQ - 1)];
-          ki = (int)(e >> 16);
-          kj = (int)(e & 0xFFFFu);
-        }
+        const uint32_t e = q[(qh + (uint32_t)lane) & (kQ - 1)];
+        const int ki = act ? (int)(e >> 16) : 0, kj = act ? (int)(e & 0xFFFFu) : 0;
+        const float4 pi = S.P[ki], pj = S.P[kj];
         const int Ji = S.J[ki], Jj = S.J[kj];
-        const int si = S.Sl[ki], sj = S.Sl[kj];
-        pi = S.P[ki];
-        pj = S.P[kj];
-        vi = vtr[act ? Ji : pad];
-        vj = vtr[act ? Jj : pad];
+        const uint32_t gi = S.gid[ki], gj = S.gid[kj];
+        const float4 vi = vtr[act ? Ji : pad];
+        const float4 vj = vtr[act ? Jj : pad];
         if (act) {
           float fx, fy, fz, mag;
           pair_force<SPH>(P, pi.x - pj.x, pi.y - pj.y, pi.z - pj.z, vi, vj, (int64_t)Jj >= NF,
-                          __float_as_uint(pi.w), __float_as_uint(pj.w), klo, khi, fx, fy, fz, mag);
+                          gi, gj, klo, khi, fx, fy, fz, mag);
           bad |= !(fabsf(mag) < 1.0e9f);
           const long long cx = to_fixed(fx), cy = to_fixed(fy), cz = to_fixed(fz);
+          const int si = __float_as_int(pi.w), sj = __float_as_int(pj.w);
           atomicAdd(&S.acc[3 * si], (unsigned long long)cx);
           atomicAdd(&S.acc[3 * si + 1], (unsigned long long)cy);
           atomicAdd(&S.acc[3 * si + 2], (unsigned long long)cz);
@@ -370,7 +390,8 @@ __global__ __launch_bounds__(kBT) void k_force_brick(
         // rows dy = -1, 0, 1 of plane hcz + dz: cells ha - 1 .. ha + 1
         int rb = ((hcz + dz) * HY + hb - 1) * HX + ha - 1;
         int row = live ? 0 : 3;
-        int t = S.cs[rb], tend = live ? S.cs[rb + 3] : 0;
+        int t = live ? S.cs[rb] : 0, tend = live ? S.cs[rb + 3] : 0;
+        const uint32_t key = (uint32_t)ki << 16;
         for (;;) {
           // advance lanes whose row is exhausted (skipping empty rows)
           bool need = row < 3 && t >= tend;
@@ -378,38 +399,37 @@ __global__ __launch_bounds__(kBT) void k_force_brick(
             if (need) {
               ++row;
               rb += HX;
-              if (row < 3) {
-                t = S.cs[rb];
-                tend = S.cs[rb + 3];
-              }
+              const bool more = row < 3;
+              t = more ? S.cs[rb] : 0;
+              tend = more ? S.cs[rb + 3] : 0;
             }
             need = row < 3 && t >= tend;
           }
-          if (!wave_any(row < 3)) break;
-          const bool on = row < 3;
-          float4 cq[kPassB];
+          if (!wave_any(t < tend)) break;
+          // kPass candidates t .. t + kPass - 1 (the spare entries make the
+          // reads past a run's end safe; those candidates are masked)
+          float4 cq[kPass];
 #pragma unroll
-          for (int u = 0; u < kPassB; ++u) {
-            const int c = t + u;
-            cq[u] = S.P[(on && c < tend) ? c : ki];
-          }
+          for (int v = 0; v < kPass; ++v) cq[v] = S.P[t + v];
 #pragma unroll
-          for (int u = 0; u < kPassB; ++u) {
-            const int c = t + u;
-            const float r2 = pair_r2(sub_nc(a.x, cq[u].x), sub_nc(a.y, cq[u].y), sub_nc(a.z, cq[u].z));
-            // r2 > 0: a coincident particle exerts no force (nor does i on itself)
-            bool keep = on && c < tend && r2 < P.rc2 && r2 > 0.0f && c != ki;
-            if (keep) keep = S.Sl[c] < 0 || c > ki;
+          for (int v = 0; v < kPass; ++v) {
+            const float r2 = pair_r2(sub_nc(a.x, cq[v].x), sub_nc(a.y, cq[v].y),
+                                     sub_nc(a.z, cq[v].z));
+            // r2 > 0 drops i itself (and a coincident particle, which exerts
+            // no force); a home partner is kept from the lower index only
+            const bool keep = (t + v < tend) & (r2 < P.rc2) & (r2 > 0.0f) &
+                              ((__float_as_int(cq[v].w) < 0) | (t + v > ki));
             const unsigned long long m = __ballot(keep);
-            if (keep) {
-              const uint32_t off = (uint32_t)__builtin_amdgcn_mbcnt_hi(
-                  (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-              q[(qt + off) & (kQ - 1)] = ((uint32_t)ki << 16) | (uint32_t)c;
-            }
+            const uint32_t off = (uint32_t)__builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            const uint32_t slot = keep ? ((qt + off) & (kQ - 1)) : (uint32_t)(kQ + lane);
+            q[slot] = key | (uint32_t)(t + v);
             qt += (uint32_t)__popcll(m);
+            // at most 63 pending + 2 x 64 appended < kQ between drains
+            if (v & 1)
+              while (qt - qh >= 64u) round(64);
           }
-          t += kPassB;
-          while (qt - qh >= 64u) round(64);
+          t += kPass;
         }
       }
       while (qt != qh) round((int)min(64u, qt - qh));
@@ -417,9 +437,10 @@ __global__ __launch_bounds__(kBT) void k_force_brick(
     __syncthreads();
 
     // the sums: forces, velocity update, outputs in cell-sorted slot order
-    for (int h = tid; h < H; h += kBT) {
-      const int ks = S.hl[h];
-      const int i = S.J[ks];
+#pragma unroll
+    for (int m = 0; m < kHomePer; ++m) {
+      const int h = tid + m * kBT;
+      if (h >= H) continue;
       const int s = S.hs[h];
       double f3[3];
 #pragma unroll
@@ -428,22 +449,19 @@ __global__ __launch_bounds__(kBT) void k_force_brick(
         f3[c] = (double)v * 2.3283064365386963e-10 + (double)P.g[c];
       }
       const float fx = (float)f3[0], fy = (float)f3[1], fz = (float)f3[2];
-      const float4 vo = vel4[i];
-      const float4 vti = vt4[i];
       float4 vn;
       if (INIT) {
-        vn = make_float4(vo.x, vo.y, vo.z, __int_as_float(0));
+        vn = make_float4(vo[m].x, vo[m].y, vo[m].z, __int_as_float(0));
       } else {
-        const int event = __float_as_int(vti.w);
+        const int event = __float_as_int(vti[m].w);
         if (event) {
-          vn = make_float4(vti.x, vti.y, vti.z, __int_as_float(event));
+          vn = make_float4(vti[m].x, vti[m].y, vti[m].z, __int_as_float(event));
         } else {
-          const float4 fo = frc4[i];
-          vn = make_float4(vo.x + P.hdt * (fo.x + fx), vo.y + P.hdt * (fo.y + fy),
-                           vo.z + P.hdt * (fo.z + fz), __int_as_float(0));
+          vn = make_float4(vo[m].x + P.hdt * (fo[m].x + fx), vo[m].y + P.hdt * (fo[m].y + fy),
+                           vo[m].z + P.hdt * (fo[m].z + fz), __int_as_float(0));
         }
       }
-      pos_out[s] = pos4[i];
+      pos_out[s] = po[m];
       vel_out[s] = vn;
       frc_out[s] = make_float4(fx, fy, fz, 0.f);
     }

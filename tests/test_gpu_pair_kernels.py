@@ -97,7 +97,7 @@ def test_brick_sums_are_order_free(dpd, kernel):
         assert np.array_equal(va, c.state()[k].cpu().numpy()), k
     for sim in (a, b, c):
         sim.close()
-    other = workloads.slab_system(seed_fluid=5, seed_wall=6,
+    other = workloads.slab_system(seed_fluid=5, seed_wall=6, grid_dtype=np.float32,
                                   params=workloads.default_params(seed=5))
     s2 = _small_curved_box()
     alone = dpd.Simulation(s2)

@@ -335,18 +335,22 @@ int dpd_window_forward(dpd_ctx *ctx, int32_t steps, int32_t ckpt, int32_t axis,
 int dpd_backward(dpd_ctx *ctx, const double *dL_dprofile, double *grads,
                  double *dL_dphi);
 
-/* The decisions of the recorded window, for a frozen-decision replay (the
- * window as a smooth function of the parameters, Sec. II.C's events held
- * fixed): the window's steps are recomputed from its checkpoints exactly as
- * dpd_backward recomputes them, and after step t (0 <= t < steps) the
- * positions of every particle (the FP32 positions on which that step's
- * cell, pair and bin decisions were taken) and the step's event codes are
- * written in gid order to pos_log[t][n][3] (device, steps x n x 3 float32)
- * and ev_log[t][n] (device, steps x n int32); either may be NULL.  Walls
- * repeat their positions and have event 0.  The context's state, k and
- * counters are unchanged.  Synchronises.  DPD_E_STATE without a recorded
- * window or after dpd_set_params / dpd_set_phi / dpd_set_state. */
-int dpd_window_trace(dpd_ctx *ctx, float *pos_log, int32_t *ev_log);
+/* The trajectory and decisions of the recorded window, for references that
+ * hold its discrete decisions fixed (the window as a smooth function of
+ * the parameters, Sec. II.C's events frozen) and linearise it around the
+ * GPU's own trajectory: the window's steps are recomputed from its
+ * checkpoints exactly as dpd_backward recomputes them.  State s of every
+ * particle in gid order goes to pos_log, vel_log and frc_log (device,
+ * (steps + 1) x n x 3 float32 each): s = 0 is the window's start with its
+ * refreshed force f0, s = t + 1 the state after step t, whose positions are
+ * those on which step t's cell, pair and bin decisions were taken.  The
+ * event codes of step t go to ev_log[t][n] (device, steps x n int32).  Any
+ * pointer may be NULL.  Walls: their positions and velocities, zero forces
+ * and events.  The context's state, k and counters are unchanged.
+ * Synchronises.  DPD_E_STATE without a recorded window or after
+ * dpd_set_params / dpd_set_phi / dpd_set_state. */
+int dpd_window_trace(dpd_ctx *ctx, float *pos_log, float *vel_log, float *frc_log,
+                     int32_t *ev_log);
 
 /* Wait for the context stream and return any latched device error. */
 int dpd_sync(dpd_ctx *ctx);

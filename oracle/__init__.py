@@ -103,6 +103,11 @@ def lib():
         L.orc_window.argtypes = [P, P, C.c_int64, P, P, P, P, C.c_uint64, C.c_int, C.c_int,
                                  C.c_int, C.c_int, P, P, P, P, P, P, P]
         L.orc_window.restype = C.c_int
+        L.orc_window_start_force.argtypes = [P, P, C.c_int64, P, P, P, P, C.c_uint64, P]
+        L.orc_window_start_force.restype = C.c_int
+        L.orc_window_step.argtypes = [P, P, C.c_int64, P, P, P, P, P, C.c_uint64, C.c_int,
+                                      C.c_int, P, P, P, P, P]
+        L.orc_window_step.restype = C.c_int
         _lib = L
     return _lib
 
@@ -323,6 +328,39 @@ class Oracle:
             raise MemoryError("oracle window allocation failed")
         prof = sums / np.maximum(counts, 1.0)
         return dict(profile=prof, sums=sums, counts=counts, logs=logs, r=r_out, v=v_out)
+
+    def window_start_force(self, r, v, k0):
+        """f0 = F(r, v; k0) + g as the window starts: pairs decided at fl32(r),
+        w = 1 - r/rc unclamped (rows in this oracle's particle order)."""
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        f = np.zeros((self.n, 3), np.float64)
+        rc = lib().orc_window_start_force(C.byref(self.geom), C.byref(self.cparams), self.n,
+                                          _p(r), _p(v), _p(self.type), _p(self.gid), int(k0),
+                                          _p(f))
+        if rc != 0:
+            raise MemoryError("oracle allocation failed")
+        return f
+
+    def window_step(self, r, v, f, k, ev_t, xs_t, bin_t, axis=2, nbins=40):
+        """One window step with every decision read from the step's logs
+        (event codes ev_t, decision positions xs_t, bins bin_t), from the
+        state (r, v, f); the new force at index k.  Returns (r, v, f, sums,
+        counts) of the step (new arrays)."""
+        r = np.array(r, dtype=np.float64, order="C")
+        v = np.array(v, dtype=np.float64, order="C")
+        f = np.array(f, dtype=np.float64, order="C")
+        sums = np.zeros(nbins)
+        counts = np.zeros(nbins)
+        rc = lib().orc_window_step(C.byref(self.geom), C.byref(self.cparams), self.n, _p(r),
+                                   _p(v), _p(f), _p(self.type), _p(self.gid), int(k), int(axis),
+                                   int(nbins), _p(np.ascontiguousarray(ev_t, np.int32)),
+                                   _p(np.ascontiguousarray(xs_t, np.float32)),
+                                   _p(np.ascontiguousarray(bin_t, np.int32)), _p(sums),
+                                   _p(counts))
+        if rc != 0:
+            raise MemoryError("oracle window step allocation failed")
+        return r, v, f, sums, counts
 
     def cells(self, xs=None):
         xs = self.xs if xs is None else np.ascontiguousarray(xs, dtype=np.float32)

@@ -895,126 +895,210 @@ static int bin_of32(float x, float scale, int nbins)
     return b;
 }
 
+/* Scratch arrays of one window step (n x 3 doubles, n x 3 floats, n ints). */
+typedef struct {
+    double *fn, *vt, *vold;
+    float *xs;
+    int32_t *code;
+} win_scratch;
+
+static int win_scratch_alloc(win_scratch *S, int64_t n)
+{
+    const size_t n3 = 3 * (size_t)(n > 0 ? n : 1);
+    S->fn = malloc(sizeof(double) * n3);
+    S->vt = malloc(sizeof(double) * n3);
+    S->vold = malloc(sizeof(double) * n3);
+    S->xs = malloc(sizeof(float) * n3);
+    S->code = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    return (S->fn && S->vt && S->vold && S->xs && S->code) ? 0 : -1;
+}
+
+static void win_scratch_free(win_scratch *S)
+{
+    free(S->fn); free(S->vt); free(S->vold); free(S->xs); free(S->code);
+}
+
+/* Step t of the window from the state (r, v, f), updated in place: drift
+ * and prediction, bounce-back (Eq. 16-17) with the decision taken
+ * (record = 1) or read from ev_t (record = 0), the forces at force index k
+ * on the pair set decided at the FP32 positions (taken, or read from
+ * xs_t), the velocity update, and the step's bin sums added to sums and
+ * counts (bins taken, or read from bin_t).  record = 1 writes the step's
+ * decisions to ev_t, xs_t and bin_t. */
+static int window_step(const orc_geom *G, const orc_params *P, int64_t n, double *r,
+                       double *v, double *f, const int32_t *type, const uint32_t *gid,
+                       uint64_t k, int axis, int nbins, int record, int32_t *ev_t,
+                       float *xs_t, int32_t *bin_t, double *sums, double *counts,
+                       win_scratch *S)
+{
+    const double dt = P->dt;
+    const double delta = 0x1p-20;
+    const float scale = (float)((double)nbins / G->L[axis]);
+    double *fn = S->fn, *vt = S->vt, *vold = S->vold;
+    float *xs = S->xs;
+    int32_t *code = S->code;
+    for (int64_t i = 0; i < n; ++i) {
+        double *ri = r + 3 * i, *vi = v + 3 * i, *fi = f + 3 * i;
+        for (int a = 0; a < 3; ++a) vold[3 * i + a] = vi[a];
+        code[i] = 0;
+        if (type[i] != 0) {
+            for (int a = 0; a < 3; ++a) {
+                vt[3 * i + a] = 0.0;
+                xs[3 * i + a] = (float)ri[a];
+            }
+            continue;
+        }
+        /* drift and prediction (Groot-Warren) */
+        float x32[3], v32[3], f32[3], y32[3];
+        int sh[3];
+        for (int a = 0; a < 3; ++a) {
+            x32[a] = (float)ri[a];
+            v32[a] = (float)vi[a];
+            f32[a] = (float)fi[a];
+        }
+        drift32(G, P, x32, v32, f32, y32, sh);
+        double rs[3], rt[3];
+        for (int a = 0; a < 3; ++a) {
+            rt[a] = ri[a];
+            rs[a] = ri[a] + dt * vi[a] + 0.5 * dt * dt * fi[a] + sh[a] * G->L[a];
+            vt[3 * i + a] = vi[a] + P->lambda * dt * fi[a];
+        }
+        int c = record ? (phi_negative(G, y32) ? 1 : 0) : ev_t[i];
+        float d32[3] = {y32[0], y32[1], y32[2]};
+        if (c == 0) {
+            for (int a = 0; a < 3; ++a) ri[a] = rs[a];
+        } else {
+            /* bounce-back, Eq. 16-17 */
+            double a1 = -orc_phi64(G, rs, NULL), a0 = orc_phi64(G, rt, NULL);
+            if (a1 < 0.0) a1 = 0.0;
+            if (a1 > 1.0 - delta) a1 = 1.0 - delta;
+            if (a0 < 0.0) a0 = 0.0;
+            if (a0 > 1.0 - delta) a0 = 1.0 - delta;
+            double c1 = atanh(a1), c0 = atanh(a0);
+            double sfrac = c1 > 0.0 ? c1 / (c0 + c1) : 0.0;
+            double rbb[3];
+            for (int a = 0; a < 3; ++a) {
+                rbb[a] = rs[a] - 2.0 * sfrac * dt * vi[a];
+                d32[a] = (float)rbb[a];
+                rbb[a] += wrap32(&d32[a], G->L32[a]) * G->L[a];
+            }
+            if (record) c = phi_negative(G, d32) ? 2 : 1;
+            for (int a = 0; a < 3; ++a) {
+                ri[a] = c == 2 ? rt[a] : rbb[a];
+                if (c == 2) d32[a] = (float)rt[a];
+                vt[3 * i + a] = -vi[a];
+                vi[a] = -vi[a];
+            }
+        }
+        code[i] = c;
+        for (int a = 0; a < 3; ++a) xs[3 * i + a] = d32[a];
+    }
+    if (record) {
+        for (int64_t i = 0; i < n; ++i) {
+            ev_t[i] = code[i];
+            for (int a = 0; a < 3; ++a) xs_t[3 * i + a] = xs[3 * i + a];
+        }
+    } else {
+        /* decisions from the log; positions in the logged image */
+        for (int64_t q = 0; q < 3 * n; ++q) {
+            const int a = (int)(q % 3);
+            xs[q] = xs_t[q];
+            r[q] -= G->L[a] * nearbyint((r[q] - (double)xs_t[q]) / G->L[a]);
+        }
+    }
+    if (forces_impl(G, P, n, r, vt, xs, type, gid, k, 2, 0, 1, fn) != 0) return -1;
+    for (int64_t i = 0; i < n; ++i) {
+        if (type[i] != 0) continue;
+        for (int a = 0; a < 3; ++a) {
+            if (code[i] == 0)
+                v[3 * i + a] = vold[3 * i + a] + 0.5 * dt * (f[3 * i + a] + fn[3 * i + a]);
+            f[3 * i + a] = fn[3 * i + a];
+        }
+        int b;
+        if (record) {
+            b = bin_of32(xs[3 * i + axis], scale, nbins);
+            bin_t[i] = b;
+        } else {
+            b = bin_t[i];
+        }
+        sums[b] += v[3 * i];
+        counts[b] += 1.0;
+    }
+    return 0;
+}
+
 int orc_window(const orc_geom *G, const orc_params *P, int64_t n,
                const double *r0, const double *v0, const int32_t *type,
                const uint32_t *gid, uint64_t k0, int T, int axis, int nbins,
                int record, int32_t *ev, float *xs_log, int32_t *bin,
                double *sums, double *counts, double *r_out, double *v_out)
 {
-    const double dt = P->dt;
-    const double delta = 0x1p-20;
-    const float scale = (float)((double)nbins / G->L[axis]);
     const size_t n3 = 3 * (size_t)(n > 0 ? n : 1);
     double *r = malloc(sizeof(double) * n3), *v = malloc(sizeof(double) * n3);
-    double *f = malloc(sizeof(double) * n3), *fn = malloc(sizeof(double) * n3);
-    double *vt = malloc(sizeof(double) * n3), *vold = malloc(sizeof(double) * n3);
-    float *xs = malloc(sizeof(float) * n3);
-    int32_t *code = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    double *f = malloc(sizeof(double) * n3);
+    win_scratch S;
     int rc = -1;
-    if (!r || !v || !f || !fn || !vt || !vold || !xs || !code) goto out;
+    int ok = win_scratch_alloc(&S, n) == 0;
+    if (!r || !v || !f || !ok) goto out;
     for (int b = 0; b < nbins; ++b) sums[b] = counts[b] = 0.0;
     for (int64_t q = 0; q < 3 * n; ++q) {
         r[q] = r0[q];
         v[q] = type[q / 3] == 0 ? v0[q] : 0.0;
-        xs[q] = (float)r0[q];
+        S.xs[q] = (float)r0[q];
     }
-    if (forces_impl(G, P, n, r, v, xs, type, gid, k0, 2, 0, 1, f) != 0) goto out;
-
+    if (forces_impl(G, P, n, r, v, S.xs, type, gid, k0, 2, 0, 1, f) != 0) goto out;
     for (int t = 0; t < T; ++t) {
-        float *xl = xs_log + 3 * (size_t)t * (size_t)n;
-        for (int64_t i = 0; i < n; ++i) {
-            double *ri = r + 3 * i, *vi = v + 3 * i, *fi = f + 3 * i;
-            for (int a = 0; a < 3; ++a) vold[3 * i + a] = vi[a];
-            code[i] = 0;
-            if (type[i] != 0) {
-                for (int a = 0; a < 3; ++a) {
-                    vt[3 * i + a] = 0.0;
-                    xs[3 * i + a] = (float)ri[a];
-                }
-                continue;
-            }
-            /* drift and prediction (Groot-Warren) */
-            float x32[3], v32[3], f32[3], y32[3];
-            int sh[3];
-            for (int a = 0; a < 3; ++a) {
-                x32[a] = (float)ri[a];
-                v32[a] = (float)vi[a];
-                f32[a] = (float)fi[a];
-            }
-            drift32(G, P, x32, v32, f32, y32, sh);
-            double rs[3], rt[3];
-            for (int a = 0; a < 3; ++a) {
-                rt[a] = ri[a];
-                rs[a] = ri[a] + dt * vi[a] + 0.5 * dt * dt * fi[a] + sh[a] * G->L[a];
-                vt[3 * i + a] = vi[a] + P->lambda * dt * fi[a];
-            }
-            int c = record ? (phi_negative(G, y32) ? 1 : 0) : ev[(size_t)t * n + i];
-            float d32[3] = {y32[0], y32[1], y32[2]};
-            if (c == 0) {
-                for (int a = 0; a < 3; ++a) ri[a] = rs[a];
-            } else {
-                /* bounce-back, Eq. 16-17 */
-                double a1 = -orc_phi64(G, rs, NULL), a0 = orc_phi64(G, rt, NULL);
-                if (a1 < 0.0) a1 = 0.0;
-                if (a1 > 1.0 - delta) a1 = 1.0 - delta;
-                if (a0 < 0.0) a0 = 0.0;
-                if (a0 > 1.0 - delta) a0 = 1.0 - delta;
-                double c1 = atanh(a1), c0 = atanh(a0);
-                double sfrac = c1 > 0.0 ? c1 / (c0 + c1) : 0.0;
-                double rbb[3];
-                for (int a = 0; a < 3; ++a) {
-                    rbb[a] = rs[a] - 2.0 * sfrac * dt * vi[a];
-                    d32[a] = (float)rbb[a];
-                    rbb[a] += wrap32(&d32[a], G->L32[a]) * G->L[a];
-                }
-                if (record) c = phi_negative(G, d32) ? 2 : 1;
-                for (int a = 0; a < 3; ++a) {
-                    ri[a] = c == 2 ? rt[a] : rbb[a];
-                    if (c == 2) d32[a] = (float)rt[a];
-                    vt[3 * i + a] = -vi[a];
-                    vi[a] = -vi[a];
-                }
-            }
-            code[i] = c;
-            for (int a = 0; a < 3; ++a) xs[3 * i + a] = d32[a];
-        }
-        if (record) {
-            for (int64_t i = 0; i < n; ++i) {
-                ev[(size_t)t * n + i] = code[i];
-                for (int a = 0; a < 3; ++a) xl[3 * i + a] = xs[3 * i + a];
-            }
-        } else {
-            /* decisions from the log; positions in the logged image */
-            for (int64_t q = 0; q < 3 * n; ++q) {
-                const int a = (int)(q % 3);
-                xs[q] = xl[q];
-                r[q] -= G->L[a] * nearbyint((r[q] - (double)xl[q]) / G->L[a]);
-            }
-        }
-        if (forces_impl(G, P, n, r, vt, xs, type, gid, k0 + (uint64_t)t + 1, 2, 0, 1, fn) != 0)
+        if (window_step(G, P, n, r, v, f, type, gid, k0 + (uint64_t)t + 1, axis, nbins, record,
+                        ev + (size_t)t * n, xs_log + 3 * (size_t)t * (size_t)n,
+                        bin + (size_t)t * n, sums, counts, &S) != 0)
             goto out;
-        for (int64_t i = 0; i < n; ++i) {
-            if (type[i] != 0) continue;
-            for (int a = 0; a < 3; ++a) {
-                if (code[i] == 0)
-                    v[3 * i + a] = vold[3 * i + a] + 0.5 * dt * (f[3 * i + a] + fn[3 * i + a]);
-                f[3 * i + a] = fn[3 * i + a];
-            }
-            int b;
-            if (record) {
-                b = bin_of32(xs[3 * i + axis], scale, nbins);
-                bin[(size_t)t * n + i] = b;
-            } else {
-                b = bin[(size_t)t * n + i];
-            }
-            sums[b] += v[3 * i];
-            counts[b] += 1.0;
-        }
     }
     if (r_out) memcpy(r_out, r, sizeof(double) * 3 * (size_t)n);
     if (v_out) memcpy(v_out, v, sizeof(double) * 3 * (size_t)n);
     rc = 0;
 out:
-    free(r); free(v); free(f); free(fn); free(vt); free(vold); free(xs); free(code);
+    free(r); free(v); free(f);
+    win_scratch_free(&S);
+    return rc;
+}
+
+/* The window's starting force f0 = F(r0, v0; k0) + g (pairs decided at
+ * fl32(r0), w = 1 - r/rc without clamping), as orc_window computes it. */
+int orc_window_start_force(const orc_geom *G, const orc_params *P, int64_t n,
+                           const double *r0, const double *v0, const int32_t *type,
+                           const uint32_t *gid, uint64_t k0, double *f)
+{
+    const size_t n3 = 3 * (size_t)(n > 0 ? n : 1);
+    float *xs = malloc(sizeof(float) * n3);
+    double *v = malloc(sizeof(double) * n3);
+    if (!xs || !v) { free(xs); free(v); return -1; }
+    for (int64_t q = 0; q < 3 * n; ++q) {
+        xs[q] = (float)r0[q];
+        v[q] = type[q / 3] == 0 ? v0[q] : 0.0;
+    }
+    int rc = forces_impl(G, P, n, r0, v, xs, type, gid, k0, 2, 0, 1, f);
+    free(xs); free(v);
+    return rc;
+}
+
+/* One step of the window with every decision read from the logs of that
+ * step (ev_t, xs_t, bin_t), from the state (r, v, f) updated in place, the
+ * new force at force index k; the step's bin sums go to sums and counts
+ * (nbins each, overwritten).  The replayed window is this step iterated
+ * from f0 of orc_window_start_force with k = k0 + t + 1, so that the window
+ * can be linearised step by step around any trajectory. */
+int orc_window_step(const orc_geom *G, const orc_params *P, int64_t n, double *r, double *v,
+                    double *f, const int32_t *type, const uint32_t *gid, uint64_t k,
+                    int axis, int nbins, const int32_t *ev_t, const float *xs_t,
+                    const int32_t *bin_t, double *sums, double *counts)
+{
+    win_scratch S;
+    int rc = -1;
+    if (win_scratch_alloc(&S, n) == 0) {
+        for (int b = 0; b < nbins; ++b) sums[b] = counts[b] = 0.0;
+        rc = window_step(G, P, n, r, v, f, type, gid, k, axis, nbins, 0, (int32_t *)ev_t,
+                         (float *)xs_t, (int32_t *)bin_t, sums, counts, &S);
+    }
+    win_scratch_free(&S);
     return rc;
 }

@@ -132,7 +132,7 @@ def load_library(path: str = LIB_PATH):
                                        C.POINTER(C.c_double), C.c_double, C.c_double, C.c_int32,
                                        C.POINTER(C.c_double), P]
     L.dpd_phi_relax_static.restype = C.c_int
-    L.dpd_window_trace.argtypes = [P, P, P]
+    L.dpd_window_trace.argtypes = [P, P, P, P, P]
     L.dpd_window_trace.restype = C.c_int
     L.dpd_valu_probe.argtypes = [C.c_int32, C.c_int64, C.c_int32, P, P]
     L.dpd_valu_probe.restype = C.c_int
@@ -484,10 +484,12 @@ def dpd_phi_relax_static(phi, h, eps, dtau, iters, residual=True, stream=None):
     return res.value if residual else None
 
 
-def dpd_window_trace(ctx, pos_log=None, ev_log=None):
-    """Positions (steps, n, 3 float32) and event codes (steps, n int32) after
-    every step of the recorded window, in gid order (device tensors)."""
-    _check(load_library().dpd_window_trace(ctx, _ptr(pos_log), _ptr(ev_log)), ctx)
+def dpd_window_trace(ctx, pos_log=None, vel_log=None, frc_log=None, ev_log=None):
+    """States (steps + 1, n, 3 float32: the window's start, then after each
+    step) and event codes (steps, n int32) of the recorded window, in gid
+    order (device tensors, any may be None)."""
+    _check(load_library().dpd_window_trace(ctx, _ptr(pos_log), _ptr(vel_log), _ptr(frc_log),
+                                           _ptr(ev_log)), ctx)
 
 
 def dpd_valu_probe(kind, waves, iters, out, stream=None):

@@ -1278,11 +1278,13 @@ int backward_impl(dpd_ctx *c, const double *dldp, double *grads, double *dphi) {
 }
 
 // The recorded window's trajectory again, segment by segment from its
-// checkpoints as the backward sweep recomputes it: after step t (0-based),
-// positions and event codes of every particle in gid order into
-// pos_log + 3 n t and ev_log + n t (walls repeat their positions, events 0).
-// The context's state, k and counters are left as they were.
-int trace_impl(dpd_ctx *c, float *pos_log, int32_t *ev_log) {
+// checkpoints as the backward sweep recomputes it.  State s (0: the
+// window's start with its refreshed force, t + 1: after step t) of every
+// particle in gid order into pos/vel/frc_log + 3 n s, the event codes of
+// step t into ev_log + n t (walls: their positions and velocities, zero
+// forces and events).  The context's state, k and counters are left as
+// they were.
+int trace_impl(dpd_ctx *c, float *pos_log, float *vel_log, float *frc_log, int32_t *ev_log) {
   Window &W = c->win;
   const int64_t NF = c->NF;
   const Replica &p = c->rep[0];
@@ -1295,23 +1297,31 @@ int trace_impl(dpd_ctx *c, float *pos_log, int32_t *ev_log) {
   HIP_TRY(c, hipMemcpyAsync(W.status_save, c->status, sizeof(Status), hipMemcpyDeviceToDevice, s));
   const bool timing = c->timing;
   c->timing = false;
+  // state `st` of the trajectory into the logs (events of step st - 1)
+  auto put = [&](int st) -> hipError_t {
+    float *pl = pos_log ? pos_log + (size_t)3 * p.n * st : nullptr;
+    float *vl = vel_log ? vel_log + (size_t)3 * p.n * st : nullptr;
+    float *fl = frc_log ? frc_log + (size_t)3 * p.n * st : nullptr;
+    int32_t *el = (ev_log && st > 0) ? ev_log + (size_t)p.n * (st - 1) : nullptr;
+    hipError_t e = dpd::launch_export(s, p.G, p.nf, c->pos[c->cur] + p.fo,
+                                      c->vel[c->cur] + p.fo, c->frc[c->cur] + p.fo, 0, pl, vl,
+                                      fl, el, nullptr);
+    if (e == hipSuccess)
+      e = dpd::launch_export(s, p.G, p.nw, c->pos[c->cur] + c->NF + p.wo,
+                             c->vt + c->NF + p.wo, nullptr, 1, pl, vl, fl, el, nullptr);
+    return e;
+  };
   for (int seg = 0; seg < W.nck && !rc; ++seg) {
     const int t0 = seg * W.ckpt, t1 = std::min(W.steps, t0 + W.ckpt);
     rc = load_state(c, W.ck + (size_t)seg * 3 * NF);
     if (rc) break;
     c->k = W.k0 + (uint64_t)t0;
     HIP_TRY(c, dpd::launch_set_u64(s, c->dk, c->k));
+    if (seg == 0) HIP_TRY(c, put(0));
     for (int t = t0; t < t1 && !rc; ++t) {
       rc = one_step(c);
       if (rc) break;
-      float *pl = pos_log ? pos_log + (size_t)3 * p.n * t : nullptr;
-      int32_t *el = ev_log ? ev_log + (size_t)p.n * t : nullptr;
-      HIP_TRY(c, dpd::launch_export(s, p.G, p.nf, c->pos[c->cur] + p.fo, c->vel[c->cur] + p.fo,
-                                    c->frc[c->cur] + p.fo, 0, pl, nullptr, nullptr, el,
-                                    nullptr));
-      HIP_TRY(c, dpd::launch_export(s, p.G, p.nw, c->pos[c->cur] + c->NF + p.wo,
-                                    c->vt + c->NF + p.wo, nullptr, 1, pl, nullptr, nullptr, el,
-                                    nullptr));
+      HIP_TRY(c, put(t + 1));
     }
   }
   c->timing = timing;
@@ -1755,12 +1765,13 @@ int dpd_backward(dpd_ctx *c, const double *dL_dprofile, double *grads, double *d
   return backward_impl(c, dL_dprofile, grads, dL_dphi);
 }
 
-int dpd_window_trace(dpd_ctx *c, float *pos_log, int32_t *ev_log) {
+int dpd_window_trace(dpd_ctx *c, float *pos_log, float *vel_log, float *frc_log,
+                     int32_t *ev_log) {
   if (!c) return DPD_E_INVAL;
   if (!c->win.valid) return fail(c, DPD_E_STATE, "trace needs a recorded window");
   if (c->win.gen != c->gen)
     return fail(c, DPD_E_STATE, "parameters, phi or state changed since the window was recorded");
-  return trace_impl(c, pos_log, ev_log);
+  return trace_impl(c, pos_log, vel_log, frc_log, ev_log);
 }
 
 int dpd_sync(dpd_ctx *c) {

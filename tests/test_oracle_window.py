@@ -160,3 +160,33 @@ def test_frozen_differences_converge_at_second_order(oracle_lib, what):
     e1, e2 = abs(d1 - d2), abs(d2 - d3)
     # O(h^2): successive differences shrink about fourfold (or sit at rounding)
     assert e2 < 1e-9 * abs(d3) + 1e-15 or 2.5 < e1 / e2 < 6.0, (d1, d2, d3)
+
+
+def test_window_is_its_step_iterated(oracle_lib):
+    """The replayed window equals its one-step map iterated from the
+    window's starting force (the form used to linearise it step by step
+    around a given trajectory): the same counts and final state bit for
+    bit, the same sums up to the order of their additions (the window adds
+    every term to one running sum, the steps are summed per step)."""
+    s = workloads.tiny_slab_system(seed=19)
+    s.vel = (s.vel * 3).astype(np.float32)
+    o = oracle_lib.Oracle(s)
+    T, nb = 9, 6
+    base = o.window(T, axis=2, nbins=nb)
+    logs = base["logs"]
+    assert (logs["ev"] != 0).sum() > 0
+    rep = o.window(T, axis=2, nbins=nb, logs=logs)
+    r, v = o.r.copy(), o.v.copy()
+    v[o.type != 0] = 0.0
+    f = o.window_start_force(r, v, o.k)
+    sums = np.zeros(nb)
+    counts = np.zeros(nb)
+    for t in range(T):
+        r, v, f, sm, cn = o.window_step(r, v, f, o.k + t + 1, logs["ev"][t], logs["xs"][t],
+                                        logs["bin"][t], axis=2, nbins=nb)
+        sums += sm
+        counts += cn
+    assert np.array_equal(counts, rep["counts"])
+    np.testing.assert_allclose(sums, rep["sums"], rtol=1e-13, atol=1e-13)
+    assert np.array_equal(r, rep["r"])
+    assert np.array_equal(v, rep["v"])

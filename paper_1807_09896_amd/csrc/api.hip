@@ -126,6 +126,7 @@ struct dpd_ctx {
   int32_t *start_all = nullptr; // start of each cell's merged run
   int32_t *fluid_off = nullptr; // start of each cell's fluid part in the merged run
   void *grid = nullptr;
+  void *quad = nullptr;         // the grids in the face layout (4 values a node)
   uint32_t *bits = nullptr;     // near-interface grid cubes, one bit each
   Status *status = nullptr;
   unsigned long long *dk = nullptr;  // force evaluation index on the device
@@ -521,7 +522,7 @@ int enqueue_step(dpd_ctx *c, hipStream_t s) {
   HIP_TRY(c, timed(c, s, K_INTEGRATE, [&] {
             return dpd::launch_integrate(s, c->ppt, c->boxes, c->itiles, c->n_itiles, c->pos[a],
                                          c->vel[a], c->frc[a], c->vt, c->cell_of, c->rank_of,
-                                         c->count, c->bits, c->use_mask, c->grid, c->grid_f64,
+                                         c->count, c->bits, c->use_mask, c->quad, c->grid_f64,
                                          c->status, c->NF, c->wcstart, c->reflect ? 1 : 0);
           }));
   if (c->moving) {
@@ -871,6 +872,7 @@ int create_impl(int32_t nbox, const dpd_box *boxes, const dpd_particles *parts,
   c->start_all = (int32_t *)dalloc(c, 4 * (ncell + 1 + dpd::kStartSlack));
   c->fluid_off = (int32_t *)dalloc(c, 4 * ncell);
   c->grid = dalloc(c, (size_t)NGRID * (size_t)grids[0].dtype);
+  c->quad = dalloc(c, 4 * (size_t)NGRID * (size_t)grids[0].dtype);
   c->bits = (uint32_t *)dalloc(c, 4 * (size_t)NWORDS);
   c->boxes = (Box *)dalloc(c, sizeof(Box) * (size_t)nbox);
   c->status = (Status *)dalloc(c, sizeof(Status));
@@ -881,7 +883,7 @@ int create_impl(int32_t nbox, const dpd_box *boxes, const dpd_particles *parts,
       return bail(fail(c, DPD_E_NOMEM, "device allocation failed"));
   if (!c->vt || !c->cell_of || !c->rank_of || !c->idx || !c->count || !c->cstart || !c->bsum ||
       !c->wcstart || !c->wcell || !c->idx_all || !c->start_all || !c->fluid_off ||
-      !c->grid ||
+      !c->grid || !c->quad ||
       !c->bits || !c->boxes || !c->status || !c->dk || !c->pair_counter)
     return bail(fail(c, DPD_E_NOMEM, "device allocation failed"));
 
@@ -983,6 +985,9 @@ int create_impl(int32_t nbox, const dpd_box *boxes, const dpd_particles *parts,
     const size_t es = (size_t)grids[0].dtype;
     const void *g = (const char *)c->grid + (size_t)p.go * es;
     chk(dpd::launch_cube_mask(c->stream, p.G, g, c->grid_f64, p.nwords, c->bits + p.bo), "mask");
+    chk(dpd::launch_build_quad(c->stream, p.G, g, c->grid_f64,
+                               (char *)c->quad + 4 * (size_t)p.go * es),
+        "phase-field layout");
     chk(dpd::launch_check_grid(c->stream, g, c->grid_f64, (int64_t)p.ng[0] * p.ng[1] * p.ng[2],
                                c->status),
         "check grid");
@@ -1182,7 +1187,7 @@ int backward_step(dpd_ctx *c, const float4 *x, uint64_t t, const float4 *A, floa
   HIP_TRY(c, hipMemcpyAsync(W.wpos, x, 16 * (size_t)NF, hipMemcpyDeviceToDevice, s));
   HIP_TRY(c, dpd::launch_integrate(s, c->ppt, c->boxes, c->itiles, c->n_itiles, W.wpos, x + NF,
                                    x + 2 * NF, c->vt, c->cell_of, c->rank_of, c->count, c->bits,
-                                   c->use_mask, c->grid, c->grid_f64, c->status, NF, c->wcstart,
+                                   c->use_mask, c->quad, c->grid_f64, c->status, NF, c->wcstart,
                                    0));
   int rc = scan_scatter_sort(c, s);
   if (rc) return rc;
@@ -1698,6 +1703,8 @@ int dpd_set_phi(dpd_ctx *c, int32_t r, const void *data, int32_t on_device) {
   void *g = (char *)c->grid + (size_t)p.go * es;
   HIP_TRY(c, hipMemcpyAsync(g, stage, es * (size_t)nodes, hipMemcpyDeviceToDevice, c->stream));
   HIP_TRY(c, dpd::launch_cube_mask(c->stream, p.G, g, c->grid_f64, p.nwords, c->bits + p.bo));
+  HIP_TRY(c, dpd::launch_build_quad(c->stream, p.G, g, c->grid_f64,
+                                    (char *)c->quad + 4 * (size_t)p.go * es));
   std::vector<uint32_t> hb((size_t)p.nwords);
   HIP_TRY(c, hipMemcpyAsync(hb.data(), c->bits + p.bo, 4 * (size_t)p.nwords,
                             hipMemcpyDeviceToHost, c->stream));

@@ -316,6 +316,70 @@ __device__ __forceinline__ T phi_at(const T *__restrict__ grid, const KGeom &G, 
   return phi_interp(grid, G, grid_locate<T>(G, x, y, z));
 }
 
+// The phase field laid out for the lookups of the step: node (i, j, k) holds
+// the four values of its x-y face, (phi(i, j, k), phi(i+1, j, k),
+// phi(i, j+1, k), phi(i+1, j+1, k)) with periodic neighbours, so that the 8
+// corners of a grid cube are two 16-byte (FP32) or 32-byte (FP64) loads.
+template <typename T> struct PhiQuad;
+template <> struct PhiQuad<float> {
+  using type = float4;
+};
+template <> struct PhiQuad<double> {
+  using type = double4;
+};
+
+template <typename T>
+__device__ __forceinline__ void quad_corners(const typename PhiQuad<T>::type *__restrict__ quad,
+                                             const KGeom &G, const GridLoc<T> &L,
+                                             typename PhiQuad<T>::type &q0,
+                                             typename PhiQuad<T>::type &q1) {
+  const size_t nx = (size_t)G.ng[0], nxy = nx * (size_t)G.ng[1];
+  const size_t yx = (size_t)L.i0[1] * nx + (size_t)L.i0[0];
+  q0 = quad[(size_t)L.i0[2] * nxy + yx];
+  q1 = quad[(size_t)L.i1[2] * nxy + yx];
+}
+
+// phi_interp from the face layout: the same lerps in the same order.
+template <typename T>
+__device__ __forceinline__ T phi_interp_quad(const typename PhiQuad<T>::type *__restrict__ quad,
+                                             const KGeom &G, const GridLoc<T> &L) {
+#pragma clang fp contract(off)
+  typename PhiQuad<T>::type q0, q1;
+  quad_corners<T>(quad, G, L, q0, q1);
+  const T e00 = lerp_nc(q0.x, q0.y, L.t[0]);
+  const T e01 = lerp_nc(q0.z, q0.w, L.t[0]);
+  const T e10 = lerp_nc(q1.x, q1.y, L.t[0]);
+  const T e11 = lerp_nc(q1.z, q1.w, L.t[0]);
+  const T y0 = lerp_nc(e00, e01, L.t[1]);
+  const T y1 = lerp_nc(e10, e11, L.t[1]);
+  return lerp_nc(y0, y1, L.t[2]);
+}
+
+template <typename T>
+__device__ __forceinline__ T phi_at_quad(const typename PhiQuad<T>::type *__restrict__ quad,
+                                         const KGeom &G, float x, float y, float z) {
+  return phi_interp_quad<T>(quad, G, grid_locate<T>(G, x, y, z));
+}
+
+// phi_grad from the face layout (corners c[z][y][x] as in phi_grad).
+template <typename T>
+__device__ __forceinline__ void phi_grad_quad(const typename PhiQuad<T>::type *__restrict__ quad,
+                                              const KGeom &G, const GridLoc<T> &L, T &gx, T &gy,
+                                              T &gz) {
+  typename PhiQuad<T>::type q0, q1;
+  quad_corners<T>(quad, G, L, q0, q1);
+  const T c000 = q0.x, c001 = q0.y, c010 = q0.z, c011 = q0.w;
+  const T c100 = q1.x, c101 = q1.y, c110 = q1.z, c111 = q1.w;
+  const T tx = L.t[0], ty = L.t[1], tz = L.t[2];
+  const T ux = (T)1 - tx, uy = (T)1 - ty, uz = (T)1 - tz;
+  gx = (uz * (uy * (c001 - c000) + ty * (c011 - c010)) +
+        tz * (uy * (c101 - c100) + ty * (c111 - c110))) * GridScale<T>::inv_h(G, 0);
+  gy = (uz * (ux * (c010 - c000) + tx * (c011 - c001)) +
+        tz * (ux * (c110 - c100) + tx * (c111 - c101))) * GridScale<T>::inv_h(G, 1);
+  gz = (uy * (ux * (c100 - c000) + tx * (c101 - c001)) +
+        ty * (ux * (c110 - c010) + tx * (c111 - c011))) * GridScale<T>::inv_h(G, 2);
+}
+
 // Minimum-image separation x_i - x_j of two coordinates in [0, L) of a
 // pair within the cutoff.  Across the periodic edge the coordinate near L is
 // shifted by L first, which is exact (it lies within a factor two of L), so

@@ -83,16 +83,22 @@ hipError_t launch_check_grid(hipStream_t s, const void *grid, int grid_f64, int6
 hipError_t launch_check_phi(hipStream_t s, const KGeom &G, const void *grid, int grid_f64,
                             int64_t n, const float4 *pos4, Status *st);
 
+// The face layout of one box's phase field (PhiQuad in device.h): 16 bytes
+// per node for a float32 grid, 32 for float64, into quad.
+hipError_t launch_build_quad(hipStream_t s, const KGeom &G, const void *grid, int grid_f64,
+                             void *quad);
+
 // Fused drift + predicted velocity + phi test + reflection + binning, over
-// tiles of up to ppt x 256 particles (ppt 1 or 2); grid is the base of the
-// concatenated phi grids, bits of the concatenated cube masks.  reflect = 1
+// tiles of up to ppt x 256 particles (ppt 1 or 2); quad is the base of the
+// concatenated phase fields in the face layout, bits of the concatenated
+// cube masks.  reflect = 1
 // (some box has moving walls or specular reflection) runs the instance with
 // those forms: boxes with moving walls look up the solid's velocity among the
 // walls (entries NF + w of pos4 and vt4, runs wcstart over the global cells).
 hipError_t launch_integrate(hipStream_t s, int ppt, const Box *boxes, const Tile *tiles,
                             int ntiles, float4 *pos4, const float4 *vel4, const float4 *frc4,
                             float4 *vt4, int32_t *cell_of, int32_t *rank_of, int32_t *count,
-                            const uint32_t *bits, int use_mask, const void *grid, int grid_f64,
+                            const uint32_t *bits, int use_mask, const void *quad, int grid_f64,
                             Status *st, int64_t NF, const int32_t *wcstart, int reflect);
 
 // Walls of a moving solid advanced by dt v (decision-form drift, zero force)

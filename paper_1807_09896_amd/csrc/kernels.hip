@@ -397,6 +397,30 @@ __global__ void k_cube_mask(const KGeom G, const T *__restrict__ grid, int64_t n
   bits[w] = word;
 }
 
+// The face layout of the phase field (PhiQuad): node (i, j, k) gets
+// (phi(i, j, k), phi(i+1, j, k), phi(i, j+1, k), phi(i+1, j+1, k)).
+template <typename T>
+__global__ void k_build_quad(const KGeom G, const T *__restrict__ grid, int64_t nodes,
+                             typename PhiQuad<T>::type *__restrict__ quad) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nodes) return;
+  const int nx = G.ng[0], ny = G.ng[1];
+  const int i = (int)(q % nx);
+  const int64_t r = q / nx;
+  const int j = (int)(r % ny);
+  const int64_t k = r / ny;
+  const int i1 = i + 1 == nx ? 0 : i + 1;
+  const int j1 = j + 1 == ny ? 0 : j + 1;
+  const T *row0 = grid + ((size_t)k * ny + j) * nx;
+  const T *row1 = grid + ((size_t)k * ny + j1) * nx;
+  typename PhiQuad<T>::type v;
+  v.x = row0[i];
+  v.y = row0[i1];
+  v.z = row1[i];
+  v.w = row1[i1];
+  quad[q] = v;
+}
+
 __device__ __forceinline__ bool cube_flagged(const uint32_t *__restrict__ bits, size_t q) {
   return (bits[q >> 5] >> (q & 31)) & 1u;
 }
@@ -475,7 +499,8 @@ template <typename T, bool REFLECT>
 __device__ __forceinline__ Moved integrate_one(const KGeom &G, const KParams &P, float4 x,
                                                float4 v, float4 f,
                                                const uint32_t *__restrict__ bits, int use_mask,
-                                               const T *__restrict__ grid, Status *st, int co,
+                                               const typename PhiQuad<T>::type *__restrict__ quad,
+                                               Status *st, int co,
                                                int64_t NF, const int32_t *__restrict__ wcstart,
                                                const float4 *__restrict__ pos4,
                                                const float4 *__restrict__ vt4) {
@@ -501,10 +526,10 @@ __device__ __forceinline__ Moved integrate_one(const KGeom &G, const KParams &P,
   int event = 0;
   const GridLoc<T> loc = grid_locate<T>(G, xs, ys, zs);
   if (!use_mask || cube_flagged(bits, cube_index(G, loc))) {
-    const T phis = phi_interp(grid, G, loc);
+    const T phis = phi_interp_quad<T>(quad, G, loc);
     if (phis < (T)0) {
       // Eq. 16-17: distances beyond and before the interface from atanh(phi)
-      const T phit = phi_at(grid, G, x.x, x.y, x.z);
+      const T phit = phi_at_quad<T>(quad, G, x.x, x.y, x.z);
       const T lim = (T)1 - (T)0x1p-20;
       const T a1 = fmin(fmax(-phis, (T)0), lim);
       const T a0 = fmin(fmax(phit, (T)0), lim);
@@ -519,7 +544,7 @@ __device__ __forceinline__ Moved integrate_one(const KGeom &G, const KParams &P,
       float ux = v.x - vw.x, uy = v.y - vw.y, uz = v.z - vw.z;
       if (REFLECT && (P.reflect & kReflectSpecular)) {
         T gx, gy, gz;
-        phi_grad(grid, G, loc, gx, gy, gz);
+        phi_grad_quad<T>(quad, G, loc, gx, gy, gz);
         const T gn = sqrt(gx * gx + gy * gy + gz * gz);
         if (gn > (T)0) {
           const T nx = gx / gn, ny = gy / gn, nz = gz / gn;
@@ -532,7 +557,7 @@ __device__ __forceinline__ Moved integrate_one(const KGeom &G, const KParams &P,
       float bx = wrap1(xs - k2 * ux, G.L[0]);
       float by = wrap1(ys - k2 * uy, G.L[1]);
       float bz = wrap1(zs - k2 * uz, G.L[2]);
-      if (phi_at(grid, G, bx, by, bz) < (T)0) {
+      if (phi_at_quad<T>(quad, G, bx, by, bz) < (T)0) {
         bx = x.x;
         by = x.y;
         bz = x.z;
@@ -590,14 +615,15 @@ __global__ __launch_bounds__(kBlock) void k_integrate(
     float4 *__restrict__ pos4, const float4 *__restrict__ vel4, const float4 *__restrict__ frc4,
     float4 *__restrict__ vt4, int32_t *__restrict__ cell_of, int32_t *__restrict__ rank_of,
     int32_t *__restrict__ count, const uint32_t *__restrict__ bits_base, int use_mask,
-    const T *__restrict__ grid_base, Status *st, int64_t NF, const int32_t *__restrict__ wcstart) {
+    const typename PhiQuad<T>::type *__restrict__ quad_base, Status *st, int64_t NF,
+    const int32_t *__restrict__ wcstart) {
   const int tid = xcd_block();
   if (tid >= ntiles) return;
   const Tile tile = tiles[tid];
   const Box &B = boxes[tile.box];
   const KGeom G = B.G;
   const KParams P = B.P;
-  const T *grid = grid_base + B.go;
+  const typename PhiQuad<T>::type *quad = quad_base + B.go;
   const uint32_t *bits = bits_base + B.bo;
   const int co = (int)B.co;
   int64_t p[PPT];
@@ -622,7 +648,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(
   for (int u = 0; u < PPT; ++u) {
     m[u].cell = -1;
     if (a[u]) {
-      m[u] = integrate_one<T, REFLECT>(G, P, x[u], v[u], f[u], bits, use_mask, grid, st, co, NF,
+      m[u] = integrate_one<T, REFLECT>(G, P, x[u], v[u], f[u], bits, use_mask, quad, st, co, NF,
                                        wcstart, pos4, vt4);
       m[u].cell += co;
     }
@@ -1197,17 +1223,31 @@ inline unsigned xcd_grid(int64_t n, int block) {
   return (unsigned)(((nb + 7) / 8) * 8);
 }
 
+hipError_t launch_build_quad(hipStream_t s, const KGeom &G, const void *grid, int grid_f64,
+                             void *quad) {
+  const int64_t nodes = (int64_t)G.ng[0] * G.ng[1] * G.ng[2];
+  if (nodes <= 0) return hipSuccess;
+  if (grid_f64)
+    k_build_quad<double><<<grid_for(nodes), kBlock, 0, s>>>(G, (const double *)grid, nodes,
+                                                            (double4 *)quad);
+  else
+    k_build_quad<float><<<grid_for(nodes), kBlock, 0, s>>>(G, (const float *)grid, nodes,
+                                                           (float4 *)quad);
+  return hipGetLastError();
+}
+
 hipError_t launch_integrate(hipStream_t s, int ppt, const Box *boxes, const Tile *tiles,
                             int ntiles, float4 *pos4, const float4 *vel4, const float4 *frc4,
                             float4 *vt4, int32_t *cell_of, int32_t *rank_of, int32_t *count,
-                            const uint32_t *bits, int use_mask, const void *grid, int grid_f64,
+                            const uint32_t *bits, int use_mask, const void *quad, int grid_f64,
                             Status *st, int64_t NF, const int32_t *wcstart, int reflect) {
   if (ntiles <= 0) return hipSuccess;
   const unsigned nb = (unsigned)(((ntiles + 7) / 8) * 8);
 #define DPD_INTEGRATE(T, K, R)                                                                   \
   k_integrate<T, K, R><<<nb, kBlock, 0, s>>>(boxes, tiles, ntiles, pos4, vel4, frc4, vt4,       \
                                              cell_of, rank_of, count, bits, use_mask,           \
-                                             (const T *)grid, st, NF, wcstart)
+                                             (const typename PhiQuad<T>::type *)quad, st, NF,   \
+                                             wcstart)
 #define DPD_INTEGRATE_T(T, K) \
   if (reflect) DPD_INTEGRATE(T, K, true); else DPD_INTEGRATE(T, K, false)
   if (grid_f64) {

@@ -484,6 +484,18 @@ def batch_leg(dpd, replicas, steps):
     bsim.step(5)
     kt = bsim.kernel_times(0)
     bsim.close()
+    # the same batch as one persistent launch per step (dpd_use_persistent)
+    psim = dpd.Simulation(boxes, graph=True)
+    psim.use_persistent(True)
+    psim.step(3)
+    psim.sync()
+    psteps = max(5, steps // 5)
+    ta = time.perf_counter()
+    psim.step(psteps)
+    psim.sync()
+    tp = (time.perf_counter() - ta) * 1e3 / psteps
+    psim.close()
+    log("persistent launch per step: %.4f ms/step" % tp)
     batched = n_tot * steps / tb_
     log("batched: %.4f ms/step, %.4e particle-steps/s" % (tb_ * 1e3 / steps, batched))
     sims = [dpd.Simulation(b, graph=True) for b in boxes]
@@ -506,7 +518,7 @@ def batch_leg(dpd, replicas, steps):
             "value": batched, "unit": "particle-steps/s", "ms_per_step": tb_ * 1e3 / steps,
             "sequential_value": seq, "sequential_ms_per_step": ts * 1e3 / steps,
             "speedup_vs_sequential": batched / seq, "shape": list(shape),
-            "trial_ms_per_step": trials, "graph": True,
+            "trial_ms_per_step": trials, "graph": True, "persistent_ms_per_step": tp,
             "kernel_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in kt.items() if v[1]}}
 
 

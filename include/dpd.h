@@ -230,9 +230,10 @@ int dpd_counters(dpd_ctx *ctx, int64_t *out);
  * starts recording (dpd_step then times each kernel launch), 0 stops.
  * When out is not NULL it receives, for the kernels named by
  * dpd_kernel_name(0..DPD_NUM_KERNELS-1), the summed milliseconds in out_ms
- * and the number of timed launches in out_launches ("scan_top" has none: each
- * block of "scan_down" adds up the block sums before it; "scatter" also writes
- * the wall part of the merged cell runs).  Synchronises. */
+ * and the number of timed launches in out_launches ("scatter" also writes
+ * the wall part of the merged cell runs; "step_persistent" is the one launch
+ * of a step under dpd_use_persistent, which then replaces the five step
+ * kernels).  Synchronises. */
 #define DPD_NUM_KERNELS 8
 int dpd_kernel_times(dpd_ctx *ctx, int32_t enable, double *out_ms, int64_t *out_launches);
 const char *dpd_kernel_name(int32_t i);
@@ -274,6 +275,19 @@ int dpd_replica_profile(dpd_ctx *ctx, int32_t r, int32_t axis, int32_t nbins, do
  * bit-identical to direct launches.  Per-kernel timing, when enabled, uses
  * direct launches.  A captured graph is dropped by set_state and autotune. */
 int dpd_use_graph(dpd_ctx *ctx, int32_t enable);
+
+/* enable = 1: run each step as one persistent launch (plus a one-block
+ * kernel that clears its counters and advances k) instead of one launch per
+ * phase.  Work items (the integrate tiles, the cell-list scan chunks, scatter
+ * and per-cell sort ranges, and 256-particle pair-force tiles of every box)
+ * are taken in queue order from one device counter; an item of box r waits
+ * for the items of the previous phase of box r through per-box arrival
+ * counters (each wait bounded; a wait that reaches its bound is reported as
+ * DPD_E_DEVICE at the next synchronising call).  Results are bit-identical to
+ * the per-phase launches, and it combines with dpd_use_graph.  DPD_E_INVAL
+ * for contexts with moving walls or boxes on the LDS-staged brick pair kernel;
+ * enable = 0 returns to the per-phase launches. */
+int dpd_use_persistent(dpd_ctx *ctx, int32_t enable);
 
 /* Choose the launch shapes of the integrate kernel (particles per thread,
  * 1 or 2) and of the pair-force kernel (work-group size, 128 or 256) by

@@ -18,14 +18,14 @@ from .binding import (DPDError, dpd_autotune, dpd_batch_create, dpd_counters, dp
                       dpd_neighbor_pairs, dpd_profile, dpd_replica_count, dpd_replica_forces,
                       dpd_replica_pairs, dpd_replica_profile, dpd_replica_set_state,
                       dpd_phi_relax, dpd_replica_state, dpd_set_state, dpd_step, dpd_sync,
-                      dpd_use_graph, load_library)
+                      dpd_use_graph, dpd_use_persistent, load_library)
 
 __all__ = ["Simulation", "DPDError", "load_library", "dpd_create", "dpd_batch_create",
            "dpd_step", "dpd_forces", "dpd_get_state", "dpd_set_state", "dpd_neighbor_pairs",
            "dpd_profile", "dpd_counters", "dpd_kernel_times", "dpd_sync", "dpd_last_error",
            "dpd_destroy", "dpd_replica_count", "dpd_replica_forces", "dpd_replica_state",
            "dpd_replica_set_state", "dpd_replica_pairs", "dpd_replica_profile",
-           "dpd_use_graph", "dpd_autotune", "dpd_phi_relax", "relax_phi"]
+           "dpd_use_graph", "dpd_use_persistent", "dpd_autotune", "dpd_phi_relax", "relax_phi"]
 
 
 def relax_phi(phi, h, eps, dtau, iters, stream=None):
@@ -94,6 +94,10 @@ class Simulation:
 
     def use_graph(self, enable=True):
         dpd_use_graph(self.ctx, enable)
+
+    def use_persistent(self, enable=True):
+        """Each step as one persistent launch with per-box arrival counters."""
+        dpd_use_persistent(self.ctx, enable)
 
     def autotune(self, steps=10):
         return dpd_autotune(self.ctx, steps)

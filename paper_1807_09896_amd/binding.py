@@ -41,7 +41,7 @@ EXPORTED = ["dpd_create", "dpd_step", "dpd_forces", "dpd_get_state", "dpd_set_st
             "dpd_replica_profile", "dpd_use_graph", "dpd_autotune", "dpd_set_params",
             "dpd_set_phi", "dpd_window_forward", "dpd_backward", "dpd_phi_relax",
             "dpd_snapshot_size", "dpd_snapshot_io", "dpd_valu_probe", "dpd_phi_relax_static",
-            "dpd_window_trace"]
+            "dpd_window_trace", "dpd_use_persistent"]
 
 
 class DPDError(RuntimeError):
@@ -154,6 +154,8 @@ def load_library(path: str = LIB_PATH):
     L.dpd_replica_profile.restype = C.c_int
     L.dpd_use_graph.argtypes = [P, C.c_int32]
     L.dpd_use_graph.restype = C.c_int
+    L.dpd_use_persistent.argtypes = [P, C.c_int32]
+    L.dpd_use_persistent.restype = C.c_int
     L.dpd_autotune.argtypes = [P, C.c_int32, P, P]
     L.dpd_autotune.restype = C.c_int
     L.dpd_set_params.argtypes = [P, C.c_int32, P]
@@ -359,6 +361,10 @@ def dpd_replica_profile(ctx, r, axis, nbins, out):
 
 def dpd_use_graph(ctx, enable):
     _check(load_library().dpd_use_graph(ctx, int(enable)), ctx)
+
+
+def dpd_use_persistent(ctx, enable):
+    _check(load_library().dpd_use_persistent(ctx, int(enable)), ctx)
 
 
 def dpd_autotune(ctx, steps):

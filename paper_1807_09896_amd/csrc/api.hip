@@ -33,13 +33,13 @@ namespace {
 
 thread_local std::string g_create_error = "no error";
 
-enum Kernel { K_INTEGRATE = 0, K_SCAN_REDUCE, K_SCAN_TOP, K_SCAN_DOWN, K_SCATTER, K_SORT,
+enum Kernel { K_INTEGRATE = 0, K_SCAN_REDUCE, K_PERSIST, K_SCAN_DOWN, K_SCATTER, K_SORT,
               K_FORCE, K_OTHER };
-// "scan_top" records no launches (each scan_down block adds up the block
-// sums before it); the slot keeps the numbering of the others.
-const char *kKernelNames[DPD_NUM_KERNELS] = {"integrate_reflect_bin", "scan_reduce", "scan_top",
-                                             "scan_down", "scatter", "sort_cells", "pair_force",
-                                             "other"};
+// "step_persistent": the one launch of a persistent step (dpd_use_persistent),
+// which does the work of all the others.
+const char *kKernelNames[DPD_NUM_KERNELS] = {"integrate_reflect_bin", "scan_reduce",
+                                             "step_persistent", "scan_down", "scatter",
+                                             "sort_cells", "pair_force", "other"};
 
 struct TimedLaunch {
   int kernel;
@@ -144,6 +144,18 @@ struct dpd_ctx {
   bool use_graph = false;
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
+
+  // persistent step (dpd_use_persistent): work items, per-(box, phase) item
+  // counts and arrivals, the queue counter, per-box scan chunk sums, 256-particle
+  // force tiles, and the launch arguments for either buffer set
+  bool persistent = false;
+  dpd::PItem *pitems = nullptr;
+  int n_pitems = 0;
+  int32_t *pneed = nullptr, *parrive = nullptr, *phead = nullptr, *pbsum = nullptr;
+  Tile *ptiles = nullptr;
+  int n_ptiles = 0, ptiles_cap = 0;
+  dpd::PArgs *pargs[2] = {nullptr, nullptr};
+  int pblocks = 0;
 
   Window win;
   uint64_t gen = 0;  // bumped when parameters, phi or the state are replaced
@@ -283,6 +295,10 @@ int latched_error(dpd_ctx *c) {
   if (st.unstable)
     return fail(c, DPD_E_UNSTABLE, "a particle moved more than half a cell in one step (" +
                                        std::to_string(st.unstable) + " events)");
+  if (st.stalled)
+    return fail(c, DPD_E_DEVICE, "a persistent step's wait reached its bound (" +
+                                     std::to_string(st.stalled) +
+                                     " waits); the state after it is not valid");
   return DPD_OK;
 }
 
@@ -330,6 +346,8 @@ int build_tiles(dpd_ctx *c, int size, Tile **dst, int *n, int *cap, bool without
   return DPD_OK;
 }
 
+int build_persistent(dpd_ctx *c);
+
 int set_shapes(dpd_ctx *c, int ppt, int fblock) {
   c->ppt = ppt;
   c->fblock = fblock;
@@ -337,7 +355,129 @@ int set_shapes(dpd_ctx *c, int ppt, int fblock) {
   int rc = build_tiles(c, 256 * ppt, &c->itiles, &c->n_itiles, &c->itiles_cap);
   if (!rc) rc = build_tiles(c, fblock, &c->ftiles, &c->n_ftiles, &c->ftiles_cap);
   if (!rc) rc = build_tiles(c, fblock, &c->otiles, &c->n_otiles, &c->otiles_cap, true);
+  if (!rc && c->persistent) rc = build_persistent(c);
   return rc;
+}
+
+// Work items of the persistent step, in queue order: every integrate tile,
+// then per box its scan chunks (reduce, then down), its scatter ranges (fluid
+// slots, then walls), its per-cell sort ranges, and its force tiles; each
+// phase's items of all boxes before the next phase's, so that no item waits
+// on one after it.  need[box][phase] counts them.
+constexpr int kScatterItem = 4096;   // particles per scatter item
+constexpr int kSortItem = 2048;      // cells per sort item
+
+int build_persistent(dpd_ctx *c) {
+  using dpd::PItem;
+  const int R = c->R, NP = dpd::kPhases;
+  int rc = build_tiles(c, 256, &c->ptiles, &c->n_ptiles, &c->ptiles_cap, true);
+  if (rc) return rc;
+  std::vector<Tile> it((size_t)c->n_itiles), ft((size_t)c->n_ptiles);
+  if (c->n_itiles)
+    HIP_TRY(c, hipMemcpy(it.data(), c->itiles, sizeof(Tile) * it.size(), hipMemcpyDeviceToHost));
+  if (c->n_ptiles)
+    HIP_TRY(c, hipMemcpy(ft.data(), c->ptiles, sizeof(Tile) * ft.size(), hipMemcpyDeviceToHost));
+  std::vector<PItem> items;
+  std::vector<int32_t> need((size_t)R * NP, 0);
+  auto add = [&](int phase, int box, int64_t a, int64_t b) {
+    items.push_back(PItem{phase, box, (int32_t)a, (int32_t)b});
+    need[(size_t)box * NP + phase] += 1;
+  };
+  for (int t = 0; t < c->n_itiles; ++t) add(dpd::kPhIntegrate, it[t].box, t, 0);
+  std::vector<int> chunk0((size_t)R);
+  int nch_all = 0;
+  for (int r = 0; r < R; ++r) {
+    chunk0[r] = nch_all;
+    nch_all += (int)((c->rep[r].ncell + dpd::kScanChunk - 1) / dpd::kScanChunk);
+  }
+  for (int ph : {(int)dpd::kPhReduce, (int)dpd::kPhDown})
+    for (int r = 0; r < R; ++r) {
+      const int n = (int)((c->rep[r].ncell + dpd::kScanChunk - 1) / dpd::kScanChunk);
+      for (int j = 0; j < n; ++j) add(ph, r, j, chunk0[r]);
+    }
+  for (int r = 0; r < R; ++r) {
+    const Replica &p = c->rep[r];
+    for (int64_t a = p.fo; a < p.fo + p.nf; a += kScatterItem)
+      add(dpd::kPhScatter, r, a, std::min(a + kScatterItem, p.fo + p.nf));
+    const int64_t w0 = c->NF + p.wo, w1 = w0 + p.nw;
+    for (int64_t a = w0; a < w1; a += kScatterItem)
+      add(dpd::kPhScatter, r, a, std::min(a + kScatterItem, w1));
+  }
+  for (int r = 0; r < R; ++r) {
+    const Replica &p = c->rep[r];
+    for (int64_t a = p.co; a < p.co + p.ncell; a += kSortItem)
+      add(dpd::kPhSort, r, a, std::min(a + kSortItem, p.co + p.ncell));
+  }
+  for (int t = 0; t < c->n_ptiles; ++t) add(dpd::kPhForce, ft[t].box, t, 0);
+  if (c->NF + c->NW + (int64_t)nch_all >= ((int64_t)1 << 31))
+    return fail(c, DPD_E_INVAL, "the batch is too large for the persistent step");
+
+  for (void *q : {(void *)c->pitems, (void *)c->pneed, (void *)c->parrive, (void *)c->phead,
+                  (void *)c->pbsum, (void *)c->pargs[0], (void *)c->pargs[1]})
+    if (q) dfree(c, q);
+  c->pitems = (PItem *)dalloc(c, sizeof(PItem) * std::max<size_t>(items.size(), 1));
+  c->pneed = (int32_t *)dalloc(c, 4 * need.size());
+  c->parrive = (int32_t *)dalloc(c, 4 * need.size());
+  c->phead = (int32_t *)dalloc(c, 4);
+  c->pbsum = (int32_t *)dalloc(c, 4 * (size_t)std::max(nch_all, 1));
+  c->pargs[0] = (dpd::PArgs *)dalloc(c, sizeof(dpd::PArgs));
+  c->pargs[1] = (dpd::PArgs *)dalloc(c, sizeof(dpd::PArgs));
+  if (!c->pitems || !c->pneed || !c->parrive || !c->phead || !c->pbsum || !c->pargs[0] ||
+      !c->pargs[1])
+    return fail(c, DPD_E_NOMEM, "persistent-step allocation failed");
+  c->n_pitems = (int)items.size();
+  if (!items.empty())
+    HIP_TRY(c, hipMemcpy(c->pitems, items.data(), sizeof(PItem) * items.size(),
+                         hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(c->pneed, need.data(), 4 * need.size(), hipMemcpyHostToDevice));
+  for (int a = 0; a < 2; ++a) {
+    const int b = 1 - a;
+    dpd::PArgs A{};
+    A.boxes = c->boxes;
+    A.items = c->pitems;
+    A.nitems = c->n_pitems;
+    A.spin_limit = 1 << 16;
+    A.need = c->pneed;
+    A.arrive = c->parrive;
+    A.head = c->phead;
+    A.itiles = c->itiles;
+    A.ftiles = c->ptiles;
+    A.pos4 = c->pos[a];
+    A.vel4 = c->vel[a];
+    A.frc4 = c->frc[a];
+    A.vt4 = c->vt;
+    A.cell_of = c->cell_of;
+    A.rank_of = c->rank_of;
+    A.count = c->count;
+    A.bits = c->bits;
+    A.use_mask = c->use_mask;
+    A.quad = c->quad;
+    A.st = c->status;
+    A.NF = c->NF;
+    A.NW = c->NW;
+    A.wcstart = c->wcstart;
+    A.wcell = c->wcell;
+    A.cstart = c->cstart;
+    A.bsum = c->pbsum;
+    A.start_all = c->start_all;
+    A.fluid_off = c->fluid_off;
+    A.idx = c->idx;
+    A.idx_all = c->idx_all;
+    A.pad = (int32_t)(c->NF + c->NW);
+    A.ncell_all = (int32_t)c->NCELL;
+    A.pos_out = c->pos[b];
+    A.vel_out = c->vel[b];
+    A.frc_out = c->frc[b];
+    A.dk = c->dk;
+    HIP_TRY(c, hipMemcpy(c->pargs[a], &A, sizeof(A), hipMemcpyHostToDevice));
+  }
+  int ncu = 0;
+  HIP_TRY(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
+  const int per = dpd::persistent_blocks_per_cu(c->ppt, c->grid_f64, c->reflect ? 1 : 0,
+                                                c->sph ? 1 : 0);
+  if (per <= 0) return fail(c, DPD_E_DEVICE, "persistent step: no resident blocks");
+  c->pblocks = per * ncu;
+  return DPD_OK;
 }
 
 // Cuts of one axis of n cells into bricks of at most B cells.  The brick at
@@ -519,6 +659,15 @@ int wall_pass(dpd_ctx *c, hipStream_t s, int move) {
 
 int enqueue_step(dpd_ctx *c, hipStream_t s) {
   const int a = c->cur;
+  if (c->persistent) {
+    HIP_TRY(c, timed(c, s, K_PERSIST, [&] {
+              return dpd::launch_step_persistent(
+                  s, c->pargs[a], c->n_pitems, c->pblocks, c->parrive, dpd::kPhases * c->R,
+                  c->phead, c->dk, c->grid_f64, c->ppt, c->reflect ? 1 : 0, c->sph ? 1 : 0);
+            }));
+    c->cur = 1 - a;
+    return DPD_OK;
+  }
   HIP_TRY(c, timed(c, s, K_INTEGRATE, [&] {
             return dpd::launch_integrate(s, c->ppt, c->boxes, c->itiles, c->n_itiles, c->pos[a],
                                          c->vel[a], c->frc[a], c->vt, c->cell_of, c->rank_of,
@@ -1383,6 +1532,27 @@ int dpd_use_graph(dpd_ctx *c, int32_t enable) {
   if (!c) return DPD_E_INVAL;
   if ((enable != 0) != c->use_graph) drop_graphs(c);
   c->use_graph = enable != 0;
+  return DPD_OK;
+}
+
+int dpd_use_persistent(dpd_ctx *c, int32_t enable) {
+  if (!c) return DPD_E_INVAL;
+  if (!enable) {
+    if (c->persistent) drop_graphs(c);
+    c->persistent = false;
+    return DPD_OK;
+  }
+  if (c->nbricks > 0)
+    return fail(c, DPD_E_INVAL, "the persistent step needs the per-particle pair kernel");
+  if (c->moving) return fail(c, DPD_E_INVAL, "the persistent step does not move walls");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->persistent = true;
+  int rc = build_persistent(c);
+  if (rc) {
+    c->persistent = false;
+    return rc;
+  }
+  drop_graphs(c);
   return DPD_OK;
 }
 

@@ -98,7 +98,15 @@ struct Status {
   unsigned long long bad_phi;    // fluid particles with phi < 0 at create
   unsigned long long bad_grid;   // non-finite phi grid values at create
   unsigned long long lookups;    // phi evaluations at drifted positions
-  unsigned long long pad;
+  unsigned long long stalled;    // persistent-step waits that hit their bound
+};
+
+// The persistent step (k_step_persistent): work items in queue order, each
+// one block's work in one phase of one box.
+enum PersistPhase { kPhIntegrate = 0, kPhReduce, kPhDown, kPhScatter, kPhSort, kPhForce, kPhases };
+struct PItem {
+  int32_t phase, box;
+  int32_t a, b;   // tile index (integrate, force), chunk index (reduce, down), or range [a, b)
 };
 
 // ---------------------------------------------------------------------------

@@ -83,6 +83,41 @@ hipError_t launch_check_grid(hipStream_t s, const void *grid, int grid_f64, int6
 hipError_t launch_check_phi(hipStream_t s, const KGeom &G, const void *grid, int grid_f64,
                             int64_t n, const float4 *pos4, Status *st);
 
+// One launch for a whole step of a batch (k_step_persistent): work items of
+// the six phases in queue order with per-box, per-phase arrival counters,
+// preceded by a one-block kernel that clears the counters and advances k.
+// Arguments of the persistent step, in device memory.
+struct PArgs {
+  const Box *boxes;
+  const PItem *items;
+  int nitems;
+  int spin_limit;
+  const int32_t *need;     // items per (box, phase)
+  int32_t *arrive;         // arrivals per (box, phase), zeroed before the launch
+  int32_t *head;           // queue counter, zeroed before the launch
+  const Tile *itiles, *ftiles;
+  float4 *pos4;
+  const float4 *vel4, *frc4;
+  float4 *vt4;
+  int32_t *cell_of, *rank_of, *count;
+  const uint32_t *bits;
+  int use_mask;
+  const void *quad;
+  Status *st;
+  int64_t NF, NW;
+  const int32_t *wcstart, *wcell;
+  int32_t *cstart, *bsum, *start_all, *fluid_off, *idx, *idx_all;
+  int32_t pad, ncell_all;
+  float4 *pos_out, *vel_out, *frc_out;
+  const unsigned long long *dk;
+};
+hipError_t launch_step_persistent(hipStream_t s, const PArgs *args, int nitems, int blocks,
+                                  int32_t *arrive, int narrive, int32_t *head,
+                                  unsigned long long *dk, int grid_f64, int ppt, int reflect,
+                                  int sph);
+// Resident blocks per CU of the instance the launch would run, or -1.
+int persistent_blocks_per_cu(int ppt, int grid_f64, int reflect, int sph);
+
 // The face layout of one box's phase field (PhiQuad in device.h): 16 bytes
 // per node for a float32 grid, 32 for float64, into quad.
 hipError_t launch_build_quad(hipStream_t s, const KGeom &G, const void *grid, int grid_f64,

@@ -148,11 +148,10 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *lds, int &total)
   return incl - v;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(int64_t n,
-                                                              const int32_t *__restrict__ count,
-                                                              int32_t *__restrict__ bsum) {
-  __shared__ int lds[kScanThreads];
-  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+// Sum of count over the chunk [base, min(base + kScanChunk, n)) into *out.
+__device__ __forceinline__ void scan_reduce_chunk(int64_t base, int64_t n,
+                                                  const int32_t *__restrict__ count,
+                                                  int32_t *__restrict__ out, int *lds) {
   int acc = 0;
   for (int k = 0; k < kScanItems; ++k) {
     const int64_t i = base + (int64_t)k * kScanThreads + threadIdx.x;
@@ -164,7 +163,15 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(int64_t n,
     if ((int)threadIdx.x < off) lds[threadIdx.x] += lds[threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0) bsum[blockIdx.x] = lds[0];
+  if (threadIdx.x == 0) *out = lds[0];
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(int64_t n,
+                                                              const int32_t *__restrict__ count,
+                                                              int32_t *__restrict__ bsum) {
+  __shared__ int lds[kScanThreads];
+  scan_reduce_chunk((int64_t)blockIdx.x * kScanChunk, n, count, bsum + blockIdx.x, lds);
 }
 
 // Sum of v over the block (kScanThreads threads, four wavefronts).
@@ -184,16 +191,16 @@ __device__ __forceinline__ int block_sum(int v, int *lds) {
 // offsets wstart (exclusive scan of the static wall counts) it also writes
 // the merged runs: start_all[c] = start[c] + wstart[c] begins cell c's run of
 // walls then fluid, fluid_off[c] = start_all[c] + (walls in c) its fluid part.
-__global__ __launch_bounds__(kScanThreads) void k_scan_down(
-    int64_t n, int32_t *__restrict__ count, int32_t *__restrict__ start,
-    const int32_t *__restrict__ bsum, const int32_t *__restrict__ wstart,
-    int32_t *__restrict__ start_all, int32_t *__restrict__ fluid_off) {
-  __shared__ int tile[kScanChunk + kScanChunk / 32];
-  __shared__ int lds[kScanThreads];
-  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
-  int prior = 0;
-  for (int j = (int)threadIdx.x; j < (int)blockIdx.x; j += kScanThreads) prior += bsum[j];
-  const int offset = block_sum(prior, lds);
+// The chunk [base, min(base + kScanChunk, n)) of the exclusive scan, offset
+// by the sum of everything before it; the last chunk (last) also writes the
+// entry n after the end.  count is cleared for the next step.
+__device__ __forceinline__ void scan_down_chunk(int64_t base, int64_t n, int offset, bool last,
+                                                int32_t *__restrict__ count,
+                                                int32_t *__restrict__ start,
+                                                const int32_t *__restrict__ wstart,
+                                                int32_t *__restrict__ start_all,
+                                                int32_t *__restrict__ fluid_off, int *tile,
+                                                int *lds) {
   for (int k = 0; k < kScanItems; ++k) {
     const int local = k * kScanThreads + threadIdx.x;
     const int64_t i = base + local;
@@ -233,10 +240,24 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(
       }
     }
   }
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kScanThreads - 1) {
+  if (last && threadIdx.x == kScanThreads - 1) {
     start[n] = offset + total;
     if (wstart) start_all[n] = offset + total + wstart[n];
   }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(
+    int64_t n, int32_t *__restrict__ count, int32_t *__restrict__ start,
+    const int32_t *__restrict__ bsum, const int32_t *__restrict__ wstart,
+    int32_t *__restrict__ start_all, int32_t *__restrict__ fluid_off) {
+  __shared__ int tile[kScanChunk + kScanChunk / 32];
+  __shared__ int lds[kScanThreads];
+  int prior = 0;
+  for (int j = (int)threadIdx.x; j < (int)blockIdx.x; j += kScanThreads) prior += bsum[j];
+  const int offset = block_sum(prior, lds);
+  scan_down_chunk((int64_t)blockIdx.x * kScanChunk, n, offset, blockIdx.x == gridDim.x - 1, count,
+                  start, wstart, start_all, fluid_off, tile, lds);
 }
 
 // idx[start[cell_of[p]] + rank_of[p]] = p for the n entries.  Threads n ..
@@ -244,14 +265,14 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(
 // cell wcell[w], is index n + w of the position arrays), and with dk the
 // first thread advances the force evaluation index, so that one launch does
 // the work of three.
-__global__ void k_scatter(int64_t n, const int32_t *__restrict__ cell_of,
-                          const int32_t *__restrict__ rank_of, const int32_t *__restrict__ start,
-                          int32_t *__restrict__ idx, int64_t nw, const int32_t *__restrict__ wcell,
-                          const int32_t *__restrict__ wstart,
-                          const int32_t *__restrict__ start_all, int32_t *__restrict__ idx_all,
-                          unsigned long long *__restrict__ dk) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (dk && p == 0) *dk += 1ull;
+__device__ __forceinline__ void scatter_one(int64_t p, int64_t n, const int32_t *__restrict__ cell_of,
+                                            const int32_t *__restrict__ rank_of,
+                                            const int32_t *__restrict__ start,
+                                            int32_t *__restrict__ idx, int64_t nw,
+                                            const int32_t *__restrict__ wcell,
+                                            const int32_t *__restrict__ wstart,
+                                            const int32_t *__restrict__ start_all,
+                                            int32_t *__restrict__ idx_all) {
   if (p < n) {
     idx[start[cell_of[p]] + rank_of[p]] = (int32_t)p;
     return;
@@ -260,6 +281,17 @@ __global__ void k_scatter(int64_t n, const int32_t *__restrict__ cell_of,
   if (w >= nw) return;
   const int c = wcell[w];
   idx_all[start_all[c] + ((int)w - wstart[c])] = (int32_t)(n + w);
+}
+
+__global__ void k_scatter(int64_t n, const int32_t *__restrict__ cell_of,
+                          const int32_t *__restrict__ rank_of, const int32_t *__restrict__ start,
+                          int32_t *__restrict__ idx, int64_t nw, const int32_t *__restrict__ wcell,
+                          const int32_t *__restrict__ wstart,
+                          const int32_t *__restrict__ start_all, int32_t *__restrict__ idx_all,
+                          unsigned long long *__restrict__ dk) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (dk && p == 0) *dk += 1ull;
+  scatter_one(p, n, cell_of, rank_of, start, idx, nw, wcell, wstart, start_all, idx_all);
 }
 
 // A cell's run of up to K storage indices (the common case: about four per
@@ -297,12 +329,11 @@ __device__ __forceinline__ void sort_run_regs(int32_t *__restrict__ idx, int a, 
 // Runs of up to 16 are sorted in registers (sort_run_regs); longer runs, and
 // the gid order, by an insertion sort in memory.
 template <bool BY_GID>
-__global__ void k_sort_cells(int64_t ncell, const int32_t *__restrict__ start,
-                             int32_t *__restrict__ idx, const float4 *__restrict__ key4,
-                             const int32_t *__restrict__ fluid_off,
-                             int32_t *__restrict__ idx_all) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncell) return;
+__device__ __forceinline__ void sort_cell(int64_t c, const int32_t *__restrict__ start,
+                                          int32_t *__restrict__ idx,
+                                          const float4 *__restrict__ key4,
+                                          const int32_t *__restrict__ fluid_off,
+                                          int32_t *__restrict__ idx_all) {
   const int a = start[c], b = start[c + 1];
   if (!BY_GID && b - a <= 16) {
     int32_t *out = idx_all ? idx_all + fluid_off[c] : nullptr;
@@ -328,6 +359,16 @@ __global__ void k_sort_cells(int64_t ncell, const int32_t *__restrict__ start,
     const int o = fluid_off[c];
     for (int i = a; i < b; ++i) idx_all[o + (i - a)] = idx[i];
   }
+}
+
+template <bool BY_GID>
+__global__ void k_sort_cells(int64_t ncell, const int32_t *__restrict__ start,
+                             int32_t *__restrict__ idx, const float4 *__restrict__ key4,
+                             const int32_t *__restrict__ fluid_off,
+                             int32_t *__restrict__ idx_all) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  sort_cell<BY_GID>(c, start, idx, key4, fluid_off, idx_all);
 }
 
 // The pad entry after fluid and walls: a position far outside the box, so
@@ -607,18 +648,16 @@ __device__ __forceinline__ int wave_rank(const RunInfo &r, int base) {
   return __shfl(base, h, 64) + (lane - h);
 }
 
-// One block per tile of up to PPT x kBlock particles of one box; each thread
-// advances PPT particles.
+// Tile tid of up to PPT x kBlock particles of one box, by one block of
+// kBlock threads; each thread advances PPT particles.
 template <typename T, int PPT, bool REFLECT>
-__global__ __launch_bounds__(kBlock) void k_integrate(
-    const Box *__restrict__ boxes, const Tile *__restrict__ tiles, int ntiles,
+__device__ __forceinline__ void integrate_tile(
+    int tid, const Box *__restrict__ boxes, const Tile *__restrict__ tiles,
     float4 *__restrict__ pos4, const float4 *__restrict__ vel4, const float4 *__restrict__ frc4,
     float4 *__restrict__ vt4, int32_t *__restrict__ cell_of, int32_t *__restrict__ rank_of,
     int32_t *__restrict__ count, const uint32_t *__restrict__ bits_base, int use_mask,
     const typename PhiQuad<T>::type *__restrict__ quad_base, Status *st, int64_t NF,
     const int32_t *__restrict__ wcstart) {
-  const int tid = xcd_block();
-  if (tid >= ntiles) return;
   const Tile tile = tiles[tid];
   const Box &B = boxes[tile.box];
   const KGeom G = B.G;
@@ -668,6 +707,20 @@ __global__ __launch_bounds__(kBlock) void k_integrate(
       rank_of[p[u]] = k;
     }
   }
+}
+
+template <typename T, int PPT, bool REFLECT>
+__global__ __launch_bounds__(kBlock) void k_integrate(
+    const Box *__restrict__ boxes, const Tile *__restrict__ tiles, int ntiles,
+    float4 *__restrict__ pos4, const float4 *__restrict__ vel4, const float4 *__restrict__ frc4,
+    float4 *__restrict__ vt4, int32_t *__restrict__ cell_of, int32_t *__restrict__ rank_of,
+    int32_t *__restrict__ count, const uint32_t *__restrict__ bits_base, int use_mask,
+    const typename PhiQuad<T>::type *__restrict__ quad_base, Status *st, int64_t NF,
+    const int32_t *__restrict__ wcstart) {
+  const int tid = xcd_block();
+  if (tid >= ntiles) return;
+  integrate_tile<T, PPT, REFLECT>(tid, boxes, tiles, pos4, vel4, frc4, vt4, cell_of, rank_of, count,
+                                  bits_base, use_mask, quad_base, st, NF, wcstart);
 }
 
 // Walls of a box whose solid moves translate with it: x += dt v per axis in
@@ -767,20 +820,16 @@ __device__ __forceinline__ void add_pair(Acc &acc, float dx, float dy, float dz,
   acc.z += mag * ez;
 }
 
-// Eight wavefronts per SIMD (at most 64 VGPRs): the walk waits on dependent
-// loads, and more wavefronts in flight hide more of that wait.
+// Tile tid by one block of BS threads; list: kListCap x BS words of LDS.
 template <bool INIT, int BS, bool SPH>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_force(
-    const Box *__restrict__ boxes, const Tile *__restrict__ tiles, int ntiles, int64_t NF,
-    int32_t pad, int32_t ncell_all, const float4 *__restrict__ pos4,
+__device__ __forceinline__ void force_tile(
+    int tid, uint32_t *list, const Box *__restrict__ boxes, const Tile *__restrict__ tiles,
+    int64_t NF, int32_t pad, int32_t ncell_all, const float4 *__restrict__ pos4,
     const float4 *__restrict__ vt4, const float4 *__restrict__ vel4,
     const float4 *__restrict__ frc4, const int32_t *__restrict__ idx,
     const int32_t *__restrict__ idx_all, const int32_t *__restrict__ start_all,
     float4 *__restrict__ pos_out, float4 *__restrict__ vel_out, float4 *__restrict__ frc_out,
     const unsigned long long *__restrict__ dk, Status *st) {
-  __shared__ uint32_t list[kListCap * BS];
-  const int tid = xcd_block();
-  if (tid >= ntiles) return;
   const Tile tile = tiles[tid];
   if ((int)threadIdx.x >= tile.count) return;
   const Box &B = boxes[tile.box];
@@ -934,6 +983,24 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_
   frc_out[s] = make_float4(fx, fy, fz, 0.f);
 }
 
+// Eight wavefronts per SIMD (at most 64 VGPRs): the walk waits on dependent
+// loads, and more wavefronts in flight hide more of that wait.
+template <bool INIT, int BS, bool SPH>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_force(
+    const Box *__restrict__ boxes, const Tile *__restrict__ tiles, int ntiles, int64_t NF,
+    int32_t pad, int32_t ncell_all, const float4 *__restrict__ pos4,
+    const float4 *__restrict__ vt4, const float4 *__restrict__ vel4,
+    const float4 *__restrict__ frc4, const int32_t *__restrict__ idx,
+    const int32_t *__restrict__ idx_all, const int32_t *__restrict__ start_all,
+    float4 *__restrict__ pos_out, float4 *__restrict__ vel_out, float4 *__restrict__ frc_out,
+    const unsigned long long *__restrict__ dk, Status *st) {
+  __shared__ uint32_t list[kListCap * BS];
+  const int tid = xcd_block();
+  if (tid >= ntiles) return;
+  force_tile<INIT, BS, SPH>(tid, list, boxes, tiles, NF, pad, ncell_all, pos4, vt4, vel4, frc4,
+                            idx, idx_all, start_all, pos_out, vel_out, frc_out, dk, st);
+}
+
 // Interacting pairs with the same decision as the force kernel.  Each thread
 // counts its pairs, a wavefront reserves room with one atomic, then the
 // pairs are written.
@@ -1082,6 +1149,192 @@ __global__ void k_profile(const KGeom G, int64_t nf, const float4 *__restrict__ 
   atomicAdd(o + 2, (double)v.y);
   atomicAdd(o + 3, (double)v.z);
   atomicAdd(o + 4, (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent step: one launch for a whole step of every box of a batch.
+// Blocks take work items in queue order from one counter; an item of phase
+// p of box r first waits until every item of phase p - 1 of box r has
+// arrived (a per-box, per-phase counter), so boxes run through the phases
+// independently and no launch boundary separates them.  Every item waits
+// only on items earlier in the queue, which blocks that are already running
+// have taken, so the waits end whatever the number of resident blocks; each
+// is also bounded (spin_limit sleeps), after which the item runs anyway and
+// `stalled` reports the step as invalid.  The per-phase bodies are those of
+// the per-phase kernels, so results are bit-identical to them.
+// ---------------------------------------------------------------------------
+
+// A value the same in every lane, as a scalar: function arguments arrive in
+// vector registers, and without this every pointer loaded through them would
+// be a per-lane value (vector loads of the arguments, buffer descriptors
+// built lane by lane).
+template <typename P>
+__device__ __forceinline__ P *uniform_ptr(P *p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (P *)(((uint64_t)hi << 32) | lo);
+}
+// The arguments block, read through the constant address space (scalar loads).
+typedef const __attribute__((address_space(4))) PArgs *ArgsPtr;
+__device__ __forceinline__ ArgsPtr uniform_args(const PArgs *p) {
+  return (ArgsPtr)uniform_ptr(p);
+}
+__device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// A pointer into the block's LDS (the caller's __shared__ array): the cast
+// through the local address space lets the compiler use LDS instructions.
+template <typename P>
+__device__ __forceinline__ P *lds_ptr(P *p) {
+  return (P *)(__attribute__((address_space(3))) P *)p;
+}
+
+// The phase bodies as separate functions, each register-allocated on its own
+// (inlined into one loop, the union of their live ranges would cut the
+// kernel to two wavefronts per SIMD); each reads the arguments it needs.
+template <typename T, int PPT, bool REFLECT>
+__device__ __attribute__((noinline)) void p_integrate(const PArgs *__restrict__ A0, int tile0) {
+  const ArgsPtr A = uniform_args(A0);
+  const int tile = uniform_int(tile0);
+  integrate_tile<T, PPT, REFLECT>(tile, A->boxes, A->itiles, A->pos4, A->vel4, A->frc4, A->vt4,
+                                  A->cell_of, A->rank_of, A->count, A->bits, A->use_mask,
+                                  (const typename PhiQuad<T>::type *)A->quad, A->st, A->NF,
+                                  A->wcstart);
+}
+
+// chunk a of box `box`'s cells; its block sum at bsum[b + a]
+__device__ __attribute__((noinline)) void p_reduce(const PArgs *__restrict__ A0, int box0,
+                                                   int a0, int b0, int *lds0) {
+  const ArgsPtr A = uniform_args(A0);
+  const int box = uniform_int(box0), a = uniform_int(a0), b = uniform_int(b0);
+  int *lds = lds_ptr(lds0);
+  const int64_t co = A->boxes[box].co, ncell = A->boxes[box].ncell;
+  scan_reduce_chunk(co + (int64_t)a * kScanChunk, co + ncell, A->count, A->bsum + b + a, lds);
+}
+
+// the box's fluid starts at slot fo; its chunks before this one add to it
+__device__ __attribute__((noinline)) void p_down(const PArgs *__restrict__ A0, int box0, int a0,
+                                                 int b0, int *tile0, int *lds0) {
+  const ArgsPtr A = uniform_args(A0);
+  const int box = uniform_int(box0), a = uniform_int(a0), b = uniform_int(b0);
+  int *tile = lds_ptr(tile0), *lds = lds_ptr(lds0);
+  const int64_t co = A->boxes[box].co, ncell = A->boxes[box].ncell, fo = A->boxes[box].fo;
+  int prior = 0;
+  for (int j = (int)threadIdx.x; j < a; j += kScanThreads) prior += A->bsum[b + j];
+  const int offset = (int)fo + block_sum(prior, lds);
+  const bool last = (int64_t)(a + 1) * kScanChunk >= ncell;
+  scan_down_chunk(co + (int64_t)a * kScanChunk, co + ncell, offset, last, A->count, A->cstart,
+                  A->wcstart, A->start_all, A->fluid_off, tile, lds);
+}
+
+__device__ __attribute__((noinline)) void p_scatter(const PArgs *__restrict__ A0, int a0, int b0) {
+  const ArgsPtr A = uniform_args(A0);
+  const int a = uniform_int(a0), b = uniform_int(b0);
+  for (int64_t p = (int64_t)a + threadIdx.x; p < (int64_t)b; p += kBlock)
+    scatter_one(p, A->NF, A->cell_of, A->rank_of, A->cstart, A->idx, A->NW, A->wcell, A->wcstart,
+                A->start_all, A->idx_all);
+}
+
+__device__ __attribute__((noinline)) void p_sort(const PArgs *__restrict__ A0, int a0, int b0) {
+  const ArgsPtr A = uniform_args(A0);
+  const int a = uniform_int(a0), b = uniform_int(b0);
+  for (int64_t c = (int64_t)a + threadIdx.x; c < (int64_t)b; c += kBlock)
+    sort_cell<false>(c, A->cstart, A->idx, nullptr, A->fluid_off, A->idx_all);
+}
+
+template <bool SPH>
+__device__ __attribute__((noinline)) void p_force(const PArgs *__restrict__ A0, int tile0,
+                                                  uint32_t *list0) {
+  const ArgsPtr A = uniform_args(A0);
+  const int tile = uniform_int(tile0);
+  uint32_t *list = lds_ptr(list0);
+  force_tile<false, kBlock, SPH>(tile, list, A->boxes, A->ftiles, A->NF, A->pad, A->ncell_all,
+                                 A->pos4, A->vt4, A->vel4, A->frc4, A->idx, A->idx_all,
+                                 A->start_all, A->pos_out, A->vel_out, A->frc_out, A->dk, A->st);
+}
+
+template <typename T, int PPT, bool REFLECT, bool SPH>
+// Seven wavefronts per SIMD: the phase functions are allocated separately
+// and the largest (the pair force, 64 VGPRs in its own kernel) needs a few
+// more registers as a callee.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) void
+k_step_persistent(const PArgs *__restrict__ A) {
+  __shared__ union {
+    uint32_t list[kListCap * kBlock];
+    struct {
+      int tile[kScanChunk + kScanChunk / 32];
+      int lds[kScanThreads];
+    } scan;
+  } sm;
+  __shared__ int s_item, s_ok;
+  const int t = (int)threadIdx.x;
+  const int nitems = A->nitems;
+  // The item index and the item are the same in every lane; readfirstlane
+  // makes that visible to the compiler, and the loop tests it at its head,
+  // so the loop and the phase switch are uniform branches and every barrier
+  // runs with all lanes.  (With the index as a per-lane value and the exit
+  // in the middle of the loop, the loop was compiled as divergent and
+  // rotated so that lanes 1-63 of the first wavefront went back to the top
+  // barrier and re-read the index before lane 0 had taken the next one.)
+  if (t == 0) s_item = atomicAdd(A->head, 1);
+  __syncthreads();
+  int it = __builtin_amdgcn_readfirstlane(s_item);
+  while (it < nitems) {
+    const PItem Iv = A->items[it];
+    PItem I;
+    I.phase = __builtin_amdgcn_readfirstlane(Iv.phase);
+    I.box = __builtin_amdgcn_readfirstlane(Iv.box);
+    I.a = __builtin_amdgcn_readfirstlane(Iv.a);
+    I.b = __builtin_amdgcn_readfirstlane(Iv.b);
+    if (t == 0) {
+      int ok = 1;
+      if (I.phase != kPhIntegrate) {
+        const int dep = I.box * kPhases + I.phase - 1;
+        const int need = A->need[dep];
+        const int limit = A->spin_limit;
+        int spins = 0;
+        while (__hip_atomic_load(&A->arrive[dep], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <
+               need) {
+          __builtin_amdgcn_s_sleep(4);
+          if (++spins >= limit) {
+            ok = 0;
+            break;
+          }
+        }
+      }
+      s_ok = ok;
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (t == 0 && !__builtin_amdgcn_readfirstlane(s_ok)) atomicAdd(&A->st->stalled, 1ull);
+    switch (I.phase) {
+      case kPhIntegrate: p_integrate<T, PPT, REFLECT>(A, I.a); break;
+      case kPhReduce: p_reduce(A, I.box, I.a, I.b, sm.scan.lds); break;
+      case kPhDown: p_down(A, I.box, I.a, I.b, sm.scan.tile, sm.scan.lds); break;
+      case kPhScatter: p_scatter(A, I.a, I.b); break;
+      case kPhSort: p_sort(A, I.a, I.b); break;
+      default: p_force<SPH>(A, I.a, sm.list); break;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (t == 0) {
+      __hip_atomic_fetch_add(&A->arrive[I.box * kPhases + I.phase], 1, __ATOMIC_RELEASE,
+                             __HIP_MEMORY_SCOPE_AGENT);
+      s_item = atomicAdd(A->head, 1);
+    }
+    __syncthreads();
+    it = __builtin_amdgcn_readfirstlane(s_item);
+  }
+}
+
+// Before a persistent step: clear the arrival counters and the queue counter
+// (a kernel, so that a captured graph holds no memset node) and advance the
+// force evaluation index k.
+__global__ void k_persist_prep(int32_t *arrive, int n, int32_t *head, unsigned long long *dk) {
+  for (int i = (int)threadIdx.x; i < n; i += (int)blockDim.x) arrive[i] = 0;
+  if (threadIdx.x == 0) {
+    *head = 0;
+    *dk += 1ull;
+  }
 }
 
 }  // namespace
@@ -1326,6 +1579,54 @@ hipError_t launch_profile(hipStream_t s, const KGeom &G, int64_t nf, const float
   if (nf <= 0) return hipSuccess;
   k_profile<<<grid_for(nf), kBlock, 0, s>>>(G, nf, pos4, vel4, axis, nbins, out);
   return hipGetLastError();
+}
+
+hipError_t launch_step_persistent(hipStream_t s, const PArgs *args, int nitems, int blocks,
+                                  int32_t *arrive, int narrive, int32_t *head,
+                                  unsigned long long *dk, int grid_f64, int ppt, int reflect,
+                                  int sph) {
+  if (nitems <= 0) return hipSuccess;
+  k_persist_prep<<<1, 256, 0, s>>>(arrive, narrive, head, dk);
+  const unsigned nb = (unsigned)std::max(1, std::min(nitems, blocks));
+#define DPD_PERSIST(T, P, R, S) k_step_persistent<T, P, R, S><<<nb, kBlock, 0, s>>>(args)
+#define DPD_PERSIST_S(T, P, R) \
+  if (sph) DPD_PERSIST(T, P, R, true); else DPD_PERSIST(T, P, R, false)
+#define DPD_PERSIST_R(T, P) \
+  if (reflect) { DPD_PERSIST_S(T, P, true); } else { DPD_PERSIST_S(T, P, false); }
+#define DPD_PERSIST_P(T) \
+  if (ppt == 1) { DPD_PERSIST_R(T, 1); } else { DPD_PERSIST_R(T, 2); }
+  if (grid_f64) {
+    DPD_PERSIST_P(double);
+  } else {
+    DPD_PERSIST_P(float);
+  }
+#undef DPD_PERSIST_P
+#undef DPD_PERSIST_R
+#undef DPD_PERSIST_S
+#undef DPD_PERSIST
+  return hipGetLastError();
+}
+
+namespace {
+template <typename T, int P, bool R, bool S>
+int occupancy_of() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_persistent<T, P, R, S>, kBlock, 0) !=
+      hipSuccess)
+    return -1;
+  return n;
+}
+template <typename T, int P>
+int occupancy_rs(int reflect, int sph) {
+  if (reflect) return sph ? occupancy_of<T, P, true, true>() : occupancy_of<T, P, true, false>();
+  return sph ? occupancy_of<T, P, false, true>() : occupancy_of<T, P, false, false>();
+}
+}  // namespace
+
+int persistent_blocks_per_cu(int ppt, int grid_f64, int reflect, int sph) {
+  if (grid_f64)
+    return ppt == 1 ? occupancy_rs<double, 1>(reflect, sph) : occupancy_rs<double, 2>(reflect, sph);
+  return ppt == 1 ? occupancy_rs<float, 1>(reflect, sph) : occupancy_rs<float, 2>(reflect, sph);
 }
 
 hipError_t launch_fill_zero(hipStream_t s, void *p, size_t bytes) {

@@ -219,7 +219,10 @@ def main():
     nf, nw = system.n_fluid, system.n_wall
     b_alg = nf * (72 + 16 + 28 + 12 + 1) + 16 * nw + 8 * ncell + (
         64 if system.phi.dtype == np.float64 else 32) * lookups
-    step_gbs = b_alg / (ms_per_step * 1e-3) / 1e9
+    # the step's duration from the same HIP-event pass: the sum of its
+    # kernels' event-timed launches per step
+    step_event_ms = sum(ms for ms, c in kt.values() if c) / max(args.timing_steps, 1)
+    step_gbs = b_alg / (step_event_ms * 1e-3) / 1e9
     # the pair force's own algorithmic bytes: positions, predicted velocities
     # and gids of fluid and walls read once, the state written once in cell
     # order (r, v, f: 48 B per fluid particle), the merged cell runs read once
@@ -318,7 +321,11 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "step (integrate + cell list + pair_force)",
                      "achieved": step_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": step_gbs / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes": b_alg, "avg_step_ms": ms_per_step},
+                     "algorithmic_bytes": b_alg, "avg_step_ms": step_event_ms,
+                     "avg_step_ms_from": "HIP events on the library stream, sum of the "
+                                         "step's kernels over %d steps" % args.timing_steps,
+                     "traffic_GBs": (traffic / (step_event_ms * 1e-3) / 1e9
+                                     if traffic else None)},
         "pair_force": {"avg_ms_per_step": force_ms, "launches_per_step": force_launches_per_step,
                        "pairs_ff": cnt["pairs_ff"], "pairs_fw": cnt["pairs_fw"],
                        "candidates_ff_half": cnt["candidates_ff_half"],

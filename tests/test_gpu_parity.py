@@ -102,6 +102,27 @@ def test_initial_forces_cells_pairs(dpd, oracle_lib, name):
     sim.close()
 
 
+def _rounding_reach(s):
+    """How far apart the kernel's and the oracle's reflected positions (Eq.
+    17) can be: the kernel rounds x* - k2 u to FP32 once (half a unit in the
+    last place of the largest edge per axis; k2's own FP32 error moves a
+    step of at most 0.1 by ~1e-8), the oracle keeps FP64.  Returns that
+    distance and the change it can make to phi (the trilinear field's
+    largest slope times it, plus three FP32 roundings of a value <= 1)."""
+    ulp = float(np.spacing(np.float32(max(s.L))))
+    dx = np.sqrt(3.0) * (0.5 * ulp + 1e-8)
+    phi = np.asarray(s.phi, np.float64)
+    g2 = 0.0
+    for axis, h in ((2, s.h[0]), (1, s.h[1]), (0, s.h[2])):
+        g2 += (np.abs(np.roll(phi, -1, axis=axis) - phi).max() / h) ** 2
+    return dx, np.sqrt(g2) * dx + 2e-7
+
+
+def _min_image(d, L):
+    d = np.abs(d)
+    return np.minimum(d, np.asarray(L)[None, :] - d)
+
+
 def _one_step_compare(dpd, oracle_lib, s, nsteps_before=0, sim=None, r=0):
     """One step of the GPU path from a common FP32 snapshot against the
     oracle.  With `sim` (a batch context holding s as box r) the snapshot is
@@ -128,20 +149,29 @@ def _one_step_compare(dpd, oracle_lib, s, nsteps_before=0, sim=None, r=0):
     f_gpu = sim.forces(r).cpu().numpy().astype(np.float64)
     fluid_g = by_gid(o, s.type) == 0
     ev_or_g = by_gid(o, ev_or)
-    # events: bounce or not, bit-exact; the code (1 vs 2) outside the band
-    # where the fallback test phi(r_bb) < 0 sits within rounding of zero
+    # events: bounce or not, bit-exact; the code (1 vs 2) wherever the
+    # fallback test phi(r_bb) < 0 lies beyond the reach of the FP32 rounding
+    # of the reflected position
+    dx, dphi = _rounding_reach(s)
     assert np.array_equal(st["events"] > 0, ev_or_g > 0)
     both = (st["events"] > 0) & (ev_or_g > 0)
     if both.any():
         x_or = by_gid(o, o.r)[both]
         phib = trilinear_f64(s.phi, s.h, x_or)
-        clear = np.abs(phib) > 1e-5
+        clear = np.abs(phib) > dphi
         assert np.array_equal(st["events"][both][clear], ev_or_g[both][clear])
+        say("  events %d, codes compared %d (band %.2e)" % (both.sum(), clear.sum(), dphi))
     cells_or = by_gid(o, o.cells())
     bounced = ev_or_g > 0
     assert np.array_equal(st["cell_of"][~bounced], cells_or[~bounced])
-    mism = np.nonzero(st["cell_of"][bounced] != cells_or[bounced])[0]
-    assert len(mism) <= max(1, bounced.sum() // 1000)
+    # a bounced particle's cell may differ only where its position lies
+    # within that rounding of a cell face
+    mism = np.nonzero(st["cell_of"] != cells_or)[0]
+    if len(mism):
+        x_m = by_gid(o, o.r)[mism]
+        w = np.asarray(s.L) / np.floor(np.asarray(s.L) / s.params["rc"])
+        face = np.abs(x_m / w[None, :] - np.round(x_m / w[None, :])) * w[None, :]
+        assert np.all(face.min(axis=1) <= dx), face.min(axis=1)
     # positions and velocities
     r_or = by_gid(o, o.r)
     d = np.abs(st["pos"].astype(np.float64) - r_or)
@@ -158,32 +188,41 @@ def _one_step_compare(dpd, oracle_lib, s, nsteps_before=0, sim=None, r=0):
     # decision-form drift, identical to the GPU's by construction).
     f_sh = by_gid(o, o.forces(k=o.k, r=o.xs.astype(np.float64), vt=o.vt, xs=o.xs))
     err = np.abs(f_gpu - f_sh).max(axis=1)
+    # every fluid particle at the same bar, bounced ones and their partners
+    # included (their reflected positions differ by the FP32 rounding of Eq.
+    # 17, which moves a pair force by ~1e-4 absolute: a few 1e-6 F_scale)
     near = np.zeros(len(err), bool)
     if bounced.any():
-        # particles that bounced, and their partners, see a reflected
-        # position computed in FP32 vs FP64 (Eq. 17): checked at 1e-4
         pr = o.pairs().astype(np.int64)
         hit = bounced[pr[:, 0]] | bounced[pr[:, 1]]
         near[pr[hit, 0]] = True
         near[pr[hit, 1]] = True
         near |= bounced
-    strict = fluid_g & ~near
-    assert err[strict].max() <= FORCE_TOL * scale, (err[strict].max(), scale)
+    assert err[fluid_g].max() <= FORCE_TOL * scale, (err[fluid_g].max(), scale)
     if (fluid_g & near).any():
-        assert err[fluid_g & near].max() <= 1e-4 * scale
+        say("  next to bounces: max |df| / F_scale %.2e (elsewhere %.2e)"
+            % (err[fluid_g & near].max() / scale, err[fluid_g & ~near].max() / scale))
     # and against the FP64 trajectory within the drift rounding
     assert np.abs(f_gpu - f_or)[fluid_g].max() <= 2e-4 * scale
-    # interacting pairs after the step, except pairs of a particle whose
-    # bounced position differs from the oracle's by rounding
+    # interacting pairs after the step, bit-exact except pairs of a bounced
+    # particle whose FP64 distance lies within twice that rounding of rc
     gp = sim.pairs(r)
     op = o.pairs()
     if not bounced.any():
         assert np.array_equal(sorted_pairs(gp), sorted_pairs(op))
     else:
-        gpi, opi = gp.astype(np.int64), op.astype(np.int64)
-        keep_g = ~(bounced[gpi[:, 0]] | bounced[gpi[:, 1]])
-        keep_o = ~(bounced[opi[:, 0]] | bounced[opi[:, 1]])
-        assert np.array_equal(sorted_pairs(gp[keep_g]), sorted_pairs(op[keep_o]))
+        rc = s.params["rc"]
+
+        def edge(pairs):
+            pi = pairs.astype(np.int64)
+            b = bounced[pi[:, 0]] | bounced[pi[:, 1]]
+            dist = np.sqrt((_min_image(r_or[pi[:, 0]] - r_or[pi[:, 1]], s.L) ** 2).sum(1))
+            return b & (np.abs(dist - rc) <= 2 * dx)
+
+        eg, eo = edge(gp), edge(op)
+        say("  pairs: %d vs %d, %d / %d at the cutoff's rounding edge"
+            % (len(gp), len(op), eg.sum(), eo.sum()))
+        assert np.array_equal(sorted_pairs(gp[~eg]), sorted_pairs(op[~eo]))
     n_events = int((ev_or_g > 0).sum())
     if own:
         sim.close()
@@ -263,49 +302,6 @@ def test_profile_observable(dpd, oracle_lib):
     assert np.allclose(prof[:, 1], ref["sum_vx"], atol=1e-4)
     assert np.allclose(prof[:, 4], ref["sum_v2"], rtol=1e-6, atol=1e-3)
     sim.close()
-
-
-def test_statistical_parity_plane_poiseuille(dpd, oracle_lib):
-    """The 10^3 slab started from rest under g_x = 0.02, 16 independent seeds
-    on both sides: per seed, the binned mean v_x and density over steps
-    200-600; the paired GPU-minus-oracle differences have zero mean within
-    their standard error in every bin (max |t| < 4.5 over 20 bins, and the
-    mean t^2 near 1)."""
-    nb = 10
-    res_o, res_g = [], []
-
-    def bins(z, vx):
-        b = np.clip(np.floor((np.mod(z, 10.0) - 1.5) / 0.7).astype(int), 0, nb - 1)
-        return np.bincount(b, minlength=nb), np.bincount(b, weights=vx, minlength=nb)
-
-    for seed in range(16):
-        s = workloads.slab_system(seed_fluid=100 + seed, seed_wall=200 + seed,
-                                  params=workloads.default_params(g=(0.02, 0, 0), seed=300 + seed))
-        fl = s.type == 0
-        gid_fluid = s.gid[fl]
-        o = oracle_lib.Oracle(s)
-        sim = dpd.Simulation(s)
-        o.step(200)
-        sim.step(200)
-        co = np.zeros(nb); vo = np.zeros(nb); cg = np.zeros(nb); vg = np.zeros(nb)
-        for _ in range(40):
-            o.step(10)
-            sim.step(10)
-            c1, v1 = bins(o.r[fl, 2], o.v[fl, 0])
-            co += c1; vo += v1
-            st = sim.state()
-            p = st["pos"].cpu().numpy()[gid_fluid]
-            v = st["vel"].cpu().numpy()[gid_fluid]
-            c2, v2 = bins(p[:, 2], v[:, 0])
-            cg += c2; vg += v2
-        sim.close()
-        res_o.append(np.concatenate([vo / co, co / 40]))
-        res_g.append(np.concatenate([vg / cg, cg / 40]))
-    d = np.array(res_g) - np.array(res_o)
-    tval = d.mean(0) / (d.std(0, ddof=1) / math.sqrt(len(d)))
-    say("paired t", np.round(tval, 2))
-    assert np.abs(tval).max() < 4.5
-    assert np.mean(tval ** 2) < 2.5
 
 
 def test_edge_cases(dpd, oracle_lib):

@@ -1292,7 +1292,9 @@ k_step_persistent(const PArgs *__restrict__ A) {
         const int need = A->need[dep];
         const int limit = A->spin_limit;
         int spins = 0;
-        while (__hip_atomic_load(&A->arrive[dep], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <
+        // relaxed loads while spinning (an acquire would invalidate this
+        // XCD's L2 on every iteration); the acquire fence follows the wait
+        while (__hip_atomic_load(&A->arrive[dep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
                need) {
           __builtin_amdgcn_s_sleep(4);
           if (++spins >= limit) {

@@ -4,7 +4,8 @@ the per-phase launches, through the C ABI.
 Bars: bit-identical state, events, cells and forces after 30 steps, for a
 batch of seven uneven boxes (direct launches and graph replay, and with the
 attractive-repulsive force), for a single box with a float64 phase field,
-and after switching back and forth mid-run; one timed launch per step; the
+for boxes whose cells span several scan chunks, and after switching back
+and forth mid-run; one timed launch per step; the
 contexts it does not serve (moving walls, the brick pair kernel) refused.
 """
 import sys
@@ -93,6 +94,20 @@ def test_single_box_float64_grid_and_switching(dpd):
     _same(_snap(mix, 0), _snap(ref, 0), "switching")
     ref.close()
     mix.close()
+
+
+def test_boxes_with_several_scan_chunks(dpd):
+    """Boxes of more than one scan chunk (4096 cells): a 24 x 16 x 24 curved
+    box (9216 cells, three chunks) alone and in a batch after a small box,
+    so chunk offsets inside a box and box offsets both enter the scan."""
+    big = workloads.sinusoid_cylinder_system(
+        L=(24.0, 16.0, 24.0), base=3.0, amp=1.5, radius=3.0, seed=77,
+        params=workloads.default_params(g=(0.02, 0, 0), seed=78, replica=1))
+    small = workloads.slab_system(seed_fluid=79, seed_wall=80, grid_dtype=np.float32,
+                                  params=workloads.default_params(seed=81))
+    say("multi-chunk boxes", big.n, small.n)
+    _compare(dpd, [big], 15, False, "one box, three chunks")
+    _compare(dpd, [small, big], 15, True, "batch with a three-chunk box")
 
 
 def test_one_timed_launch_per_step(dpd):

@@ -603,10 +603,8 @@ __device__ __forceinline__ Moved integrate_one(const KGeom &G, const KParams &P,
         by = x.y;
         bz = x.z;
         event = 2;
-        atomicAdd(&st->fallback, 1ull);
       } else {
         event = 1;
-        atomicAdd(&st->bounce, 1ull);
       }
       xs = bx;
       ys = by;
@@ -706,6 +704,19 @@ __device__ __forceinline__ void integrate_tile(
       cell_of[p[u]] = m[u].cell;
       rank_of[p[u]] = k;
     }
+  }
+  // event counts: one atomic per wavefront, after the stores (a per-lane
+  // atomic on the one counter word put its latency into the step's chain)
+  int nbounce = 0, nfall = 0;
+#pragma unroll
+  for (int u = 0; u < PPT; ++u) {
+    const int ev = a[u] ? __float_as_int(m[u].vt.w) : 0;
+    nbounce += __popcll(__ballot(ev == 1));
+    nfall += __popcll(__ballot(ev == 2));
+  }
+  if (__lane_id() == 0) {
+    if (nbounce) atomicAdd(&st->bounce, (unsigned long long)nbounce);
+    if (nfall) atomicAdd(&st->fallback, (unsigned long long)nfall);
   }
 }
 

@@ -231,10 +231,12 @@ int dpd_counters(dpd_ctx *ctx, int64_t *out);
  * When out is not NULL it receives, for the kernels named by
  * dpd_kernel_name(0..DPD_NUM_KERNELS-1), the summed milliseconds in out_ms
  * and the number of timed launches in out_launches ("scatter" also writes
- * the wall part of the merged cell runs; "step_persistent" is the one launch
- * of a step under dpd_use_persistent, which then replaces the five step
- * kernels).  Synchronises. */
-#define DPD_NUM_KERNELS 8
+ * the wall part of the merged cell runs; "pair_codes" writes the coarse
+ * position codes of the merged runs that the pair kernel's candidate
+ * pre-test reads; "step_persistent" is the one launch of a step under
+ * dpd_use_persistent, which then replaces the six step kernels).
+ * Synchronises. */
+#define DPD_NUM_KERNELS 9
 int dpd_kernel_times(dpd_ctx *ctx, int32_t enable, double *out_ms, int64_t *out_launches);
 const char *dpd_kernel_name(int32_t i);
 

@@ -26,7 +26,7 @@ DPD_E_STATE = -5
 DPD_FLAG_NO_MASK = 1
 DPD_FLAG_SPECULAR = 2
 DPD_FLAG_SPH = 4
-DPD_NUM_KERNELS = 8
+DPD_NUM_KERNELS = 9
 
 _ERRNAMES = {DPD_E_INVAL: "DPD_E_INVAL", DPD_E_NOMEM: "DPD_E_NOMEM",
              DPD_E_DEVICE: "DPD_E_DEVICE", DPD_E_UNSTABLE: "DPD_E_UNSTABLE",

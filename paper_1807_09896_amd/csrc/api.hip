@@ -34,12 +34,12 @@ namespace {
 thread_local std::string g_create_error = "no error";
 
 enum Kernel { K_INTEGRATE = 0, K_SCAN_REDUCE, K_PERSIST, K_SCAN_DOWN, K_SCATTER, K_SORT,
-              K_FORCE, K_OTHER };
+              K_FORCE, K_OTHER, K_CODES };
 // "step_persistent": the one launch of a persistent step (dpd_use_persistent),
 // which does the work of all the others.
 const char *kKernelNames[DPD_NUM_KERNELS] = {"integrate_reflect_bin", "scan_reduce",
                                              "step_persistent", "scan_down", "scatter",
-                                             "sort_cells", "pair_force", "other"};
+                                             "sort_cells", "pair_force", "other", "pair_codes"};
 
 struct TimedLaunch {
   int kernel;
@@ -116,6 +116,7 @@ struct dpd_ctx {
   int32_t *wcstart = nullptr;   // exclusive scan of wall counts per cell (static)
   int32_t *wcell = nullptr;     // global cell of each cell-sorted wall (static)
   int32_t *idx_all = nullptr;   // merged per-cell runs: walls (NF + w), then fluid
+  uint32_t *cq = nullptr;       // coarse position codes of the merged runs, 2 words each
   // moving walls: re-sorted by cell every step (moved copy, velocities,
   // cells, ranks, per-cell counts)
   bool moving = false;
@@ -463,6 +464,7 @@ int build_persistent(dpd_ctx *c) {
     A.fluid_off = c->fluid_off;
     A.idx = c->idx;
     A.idx_all = c->idx_all;
+    A.cq = c->cq;
     A.pad = (int32_t)(c->NF + c->NW);
     A.ncell_all = (int32_t)c->NCELL;
     A.pos_out = c->pos[b];
@@ -552,11 +554,13 @@ int bin_all(dpd_ctx *c, hipStream_t s) {
 }
 
 // Cell list of the fluid at its current positions and the merged per-cell
-// runs.  key4: sort each cell by gid (a state loaded from outside) instead of
-// by storage index; bump: the force evaluation index advances in the same
-// launches.
+// runs, with the runs' coarse position codes.  key4: sort each cell by gid (a
+// state loaded from outside) instead of by storage index; bump: the force
+// evaluation index advances in the same launches; codes = false: positions
+// elsewhere than pos[cur] (the adjoint window's), whose pair walk does not
+// read the codes.
 int scan_scatter_sort(dpd_ctx *c, hipStream_t s, const float4 *key4 = nullptr,
-                      unsigned long long *bump = nullptr) {
+                      unsigned long long *bump = nullptr, bool codes = true) {
   HIP_TRY(c, timed(c, s, K_SCAN_REDUCE, [&] {
             return dpd::launch_scan_reduce(s, c->NCELL, c->count, c->bsum);
           }));
@@ -573,6 +577,10 @@ int scan_scatter_sort(dpd_ctx *c, hipStream_t s, const float4 *key4 = nullptr,
             return dpd::launch_sort_cells(s, c->NCELL, c->cstart, c->idx, key4, c->fluid_off,
                                           c->idx_all);
           }));
+  if (codes)
+    HIP_TRY(c, timed(c, s, K_CODES, [&] {
+              return dpd::launch_quant_runs(s, c->NF + c->NW, c->idx_all, c->pos[c->cur], c->cq);
+            }));
   return DPD_OK;
 }
 
@@ -584,8 +592,8 @@ int force_pass(dpd_ctx *c, hipStream_t s, int init) {
               return dpd::launch_force(s, c->fblock, c->boxes, c->otiles, c->n_otiles, c->NF,
                                        (int32_t)(c->NF + c->NW), (int32_t)c->NCELL, init,
                                        c->pos[a], c->vt, c->vel[a], c->frc[a], c->idx,
-                                       c->idx_all, c->start_all, c->pos[b], c->vel[b], c->frc[b],
-                                       c->dk, c->status, c->sph ? 1 : 0);
+                                       c->idx_all, c->start_all, c->cq, c->pos[b], c->vel[b],
+                                       c->frc[b], c->dk, c->status, c->sph ? 1 : 0);
             }));
   if (c->nbricks > 0)
     HIP_TRY(c, timed(c, s, K_FORCE, [&] {
@@ -1004,6 +1012,7 @@ int create_impl(int32_t nbox, const dpd_box *boxes, const dpd_particles *parts,
   c->wcstart = (int32_t *)dalloc(c, 4 * (ncell + 1));
   c->wcell = (int32_t *)dalloc(c, 4 * nw);
   c->idx_all = (int32_t *)dalloc(c, 4 * (nf + nw + dpd::kIdxSlack));
+  c->cq = (uint32_t *)dalloc(c, 8 * (nf + nw + dpd::kIdxSlack));
   for (const Replica &p : c->rep) {
     c->moving = c->moving || p.moving;
     c->reflect = c->reflect || p.P.reflect != 0;
@@ -1031,7 +1040,7 @@ int create_impl(int32_t nbox, const dpd_box *boxes, const dpd_particles *parts,
     if (!c->pos[b] || !c->vel[b] || !c->frc[b])
       return bail(fail(c, DPD_E_NOMEM, "device allocation failed"));
   if (!c->vt || !c->cell_of || !c->rank_of || !c->idx || !c->count || !c->cstart || !c->bsum ||
-      !c->wcstart || !c->wcell || !c->idx_all || !c->start_all || !c->fluid_off ||
+      !c->wcstart || !c->wcell || !c->idx_all || !c->cq || !c->start_all || !c->fluid_off ||
       !c->grid || !c->quad ||
       !c->bits || !c->boxes || !c->status || !c->dk || !c->pair_counter)
     return bail(fail(c, DPD_E_NOMEM, "device allocation failed"));
@@ -1338,7 +1347,7 @@ int backward_step(dpd_ctx *c, const float4 *x, uint64_t t, const float4 *A, floa
                                    x + 2 * NF, c->vt, c->cell_of, c->rank_of, c->count, c->bits,
                                    c->use_mask, c->quad, c->grid_f64, c->status, NF, c->wcstart,
                                    0));
-  int rc = scan_scatter_sort(c, s);
+  int rc = scan_scatter_sort(c, s, nullptr, nullptr, false);
   if (rc) return rc;
   HIP_TRY(c, dpd::launch_adj_prep(s, c->boxes, NF, 0, c->idx, W.wpos, c->vt, A, A + NF,
                                   A + 2 * NF, W.lw, W.axis, W.nbins, W.scale, rn, vn, fbar,
@@ -1402,7 +1411,7 @@ int backward_impl(dpd_ctx *c, const double *dldp, double *grads, double *dphi) {
     HIP_TRY(c, hipMemcpyAsync(W.wpos, x0, 16 * (size_t)NF, hipMemcpyDeviceToDevice, s));
     HIP_TRY(c, dpd::launch_vt_from_v(s, NF, x0 + NF, c->vt));
     HIP_TRY(c, dpd::launch_bin(s, p.G, p.co, NF, W.wpos, c->cell_of, c->rank_of, c->count));
-    rc = scan_scatter_sort(c, s);
+    rc = scan_scatter_sort(c, s, nullptr, nullptr, false);
     if (!rc) {
       HIP_TRY(c, dpd::launch_adj_prep(s, c->boxes, NF, 1, c->idx, W.wpos, c->vt, A, A + NF,
                                       A + 2 * NF, W.lw, W.axis, W.nbins, W.scale, nullptr,

@@ -221,6 +221,55 @@ __device__ __forceinline__ float sep_d(const SepAxis &s, float xj) {
   return sub_nc(s.a, sub_nc(xj, s.b));
 }
 
+// Coarse positions for the candidate pre-test: q = rint(256 x) modulo 2^16
+// per axis (256 x is exact in FP32, so |256 x - q| <= 1/2 before the
+// modulo), two words per particle: x | y << 16, then z.  Differences of
+// two such codes, taken modulo 2^16 and read as signed, are exact for any
+// two points less than 128 apart, whatever the box size.  With a periodic
+// image shift s L rounded the same way, the code difference vector dq lies
+// within 3/2 per axis of 256 d, d the exact image difference, so
+// |dq| <= 256 |d| + 1.5 sqrt(3): a candidate with |dq| beyond
+// 256 rc (1 + 1e-5) + 2.6 is out of range in the exact FP32 decision too
+// (whose rounding of r^2 is a few 1e-7).
+constexpr float kQScale = 256.f;
+typedef unsigned short u16x2_t __attribute__((ext_vector_type(2)));
+typedef short i16x2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t qcode(float x) {
+  return (uint32_t)__float2int_rn(x * kQScale) & 0xFFFFu;
+}
+
+__device__ __forceinline__ uint2 qcode3(float x, float y, float z) {
+  return make_uint2(qcode(x) | (qcode(y) << 16), qcode(z));
+}
+
+// |dq|^2 of a candidate's code (wxy, wz) against the lane's shifted code
+// (qxy, qz): signed 16-bit differences, squared and summed in 32 bits
+// (below 3 x 2^30, so the unsigned reading is exact).
+__device__ __forceinline__ uint32_t qdist2(uint32_t wxy, uint32_t wz, uint32_t qxy, uint32_t qz) {
+  const i16x2_t dxy =
+      __builtin_bit_cast(i16x2_t, __builtin_bit_cast(u16x2_t, wxy) - __builtin_bit_cast(u16x2_t, qxy));
+  const i16x2_t dz =
+      __builtin_bit_cast(i16x2_t, __builtin_bit_cast(u16x2_t, wz) - __builtin_bit_cast(u16x2_t, qz));
+  return (uint32_t)__builtin_amdgcn_sdot2(dxy, dxy, __builtin_amdgcn_sdot2(dz, dz, 0, false), false);
+}
+
+// Threshold of the pre-test for cutoff^2 rc2: keep a candidate iff
+// qdist2 <= qthresh.  Cutoffs of 120 and more (where a hit's code
+// difference could leave the 16-bit range) keep every candidate.
+__device__ __forceinline__ uint32_t qthresh(float rc2) {
+  if (!(rc2 < 14400.f)) return 0xFFFFFFFFu;
+  const float r = sqrtf(rc2) * (kQScale * 1.00001f) + 2.6f;
+  return (uint32_t)(r * r);
+}
+
+// One axis of the lane's own code with the image shift sL of a neighbour row
+// applied (16 bits).
+__device__ __forceinline__ uint32_t qshift(float x, float sL) {
+  return ((uint32_t)__float2int_rn(x * kQScale) - (uint32_t)__float2int_rn(sL * kQScale)) &
+         0xFFFFu;
+}
+
 // ---------------------------------------------------------------------------
 // Phase field: trilinear interpolation of the periodic node grid (decision
 // form lerp(a, b, t) = fl(a + fl(t fl(b - a))): four lerps in x, two in y,

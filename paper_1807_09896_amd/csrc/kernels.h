@@ -50,6 +50,11 @@ hipError_t launch_scatter(hipStream_t s, int64_t n, const int32_t *cell_of,
                           int32_t *idx_all = nullptr, unsigned long long *dk = nullptr);
 hipError_t launch_sort_cells(hipStream_t s, int64_t ncell, const int32_t *start, int32_t *idx,
                              const float4 *key4, const int32_t *fluid_off, int32_t *idx_all);
+// Coarse position codes of the merged runs, cq[t] from pos4[idx_all[t]] for
+// t < n (two words per entry), which the pair kernel's candidate pre-test
+// reads; n = NF + NW, after the scatter and sort.
+hipError_t launch_quant_runs(hipStream_t s, int64_t n, const int32_t *idx_all,
+                             const float4 *pos4, uint32_t *cq);
 
 
 // Write the pad entry (far-away position, zero velocity) at pos4[0], vt4[0];
@@ -107,6 +112,7 @@ struct PArgs {
   int64_t NF, NW;
   const int32_t *wcstart, *wcell;
   int32_t *cstart, *bsum, *start_all, *fluid_off, *idx, *idx_all;
+  uint32_t *cq;
   int32_t pad, ncell_all;
   float4 *pos_out, *vel_out, *frc_out;
   const unsigned long long *dk;
@@ -152,7 +158,7 @@ hipError_t launch_force(hipStream_t s, int block, const Box *boxes, const Tile *
                         int ntiles, int64_t NF, int32_t pad, int32_t ncell_all, int init,
                         const float4 *pos4, const float4 *vt4, const float4 *vel4,
                         const float4 *frc4, const int32_t *idx, const int32_t *idx_all,
-                        const int32_t *start_all,
+                        const int32_t *start_all, const uint32_t *cq,
                         float4 *pos_out, float4 *vel_out, float4 *frc_out,
                         const unsigned long long *dk, Status *st, int sph);
 

@@ -371,6 +371,16 @@ __global__ void k_sort_cells(int64_t ncell, const int32_t *__restrict__ start,
   sort_cell<BY_GID>(c, start, idx, key4, fluid_off, idx_all);
 }
 
+// Coarse codes of the merged runs, cq[t] = qcode3(pos4[idx_all[t]]): one
+// thread per entry, so that the index reads and code writes coalesce.
+__global__ void k_quant_runs(int64_t n, const int32_t *__restrict__ idx_all,
+                             const float4 *__restrict__ pos4, uint2 *__restrict__ cq) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const float4 x = pos4[idx_all[t]];
+  cq[t] = qcode3(x.x, x.y, x.z);
+}
+
 // The pad entry after fluid and walls: a position far outside the box, so
 // that it never tests as a neighbour; the spare run-array entries after the
 // last run name it.
@@ -832,13 +842,18 @@ __device__ __forceinline__ void add_pair(Acc &acc, float dx, float dy, float dz,
 }
 
 // Tile tid by one block of BS threads; list: kListCap x BS words of LDS.
-template <bool INIT, int BS, bool SPH>
+// QF: the walk tests candidates on their coarse codes (cq, two words per
+// merged-run entry, in run order) and lists every candidate the bound keeps;
+// the pair pass then takes the exact FP32 decision, so the pairs summed and
+// their order are those of the exact walk.
+template <bool INIT, int BS, bool SPH, bool QF>
 __device__ __forceinline__ void force_tile(
     int tid, uint32_t *list, const Box *__restrict__ boxes, const Tile *__restrict__ tiles,
     int64_t NF, int32_t pad, int32_t ncell_all, const float4 *__restrict__ pos4,
     const float4 *__restrict__ vt4, const float4 *__restrict__ vel4,
     const float4 *__restrict__ frc4, const int32_t *__restrict__ idx,
     const int32_t *__restrict__ idx_all, const int32_t *__restrict__ start_all,
+    const uint32_t *__restrict__ cq,
     float4 *__restrict__ pos_out, float4 *__restrict__ vel_out, float4 *__restrict__ frc_out,
     const unsigned long long *__restrict__ dk, Status *st) {
   const Tile tile = tiles[tid];
@@ -865,6 +880,8 @@ __device__ __forceinline__ void force_tile(
   const Records16 posr(pos4, pad + 1), vtr(vt4, pad + 1);
   const Ints4 runs(idx_all, pad + kIdxSlack);
   const Ints4 starts(start_all, ncell_all + 1 + kStartSlack);
+  const Ints4 codes((const int32_t *)cq, QF ? 2 * (pad + kIdxSlack) : 0);
+  const uint32_t qth = qthresh(P.rc2);
   // this lane's list column as LDS byte offsets: entry q at lane0 + q * BS * 4
   char *const lds = (char *)list;
   const uint32_t lane0 = threadIdx.x * 4u;
@@ -886,8 +903,15 @@ __device__ __forceinline__ void force_tile(
       const float r2 = dx * dx + dy * dy + dz * dz;
       const bool wall = (int64_t)j >= NF;
       const float a = wall ? P.a_fw : P.a_ff;
-      add_pair<SPH>(acc, dx, dy, dz, r2, vti.x - vtj.x, vti.y - vtj.y, vti.z - vtj.z, a, wall, P,
-                    gi, __float_as_uint(pj.w), klo, khi);
+      bool take = true;
+      if (QF) {
+        // the exact decision of the walk (the listed candidates are a superset)
+        const float r2d = pair_r2(dx, dy, dz);
+        take = r2d < P.rc2 && r2d > 0.0f;
+      }
+      if (take)
+        add_pair<SPH>(acc, dx, dy, dz, r2, vti.x - vtj.x, vti.y - vtj.y, vti.z - vtj.z, a, wall,
+                      P, gi, __float_as_uint(pj.w), klo, khi);
       j = jn;
       pj = pjn;
       vtj = vtjn;
@@ -900,7 +924,7 @@ __device__ __forceinline__ void force_tile(
   // run are read (other cells' entries, or the pad) but never listed.
   // Phase B runs when a lane's list could overflow in the next pass.
   auto walk = [&](int t, int t_end, int tb, int tb_end, SepAxis ax, SepAxis axb, SepAxis ay,
-                  SepAxis az) {
+                  SepAxis az, uint32_t qa, uint32_t qb, uint32_t qz) {
     {
       const bool sw = t >= t_end;
       t = sw ? tb : t;
@@ -908,22 +932,38 @@ __device__ __forceinline__ void force_tile(
       tb = sw ? tb_end : tb;
       ax.a = sw ? axb.a : ax.a;
       ax.b = sw ? axb.b : ax.b;
+      qa = sw ? qb : qa;
     }
     for (;;) {
       while (wave_any(t < t_end) && !wave_any(tail > full)) {
         const int rem = t_end - t;
         int jb[kBatch];
         runs.load(t, jb);
-        float4 pb[kBatch];
+        if (QF) {
+          int w[2 * kBatch];
+          codes.load(2 * t, w);
+          codes.load(2 * t + 4, w + 4);
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) pb[u] = posr[jb[u]];
+          for (int u = 0; u < kBatch; ++u) {
+            const bool keep =
+                qdist2((uint32_t)w[2 * u], (uint32_t)w[2 * u + 1], qa, qz) <= qth && jb[u] != i &&
+                u < rem;
+            *(int *)(lds + tail) = jb[u];
+            tail += keep ? (uint32_t)(BS * 4) : 0u;
+          }
+        } else {
+          float4 pb[kBatch];
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-          const float r2 = pair_r2(sep_d(ax, pb[u].x), sep_d(ay, pb[u].y), sep_d(az, pb[u].z));
-          // r2 > 0 drops i itself (and coincident particles, whose force is 0)
-          const bool hit = r2 < P.rc2 && r2 > 0.0f && u < rem;
-          *(int *)(lds + tail) = jb[u];
-          tail += hit ? (uint32_t)(BS * 4) : 0u;
+          for (int u = 0; u < kBatch; ++u) pb[u] = posr[jb[u]];
+#pragma unroll
+          for (int u = 0; u < kBatch; ++u) {
+            const float r2 =
+                pair_r2(sep_d(ax, pb[u].x), sep_d(ay, pb[u].y), sep_d(az, pb[u].z));
+            // r2 > 0 drops i itself (and coincident particles, whose force is 0)
+            const bool hit = r2 < P.rc2 && r2 > 0.0f && u < rem;
+            *(int *)(lds + tail) = jb[u];
+            tail += hit ? (uint32_t)(BS * 4) : 0u;
+          }
         }
         t = rem > 0 ? t + kBatch : t;
         const bool sw = t >= t_end && tb < tb_end;
@@ -932,6 +972,7 @@ __device__ __forceinline__ void force_tile(
         tb = sw ? tb_end : tb;
         ax.a = sw ? axb.a : ax.a;
         ax.b = sw ? axb.b : ax.b;
+        qa = sw ? qb : qa;
       }
       if (!wave_any(t < t_end)) break;
       flush();
@@ -945,12 +986,14 @@ __device__ __forceinline__ void force_tile(
     if (qz < 0) { qz += nz; sz = -G.L[2]; }
     else if (qz >= nz) { qz -= nz; sz = G.L[2]; }
     const SepAxis az = sep_axis(pi.z, sz);
+    const uint32_t cz_code = QF ? qshift(pi.z, sz) : 0u;
     for (int oy = -1; oy <= 1; ++oy) {
       int qy = cy + oy;
       float sy = 0.f;
       if (qy < 0) { qy += ny; sy = -G.L[1]; }
       else if (qy >= ny) { qy -= ny; sy = G.L[1]; }
       const SepAxis ay = sep_axis(pi.y, sy);
+      const uint32_t cy_code = QF ? qshift(pi.y, sy) << 16 : 0u;
       // the row's x-neighbours [cx-1, cx+1] as run A, plus run B where the
       // row wraps (cell nx-1 seen across the left edge, then cells 0 and 1;
       // or cells nx-2 and nx-1, then cell 0 seen across the right edge)
@@ -969,7 +1012,9 @@ __device__ __forceinline__ void force_tile(
       }
       const float sxa = left ? -G.L[0] : 0.f, sxb = right ? G.L[0] : 0.f;
       const SepAxis ax = sep_axis(pi.x, sxa), axb = sep_axis(pi.x, sxb);
-      walk(ta, ta_end, tb, tb_end, ax, axb, ay, az);
+      const uint32_t qa = QF ? (qshift(pi.x, sxa) | cy_code) : 0u;
+      const uint32_t qb = QF ? (qshift(pi.x, sxb) | cy_code) : 0u;
+      walk(ta, ta_end, tb, tb_end, ax, axb, ay, az, qa, qb, cz_code);
     }
   }
   flush();
@@ -1003,13 +1048,15 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_
     const float4 *__restrict__ vt4, const float4 *__restrict__ vel4,
     const float4 *__restrict__ frc4, const int32_t *__restrict__ idx,
     const int32_t *__restrict__ idx_all, const int32_t *__restrict__ start_all,
+    const uint32_t *__restrict__ cq,
     float4 *__restrict__ pos_out, float4 *__restrict__ vel_out, float4 *__restrict__ frc_out,
     const unsigned long long *__restrict__ dk, Status *st) {
   __shared__ uint32_t list[kListCap * BS];
   const int tid = xcd_block();
   if (tid >= ntiles) return;
-  force_tile<INIT, BS, SPH>(tid, list, boxes, tiles, NF, pad, ncell_all, pos4, vt4, vel4, frc4,
-                            idx, idx_all, start_all, pos_out, vel_out, frc_out, dk, st);
+  force_tile<INIT, BS, SPH, true>(tid, list, boxes, tiles, NF, pad, ncell_all, pos4, vt4, vel4,
+                                  frc4, idx, idx_all, start_all, cq, pos_out, vel_out, frc_out,
+                                  dk, st);
 }
 
 // Interacting pairs with the same decision as the force kernel.  Each thread
@@ -1250,6 +1297,14 @@ __device__ __attribute__((noinline)) void p_sort(const PArgs *__restrict__ A0, i
   const int a = uniform_int(a0), b = uniform_int(b0);
   for (int64_t c = (int64_t)a + threadIdx.x; c < (int64_t)b; c += kBlock)
     sort_cell<false>(c, A->cstart, A->idx, nullptr, A->fluid_off, A->idx_all);
+  // the coarse codes of the merged-run entries of these cells (walls from
+  // the scatter phase, fluid from the loop above)
+  __syncthreads();
+  const int t0 = uniform_int(A->start_all[a]), t1 = uniform_int(A->start_all[b]);
+  for (int t = t0 + (int)threadIdx.x; t < t1; t += kBlock) {
+    const float4 x = A->pos4[A->idx_all[t]];
+    ((uint2 *)A->cq)[t] = qcode3(x.x, x.y, x.z);
+  }
 }
 
 template <bool SPH>
@@ -1258,9 +1313,10 @@ __device__ __attribute__((noinline)) void p_force(const PArgs *__restrict__ A0, 
   const ArgsPtr A = uniform_args(A0);
   const int tile = uniform_int(tile0);
   uint32_t *list = lds_ptr(list0);
-  force_tile<false, kBlock, SPH>(tile, list, A->boxes, A->ftiles, A->NF, A->pad, A->ncell_all,
-                                 A->pos4, A->vt4, A->vel4, A->frc4, A->idx, A->idx_all,
-                                 A->start_all, A->pos_out, A->vel_out, A->frc_out, A->dk, A->st);
+  force_tile<false, kBlock, SPH, true>(tile, list, A->boxes, A->ftiles, A->NF, A->pad,
+                                       A->ncell_all, A->pos4, A->vt4, A->vel4, A->frc4, A->idx,
+                                       A->idx_all, A->start_all, A->cq, A->pos_out, A->vel_out,
+                                       A->frc_out, A->dk, A->st);
 }
 
 template <typename T, int PPT, bool REFLECT, bool SPH>
@@ -1394,6 +1450,14 @@ hipError_t launch_scatter(hipStream_t s, int64_t n, const int32_t *cell_of,
   if (total <= 0) return hipSuccess;
   k_scatter<<<grid_for(total), kBlock, 0, s>>>(n, cell_of, rank_of, start, idx, nw, wcell, wstart,
                                                start_all, idx_all, dk);
+  return hipGetLastError();
+}
+
+hipError_t launch_quant_runs(hipStream_t s, int64_t n, const int32_t *idx_all,
+                             const float4 *pos4, uint32_t *cq) {
+  if (n <= 0) return hipSuccess;
+  if (!idx_all || !pos4 || !cq) return hipErrorInvalidValue;
+  k_quant_runs<<<grid_for(n), kBlock, 0, s>>>(n, idx_all, pos4, (uint2 *)cq);
   return hipGetLastError();
 }
 
@@ -1531,14 +1595,16 @@ hipError_t launch_force(hipStream_t s, int block, const Box *boxes, const Tile *
                         const float4 *pos4,
                         const float4 *vt4, const float4 *vel4, const float4 *frc4,
                         const int32_t *idx, const int32_t *idx_all, const int32_t *start_all,
+                        const uint32_t *cq,
                         float4 *pos_out, float4 *vel_out, float4 *frc_out,
                         const unsigned long long *dk, Status *st, int sph) {
   if (ntiles <= 0) return hipSuccess;
+  if (!cq) return hipErrorInvalidValue;
   const unsigned nb = (unsigned)(((ntiles + 7) / 8) * 8);
 #define DPD_FORCE(I, BS, S)                                                                      \
   k_force<I, BS, S><<<nb, BS, 0, s>>>(boxes, tiles, ntiles, NF, pad, ncell_all, pos4, vt4, vel4, \
-                                      frc4, idx, idx_all, start_all, pos_out, vel_out, frc_out,  \
-                                      dk, st)
+                                      frc4, idx, idx_all, start_all, cq, pos_out, vel_out,       \
+                                      frc_out, dk, st)
 #define DPD_FORCE_S(I, BS) \
   if (sph) DPD_FORCE(I, BS, true); else DPD_FORCE(I, BS, false)
   if (block == 128) {

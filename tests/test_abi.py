@@ -35,9 +35,9 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_kernel_names_and_error_text(lib):
-    for i in range(8):
+    for i in range(9):
         assert lib.dpd_kernel_name(i)
-    assert lib.dpd_kernel_name(8) == b""
+    assert lib.dpd_kernel_name(9) == b""
     assert isinstance(lib.dpd_last_error(None), bytes)
 
 

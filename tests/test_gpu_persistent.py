@@ -120,7 +120,7 @@ def test_one_timed_launch_per_step(dpd):
     say("kernel times", kt)
     assert kt["step_persistent"][1] == 6
     for k in ("integrate_reflect_bin", "scan_reduce", "scan_down", "scatter", "sort_cells",
-              "pair_force"):
+              "pair_codes", "pair_force"):
         assert kt[k][1] == 0, k
     sim.close()
 

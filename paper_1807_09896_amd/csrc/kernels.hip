@@ -808,7 +808,11 @@ __global__ __launch_bounds__(kBlock) void k_count_flagged(const KGeom G, int64_t
 // run of each row, not for every lane's row switches.  Sums run in
 // candidate order, so runs are deterministic.
 // ---------------------------------------------------------------------------
-constexpr int kListCap = 20;
+// 26 entries per lane: with 256-thread blocks at six wavefronts per SIMD,
+// six blocks' lists (26 KB each) fill a CU's 160 KB of LDS, and most lanes'
+// pairs (about 16 plus the pre-test's extras) fit, so most wavefronts run
+// the pair pass once, after the walk, instead of twice.
+constexpr int kListCap = 26;
 constexpr int kBatch = 4;   // = the width of one run-array load
 
 struct Acc {
@@ -1039,10 +1043,10 @@ __device__ __forceinline__ void force_tile(
   frc_out[s] = make_float4(fx, fy, fz, 0.f);
 }
 
-// Eight wavefronts per SIMD (at most 64 VGPRs): the walk waits on dependent
-// loads, and more wavefronts in flight hide more of that wait.
+// Six wavefronts per SIMD: at most 80 VGPRs, so the walk and the pair pass
+// run without register spills, and six blocks' lists fit in LDS.
 template <bool INIT, int BS, bool SPH>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8))) void k_force(
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(6))) void k_force(
     const Box *__restrict__ boxes, const Tile *__restrict__ tiles, int ntiles, int64_t NF,
     int32_t pad, int32_t ncell_all, const float4 *__restrict__ pos4,
     const float4 *__restrict__ vt4, const float4 *__restrict__ vel4,

@@ -116,7 +116,7 @@ struct dpd_ctx {
   int32_t *wcstart = nullptr;   // exclusive scan of wall counts per cell (static)
   int32_t *wcell = nullptr;     // global cell of each cell-sorted wall (static)
   int32_t *idx_all = nullptr;   // merged per-cell runs: walls (NF + w), then fluid
-  uint32_t *cq = nullptr;       // coarse position codes of the merged runs, 2 words each
+  uint32_t *cq = nullptr;       // coarse position codes of the merged runs
   // moving walls: re-sorted by cell every step (moved copy, velocities,
   // cells, ranks, per-cell counts)
   bool moving = false;
@@ -1012,7 +1012,7 @@ int create_impl(int32_t nbox, const dpd_box *boxes, const dpd_particles *parts,
   c->wcstart = (int32_t *)dalloc(c, 4 * (ncell + 1));
   c->wcell = (int32_t *)dalloc(c, 4 * nw);
   c->idx_all = (int32_t *)dalloc(c, 4 * (nf + nw + dpd::kIdxSlack));
-  c->cq = (uint32_t *)dalloc(c, 8 * (nf + nw + dpd::kIdxSlack));
+  c->cq = (uint32_t *)dalloc(c, 4 * (nf + nw + dpd::kIdxSlack));
   for (const Replica &p : c->rep) {
     c->moving = c->moving || p.moving;
     c->reflect = c->reflect || p.P.reflect != 0;

@@ -221,53 +221,53 @@ __device__ __forceinline__ float sep_d(const SepAxis &s, float xj) {
   return sub_nc(s.a, sub_nc(xj, s.b));
 }
 
-// Coarse positions for the candidate pre-test: q = rint(256 x) modulo 2^16
+// Coarse positions for the candidate pre-test: q = rint(256 x) modulo 2^10
 // per axis (256 x is exact in FP32, so |256 x - q| <= 1/2 before the
-// modulo), two words per particle: x | y << 16, then z.  Differences of
-// two such codes, taken modulo 2^16 and read as signed, are exact for any
-// two points less than 128 apart, whatever the box size.  With a periodic
-// image shift s L rounded the same way, the code difference vector dq lies
-// within 3/2 per axis of 256 d, d the exact image difference, so
-// |dq| <= 256 |d| + 1.5 sqrt(3): a candidate with |dq| beyond
-// 256 rc (1 + 1e-5) + 2.6 is out of range in the exact FP32 decision too
-// (whose rounding of r^2 is a few 1e-7).
+// modulo), one word per particle: x in bits 0-9, y in 11-20, z in 22-31,
+// with bits 10 and 21 set.  Subtracting a lane's code (the same fields,
+// those two bits clear) leaves each field's difference modulo 2^10 in its
+// own bits (a borrow stops at the set bit above the field); read as signed
+// 10-bit values they are exact for any two points less than 2 apart per
+// axis, whatever the box size.  With a periodic image shift s L rounded the
+// same way, the code difference vector dq lies within 3/2 per axis of
+// 256 d, d the exact image difference, so |dq| <= 256 |d| + 1.5 sqrt(3): a
+// candidate with |dq| beyond 256 rc (1 + 1e-5) + 2.6 is out of range in the
+// exact FP32 decision too (whose rounding of r^2 is a few 1e-7).  Candidates
+// farther than 2 apart on an axis wrap to some other difference; they are
+// at worst kept, and the exact decision drops them.
 constexpr float kQScale = 256.f;
-typedef unsigned short u16x2_t __attribute__((ext_vector_type(2)));
-typedef short i16x2_t __attribute__((ext_vector_type(2)));
+constexpr uint32_t kQGuard = (1u << 10) | (1u << 21);
 
-__device__ __forceinline__ uint32_t qcode(float x) {
-  return (uint32_t)__float2int_rn(x * kQScale) & 0xFFFFu;
+__device__ __forceinline__ uint32_t qaxis(float x) {
+  return (uint32_t)__float2int_rn(x * kQScale) & 0x3FFu;
 }
 
-__device__ __forceinline__ uint2 qcode3(float x, float y, float z) {
-  return make_uint2(qcode(x) | (qcode(y) << 16), qcode(z));
+__device__ __forceinline__ uint32_t qcode3(float x, float y, float z) {
+  return qaxis(x) | (qaxis(y) << 11) | (qaxis(z) << 22) | kQGuard;
 }
 
-// |dq|^2 of a candidate's code (wxy, wz) against the lane's shifted code
-// (qxy, qz): signed 16-bit differences, squared and summed in 32 bits
-// (below 3 x 2^30, so the unsigned reading is exact).
-__device__ __forceinline__ uint32_t qdist2(uint32_t wxy, uint32_t wz, uint32_t qxy, uint32_t qz) {
-  const i16x2_t dxy =
-      __builtin_bit_cast(i16x2_t, __builtin_bit_cast(u16x2_t, wxy) - __builtin_bit_cast(u16x2_t, qxy));
-  const i16x2_t dz =
-      __builtin_bit_cast(i16x2_t, __builtin_bit_cast(u16x2_t, wz) - __builtin_bit_cast(u16x2_t, qz));
-  return (uint32_t)__builtin_amdgcn_sdot2(dxy, dxy, __builtin_amdgcn_sdot2(dz, dz, 0, false), false);
+// |dq|^2 of a candidate's code w against the lane's shifted code q.
+__device__ __forceinline__ uint32_t qdist2(uint32_t w, uint32_t q) {
+  const int d = (int)(w - q);
+  const int dx = __builtin_amdgcn_sbfe(d, 0, 10), dy = __builtin_amdgcn_sbfe(d, 11, 10),
+            dz = __builtin_amdgcn_sbfe(d, 22, 10);
+  return (uint32_t)(dx * dx + dy * dy + dz * dz);
 }
 
 // Threshold of the pre-test for cutoff^2 rc2: keep a candidate iff
-// qdist2 <= qthresh.  Cutoffs of 120 and more (where a hit's code
-// difference could leave the 16-bit range) keep every candidate.
+// qdist2 <= qthresh.  Cutoffs of 1.97 and more (where a hit's code
+// difference could leave the 10-bit range) keep every candidate.
 __device__ __forceinline__ uint32_t qthresh(float rc2) {
-  if (!(rc2 < 14400.f)) return 0xFFFFFFFFu;
+  if (!(rc2 < 3.88f)) return 0xFFFFFFFFu;
   const float r = sqrtf(rc2) * (kQScale * 1.00001f) + 2.6f;
   return (uint32_t)(r * r);
 }
 
 // One axis of the lane's own code with the image shift sL of a neighbour row
-// applied (16 bits).
+// applied (10 bits, guard clear).
 __device__ __forceinline__ uint32_t qshift(float x, float sL) {
   return ((uint32_t)__float2int_rn(x * kQScale) - (uint32_t)__float2int_rn(sL * kQScale)) &
-         0xFFFFu;
+         0x3FFu;
 }
 
 // ---------------------------------------------------------------------------

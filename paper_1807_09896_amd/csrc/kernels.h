@@ -51,7 +51,7 @@ hipError_t launch_scatter(hipStream_t s, int64_t n, const int32_t *cell_of,
 hipError_t launch_sort_cells(hipStream_t s, int64_t ncell, const int32_t *start, int32_t *idx,
                              const float4 *key4, const int32_t *fluid_off, int32_t *idx_all);
 // Coarse position codes of the merged runs, cq[t] from pos4[idx_all[t]] for
-// t < n (two words per entry), which the pair kernel's candidate pre-test
+// t < n (one word per entry), which the pair kernel's candidate pre-test
 // reads; n = NF + NW, after the scatter and sort.
 hipError_t launch_quant_runs(hipStream_t s, int64_t n, const int32_t *idx_all,
                              const float4 *pos4, uint32_t *cq);

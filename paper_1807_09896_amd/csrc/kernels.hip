@@ -374,7 +374,7 @@ __global__ void k_sort_cells(int64_t ncell, const int32_t *__restrict__ start,
 // Coarse codes of the merged runs, cq[t] = qcode3(pos4[idx_all[t]]): one
 // thread per entry, so that the index reads and code writes coalesce.
 __global__ void k_quant_runs(int64_t n, const int32_t *__restrict__ idx_all,
-                             const float4 *__restrict__ pos4, uint2 *__restrict__ cq) {
+                             const float4 *__restrict__ pos4, uint32_t *__restrict__ cq) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   const float4 x = pos4[idx_all[t]];
@@ -846,7 +846,7 @@ __device__ __forceinline__ void add_pair(Acc &acc, float dx, float dy, float dz,
 }
 
 // Tile tid by one block of BS threads; list: kListCap x BS words of LDS.
-// QF: the walk tests candidates on their coarse codes (cq, two words per
+// QF: the walk tests candidates on their coarse codes (cq, one word per
 // merged-run entry, in run order) and lists every candidate the bound keeps;
 // the pair pass then takes the exact FP32 decision, so the pairs summed and
 // their order are those of the exact walk.
@@ -884,7 +884,7 @@ __device__ __forceinline__ void force_tile(
   const Records16 posr(pos4, pad + 1), vtr(vt4, pad + 1);
   const Ints4 runs(idx_all, pad + kIdxSlack);
   const Ints4 starts(start_all, ncell_all + 1 + kStartSlack);
-  const Ints4 codes((const int32_t *)cq, QF ? 2 * (pad + kIdxSlack) : 0);
+  const Ints4 codes((const int32_t *)cq, QF ? pad + kIdxSlack : 0);
   const uint32_t qth = qthresh(P.rc2);
   // this lane's list column as LDS byte offsets: entry q at lane0 + q * BS * 4
   char *const lds = (char *)list;
@@ -928,7 +928,7 @@ __device__ __forceinline__ void force_tile(
   // run are read (other cells' entries, or the pad) but never listed.
   // Phase B runs when a lane's list could overflow in the next pass.
   auto walk = [&](int t, int t_end, int tb, int tb_end, SepAxis ax, SepAxis axb, SepAxis ay,
-                  SepAxis az, uint32_t qa, uint32_t qb, uint32_t qz) {
+                  SepAxis az, uint32_t qa, uint32_t qb) {
     {
       const bool sw = t >= t_end;
       t = sw ? tb : t;
@@ -944,14 +944,11 @@ __device__ __forceinline__ void force_tile(
         int jb[kBatch];
         runs.load(t, jb);
         if (QF) {
-          int w[2 * kBatch];
-          codes.load(2 * t, w);
-          codes.load(2 * t + 4, w + 4);
+          int w[kBatch];
+          codes.load(t, w);
 #pragma unroll
           for (int u = 0; u < kBatch; ++u) {
-            const bool keep =
-                qdist2((uint32_t)w[2 * u], (uint32_t)w[2 * u + 1], qa, qz) <= qth && jb[u] != i &&
-                u < rem;
+            const bool keep = qdist2((uint32_t)w[u], qa) <= qth && jb[u] != i && u < rem;
             *(int *)(lds + tail) = jb[u];
             tail += keep ? (uint32_t)(BS * 4) : 0u;
           }
@@ -990,14 +987,14 @@ __device__ __forceinline__ void force_tile(
     if (qz < 0) { qz += nz; sz = -G.L[2]; }
     else if (qz >= nz) { qz -= nz; sz = G.L[2]; }
     const SepAxis az = sep_axis(pi.z, sz);
-    const uint32_t cz_code = QF ? qshift(pi.z, sz) : 0u;
+    const uint32_t cz_code = QF ? qshift(pi.z, sz) << 22 : 0u;
     for (int oy = -1; oy <= 1; ++oy) {
       int qy = cy + oy;
       float sy = 0.f;
       if (qy < 0) { qy += ny; sy = -G.L[1]; }
       else if (qy >= ny) { qy -= ny; sy = G.L[1]; }
       const SepAxis ay = sep_axis(pi.y, sy);
-      const uint32_t cy_code = QF ? qshift(pi.y, sy) << 16 : 0u;
+      const uint32_t cyz_code = QF ? (qshift(pi.y, sy) << 11) | cz_code : 0u;
       // the row's x-neighbours [cx-1, cx+1] as run A, plus run B where the
       // row wraps (cell nx-1 seen across the left edge, then cells 0 and 1;
       // or cells nx-2 and nx-1, then cell 0 seen across the right edge)
@@ -1016,9 +1013,9 @@ __device__ __forceinline__ void force_tile(
       }
       const float sxa = left ? -G.L[0] : 0.f, sxb = right ? G.L[0] : 0.f;
       const SepAxis ax = sep_axis(pi.x, sxa), axb = sep_axis(pi.x, sxb);
-      const uint32_t qa = QF ? (qshift(pi.x, sxa) | cy_code) : 0u;
-      const uint32_t qb = QF ? (qshift(pi.x, sxb) | cy_code) : 0u;
-      walk(ta, ta_end, tb, tb_end, ax, axb, ay, az, qa, qb, cz_code);
+      const uint32_t qa = QF ? (qshift(pi.x, sxa) | cyz_code) : 0u;
+      const uint32_t qb = QF ? (qshift(pi.x, sxb) | cyz_code) : 0u;
+      walk(ta, ta_end, tb, tb_end, ax, axb, ay, az, qa, qb);
     }
   }
   flush();
@@ -1307,7 +1304,7 @@ __device__ __attribute__((noinline)) void p_sort(const PArgs *__restrict__ A0, i
   const int t0 = uniform_int(A->start_all[a]), t1 = uniform_int(A->start_all[b]);
   for (int t = t0 + (int)threadIdx.x; t < t1; t += kBlock) {
     const float4 x = A->pos4[A->idx_all[t]];
-    ((uint2 *)A->cq)[t] = qcode3(x.x, x.y, x.z);
+    A->cq[t] = qcode3(x.x, x.y, x.z);
   }
 }
 
@@ -1461,7 +1458,7 @@ hipError_t launch_quant_runs(hipStream_t s, int64_t n, const int32_t *idx_all,
                              const float4 *pos4, uint32_t *cq) {
   if (n <= 0) return hipSuccess;
   if (!idx_all || !pos4 || !cq) return hipErrorInvalidValue;
-  k_quant_runs<<<grid_for(n), kBlock, 0, s>>>(n, idx_all, pos4, (uint2 *)cq);
+  k_quant_runs<<<grid_for(n), kBlock, 0, s>>>(n, idx_all, pos4, cq);
   return hipGetLastError();
 }
 

@@ -76,6 +76,17 @@ SYSTEMS = {
     # sort takes every run length (the register networks and the long runs)
     "dense": lambda: workloads.bulk_system(L=(5.0, 4.0, 3.0), rho=24.0,
                                            params=workloads.default_params(seed=21)),
+    # cutoffs other than 1: the pair kernel's coarse-position pre-test scales
+    # its bound with rc; with rc = 1.5 the cells are 1.6-1.75 wide, so row
+    # candidates lie up to 3.5 apart per axis and their 10-bit code
+    # differences wrap; at rc = 2 the pre-test keeps every candidate
+    "rc15": lambda: workloads.slab_system(L=(8.0, 7.0, 9.0), wall=1.5, grid_dtype=np.float32,
+                                          seed_fluid=31, seed_wall=32,
+                                          params=workloads.default_params(rc=1.5,
+                                                                          g=(0.02, 0, 0),
+                                                                          seed=33)),
+    "rc20": lambda: workloads.bulk_system(L=(8.0, 6.0, 7.0), rho=3.0,
+                                          params=workloads.default_params(rc=2.0, seed=34)),
 }
 
 
@@ -229,7 +240,8 @@ def _one_step_compare(dpd, oracle_lib, s, nsteps_before=0, sim=None, r=0):
     return n_events
 
 
-@pytest.mark.parametrize("name", ["tiny", "slab_f64grid", "curved", "stress", "dense"])
+@pytest.mark.parametrize("name", ["tiny", "slab_f64grid", "curved", "stress", "dense", "rc15",
+                                  "rc20"])
 def test_one_step_parity(dpd, oracle_lib, name):
     s = SYSTEMS[name]()
     say("one-step", name, s.n)

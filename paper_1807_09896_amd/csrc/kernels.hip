@@ -798,11 +798,13 @@ __global__ __launch_bounds__(kBlock) void k_count_flagged(const KGeom G, int64_t
 // 27-cell neighbourhood together (the x-neighbours of a row are consecutive
 // cells, so a row is one run of merged entries, walls then fluid, or two
 // where it wraps in x) and walks each row in lockstep, four run entries per
-// lane and pass so that their loads overlap, with the FP32 cutoff decision;
-// hits go to the lane's column of an LDS list (slot-major, so the
-// wavefront's appends fall in different banks).  Phase B: each lane
-// evaluates its listed pairs; the random-number and force arithmetic runs
-// only for pairs inside the cutoff.  The wavefront runs phase B when any
+// lane and pass so that their loads overlap, testing the entries' coarse
+// position codes against a bound that keeps every pair of the FP32 cutoff
+// decision; kept candidates go to the lane's column of an LDS list
+// (slot-major, so the wavefront's appends fall in different banks).  Phase
+// B: each lane takes the exact FP32 decision on its listed candidates; the
+// random-number and force arithmetic runs only for pairs inside the
+// cutoff.  The wavefront runs phase B when any
 // lane's list could overflow in the next pass, and once at the end.  Lanes
 // never branch apart inside a pass, so the wavefront pays for the longest
 // run of each row, not for every lane's row switches.  Sums run in
@@ -846,11 +848,11 @@ __device__ __forceinline__ void add_pair(Acc &acc, float dx, float dy, float dz,
 }
 
 // Tile tid by one block of BS threads; list: kListCap x BS words of LDS.
-// QF: the walk tests candidates on their coarse codes (cq, one word per
-// merged-run entry, in run order) and lists every candidate the bound keeps;
-// the pair pass then takes the exact FP32 decision, so the pairs summed and
-// their order are those of the exact walk.
-template <bool INIT, int BS, bool SPH, bool QF>
+// The walk tests candidates on their coarse codes (cq, one word per
+// merged-run entry, in run order) and lists every candidate the bound
+// keeps; the pair pass then takes the exact FP32 decision, so the pairs
+// summed and their order are those of an exact walk over the same runs.
+template <bool INIT, int BS, bool SPH>
 __device__ __forceinline__ void force_tile(
     int tid, uint32_t *list, const Box *__restrict__ boxes, const Tile *__restrict__ tiles,
     int64_t NF, int32_t pad, int32_t ncell_all, const float4 *__restrict__ pos4,
@@ -878,13 +880,14 @@ __device__ __forceinline__ void force_tile(
   const uint32_t gi = __float_as_uint(pi.w);
   int cx, cy, cz;
   cell_index(G, pi.x, pi.y, pi.z, cx, cy, cz);
-  // pos4 and vt4 hold NF + NW + 1 records (the pad last); the run array
-  // holds NF + NW entries and kIdxSlack spare ones, which read as the pad;
-  // the run starts hold ncell_all + 1 entries and kStartSlack spare ones
+  // pos4 and vt4 hold NF + NW + 1 records (the pad last); the run array and
+  // the codes hold NF + NW entries and kIdxSlack spare ones (the run's read
+  // as the pad); the run starts hold ncell_all + 1 entries and kStartSlack
+  // spare ones
   const Records16 posr(pos4, pad + 1), vtr(vt4, pad + 1);
   const Ints4 runs(idx_all, pad + kIdxSlack);
+  const Ints4 codes((const int32_t *)cq, pad + kIdxSlack);
   const Ints4 starts(start_all, ncell_all + 1 + kStartSlack);
-  const Ints4 codes((const int32_t *)cq, QF ? pad + kIdxSlack : 0);
   const uint32_t qth = qthresh(P.rc2);
   // this lane's list column as LDS byte offsets: entry q at lane0 + q * BS * 4
   char *const lds = (char *)list;
@@ -892,8 +895,9 @@ __device__ __forceinline__ void force_tile(
   const uint32_t full = lane0 + (uint32_t)((kListCap - kBatch) * BS * 4);
   uint32_t tail = lane0;   // next free entry
   Acc acc = {0.f, 0.f, 0.f};
-  // phase B: the listed pairs of this lane, in list (= candidate) order; the
-  // next pair's data is fetched while the current one is evaluated
+  // phase B: the listed candidates of this lane, in list (= candidate)
+  // order, with the exact decision; the next candidate's data is fetched
+  // while the current one is evaluated
   auto flush = [&]() {
     int j = tail > lane0 ? *(const int *)(lds + lane0) : pad;
     float4 pj = posr[j], vtj = vtr[j];
@@ -907,13 +911,10 @@ __device__ __forceinline__ void force_tile(
       const float r2 = dx * dx + dy * dy + dz * dz;
       const bool wall = (int64_t)j >= NF;
       const float a = wall ? P.a_fw : P.a_ff;
-      bool take = true;
-      if (QF) {
-        // the exact decision of the walk (the listed candidates are a superset)
-        const float r2d = pair_r2(dx, dy, dz);
-        take = r2d < P.rc2 && r2d > 0.0f;
-      }
-      if (take)
+      // the pair decision (r2 > 0 also drops coincident particles, whose
+      // force is 0)
+      const float r2d = pair_r2(dx, dy, dz);
+      if (r2d < P.rc2 && r2d > 0.0f)
         add_pair<SPH>(acc, dx, dy, dz, r2, vti.x - vtj.x, vti.y - vtj.y, vti.z - vtj.z, a, wall,
                       P, gi, __float_as_uint(pj.w), klo, khi);
       j = jn;
@@ -924,55 +925,36 @@ __device__ __forceinline__ void force_tile(
   };
   // Phase A for one neighbour row: the wavefront walks the lane's runs in
   // lockstep, kBatch run entries per lane and pass (run A, then run B where
-  // the row wraps; a lane moves to B on its own).  Entries past the lane's
-  // run are read (other cells' entries, or the pad) but never listed.
-  // Phase B runs when a lane's list could overflow in the next pass.
-  auto walk = [&](int t, int t_end, int tb, int tb_end, SepAxis ax, SepAxis axb, SepAxis ay,
-                  SepAxis az, uint32_t qa, uint32_t qb) {
+  // the row wraps; a lane moves to B on its own), with qa / qb the lane's
+  // code shifted by the image of run A / B.  Entries past the lane's run are
+  // read (other cells' entries, or the pad) but never listed; neither is
+  // the lane's own particle.  Phase B runs when a lane's list could
+  // overflow in the next pass.
+  auto walk = [&](int t, int t_end, int tb, int tb_end, uint32_t qa, uint32_t qb) {
     {
       const bool sw = t >= t_end;
       t = sw ? tb : t;
       t_end = sw ? tb_end : t_end;
       tb = sw ? tb_end : tb;
-      ax.a = sw ? axb.a : ax.a;
-      ax.b = sw ? axb.b : ax.b;
       qa = sw ? qb : qa;
     }
     for (;;) {
       while (wave_any(t < t_end) && !wave_any(tail > full)) {
         const int rem = t_end - t;
-        int jb[kBatch];
+        int jb[kBatch], w[kBatch];
         runs.load(t, jb);
-        if (QF) {
-          int w[kBatch];
-          codes.load(t, w);
+        codes.load(t, w);
 #pragma unroll
-          for (int u = 0; u < kBatch; ++u) {
-            const bool keep = qdist2((uint32_t)w[u], qa) <= qth && jb[u] != i && u < rem;
-            *(int *)(lds + tail) = jb[u];
-            tail += keep ? (uint32_t)(BS * 4) : 0u;
-          }
-        } else {
-          float4 pb[kBatch];
-#pragma unroll
-          for (int u = 0; u < kBatch; ++u) pb[u] = posr[jb[u]];
-#pragma unroll
-          for (int u = 0; u < kBatch; ++u) {
-            const float r2 =
-                pair_r2(sep_d(ax, pb[u].x), sep_d(ay, pb[u].y), sep_d(az, pb[u].z));
-            // r2 > 0 drops i itself (and coincident particles, whose force is 0)
-            const bool hit = r2 < P.rc2 && r2 > 0.0f && u < rem;
-            *(int *)(lds + tail) = jb[u];
-            tail += hit ? (uint32_t)(BS * 4) : 0u;
-          }
+        for (int u = 0; u < kBatch; ++u) {
+          const bool keep = qdist2((uint32_t)w[u], qa) <= qth && jb[u] != i && u < rem;
+          *(int *)(lds + tail) = jb[u];
+          tail += keep ? (uint32_t)(BS * 4) : 0u;
         }
         t = rem > 0 ? t + kBatch : t;
         const bool sw = t >= t_end && tb < tb_end;
         t = sw ? tb : t;
         t_end = sw ? tb_end : t_end;
         tb = sw ? tb_end : tb;
-        ax.a = sw ? axb.a : ax.a;
-        ax.b = sw ? axb.b : ax.b;
         qa = sw ? qb : qa;
       }
       if (!wave_any(t < t_end)) break;
@@ -986,15 +968,13 @@ __device__ __forceinline__ void force_tile(
     float sz = 0.f;
     if (qz < 0) { qz += nz; sz = -G.L[2]; }
     else if (qz >= nz) { qz -= nz; sz = G.L[2]; }
-    const SepAxis az = sep_axis(pi.z, sz);
-    const uint32_t cz_code = QF ? qshift(pi.z, sz) << 22 : 0u;
+    const uint32_t cz_code = qshift(pi.z, sz) << 22;
     for (int oy = -1; oy <= 1; ++oy) {
       int qy = cy + oy;
       float sy = 0.f;
       if (qy < 0) { qy += ny; sy = -G.L[1]; }
       else if (qy >= ny) { qy -= ny; sy = G.L[1]; }
-      const SepAxis ay = sep_axis(pi.y, sy);
-      const uint32_t cyz_code = QF ? (qshift(pi.y, sy) << 11) | cz_code : 0u;
+      const uint32_t cyz_code = (qshift(pi.y, sy) << 11) | cz_code;
       // the row's x-neighbours [cx-1, cx+1] as run A, plus run B where the
       // row wraps (cell nx-1 seen across the left edge, then cells 0 and 1;
       // or cells nx-2 and nx-1, then cell 0 seen across the right edge)
@@ -1012,10 +992,7 @@ __device__ __forceinline__ void force_tile(
         tb_end = left ? w[2] : (right ? w[1] : 0);
       }
       const float sxa = left ? -G.L[0] : 0.f, sxb = right ? G.L[0] : 0.f;
-      const SepAxis ax = sep_axis(pi.x, sxa), axb = sep_axis(pi.x, sxb);
-      const uint32_t qa = QF ? (qshift(pi.x, sxa) | cyz_code) : 0u;
-      const uint32_t qb = QF ? (qshift(pi.x, sxb) | cyz_code) : 0u;
-      walk(ta, ta_end, tb, tb_end, ax, axb, ay, az, qa, qb);
+      walk(ta, ta_end, tb, tb_end, qshift(pi.x, sxa) | cyz_code, qshift(pi.x, sxb) | cyz_code);
     }
   }
   flush();
@@ -1055,9 +1032,8 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(6))) void k_
   __shared__ uint32_t list[kListCap * BS];
   const int tid = xcd_block();
   if (tid >= ntiles) return;
-  force_tile<INIT, BS, SPH, true>(tid, list, boxes, tiles, NF, pad, ncell_all, pos4, vt4, vel4,
-                                  frc4, idx, idx_all, start_all, cq, pos_out, vel_out, frc_out,
-                                  dk, st);
+  force_tile<INIT, BS, SPH>(tid, list, boxes, tiles, NF, pad, ncell_all, pos4, vt4, vel4, frc4,
+                            idx, idx_all, start_all, cq, pos_out, vel_out, frc_out, dk, st);
 }
 
 // Interacting pairs with the same decision as the force kernel.  Each thread
@@ -1314,7 +1290,7 @@ __device__ __attribute__((noinline)) void p_force(const PArgs *__restrict__ A0, 
   const ArgsPtr A = uniform_args(A0);
   const int tile = uniform_int(tile0);
   uint32_t *list = lds_ptr(list0);
-  force_tile<false, kBlock, SPH, true>(tile, list, A->boxes, A->ftiles, A->NF, A->pad,
+  force_tile<false, kBlock, SPH>(tile, list, A->boxes, A->ftiles, A->NF, A->pad,
                                        A->ncell_all, A->pos4, A->vt4, A->vel4, A->frc4, A->idx,
                                        A->idx_all, A->start_all, A->cq, A->pos_out, A->vel_out,
                                        A->frc_out, A->dk, A->st);

@@ -87,6 +87,10 @@ SYSTEMS = {
                                                                           seed=33)),
     "rc20": lambda: workloads.bulk_system(L=(8.0, 6.0, 7.0), rho=3.0,
                                           params=workloads.default_params(rc=2.0, seed=34)),
+    # box edges whose 256 L is not an integer: the coarse codes' image
+    # shifts are rounded, and the last cell of each axis is narrower
+    "odd_box": lambda: workloads.bulk_system(L=(5.4, 4.8, 6.3), h=0.3, rho=4.0,
+                                             params=workloads.default_params(seed=35)),
 }
 
 
@@ -241,7 +245,7 @@ def _one_step_compare(dpd, oracle_lib, s, nsteps_before=0, sim=None, r=0):
 
 
 @pytest.mark.parametrize("name", ["tiny", "slab_f64grid", "curved", "stress", "dense", "rc15",
-                                  "rc20"])
+                                  "rc20", "odd_box"])
 def test_one_step_parity(dpd, oracle_lib, name):
     s = SYSTEMS[name]()
     say("one-step", name, s.n)

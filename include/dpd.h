@@ -294,7 +294,10 @@ int dpd_use_persistent(dpd_ctx *ctx, int32_t enable);
 /* Choose the launch shapes of the integrate kernel (particles per thread,
  * 1 or 2) and of the pair-force kernel (work-group size, 128 or 256) by
  * timing `steps` steps of each of the four combinations from the current
- * state; the state, k and the step counter are restored after each trial, so
+ * state: one untimed round of all four, then two timed rounds in opposite
+ * orders, each combination keeping its faster time (the first trials of a
+ * run are slower, which would favour the last combination tried); the
+ * state, k and the step counter are restored after each trial, so
  * the context is left as it was apart from the shapes (results do not depend
  * on them).  If the environment variable DPD_TUNE_CACHE names a file, a
  * choice recorded there for the same device and sizes is used without trials

@@ -227,14 +227,15 @@ __device__ __forceinline__ float sep_d(const SepAxis &s, float xj) {
 // with bits 10 and 21 set.  Subtracting a lane's code (the same fields,
 // those two bits clear) leaves each field's difference modulo 2^10 in its
 // own bits (a borrow stops at the set bit above the field); read as signed
-// 10-bit values they are exact for any two points less than 2 apart per
-// axis, whatever the box size.  With a periodic image shift s L rounded the
+// 10-bit values (-512 .. 511) they are exact whenever the true code
+// difference lies in that range, i.e. for points less than about 1.99
+// apart per axis, whatever the box size.  With a periodic image shift s L rounded the
 // same way, the code difference vector dq lies within 3/2 per axis of
 // 256 d, d the exact image difference, so |dq| <= 256 |d| + 1.5 sqrt(3): a
 // candidate with |dq| beyond 256 rc (1 + 1e-5) + 2.6 is out of range in the
-// exact FP32 decision too (whose rounding of r^2 is a few 1e-7).  Candidates
-// farther than 2 apart on an axis wrap to some other difference; they are
-// at worst kept, and the exact decision drops them.
+// exact FP32 decision too (whose rounding of r^2 is a few 1e-7).  Farther
+// candidates wrap to some other difference; they are at worst kept, and
+// the exact decision drops them.
 constexpr float kQScale = 256.f;
 constexpr uint32_t kQGuard = (1u << 10) | (1u << 21);
 

@@ -1297,10 +1297,11 @@ __device__ __attribute__((noinline)) void p_force(const PArgs *__restrict__ A0, 
 }
 
 template <typename T, int PPT, bool REFLECT, bool SPH>
-// Seven wavefronts per SIMD: the phase functions are allocated separately
-// and the largest (the pair force, 64 VGPRs in its own kernel) needs a few
-// more registers as a callee.
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) void
+// Six wavefronts per SIMD, as the pair kernel: the pair list (26 KB per
+// block) limits a CU to six blocks anyway, and the phase functions are
+// allocated separately, the largest (the pair force, 74 VGPRs in its own
+// kernel) with a few more registers as a callee.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void
 k_step_persistent(const PArgs *__restrict__ A) {
   __shared__ union {
     uint32_t list[kListCap * kBlock];

@@ -360,17 +360,25 @@ int set_shapes(dpd_ctx *c, int ppt, int fblock) {
   return rc;
 }
 
-// Work items of the persistent step, in queue order: every integrate tile,
-// then per box its scan chunks (reduce, then down), its scatter ranges (fluid
-// slots, then walls), its per-cell sort ranges, and its force tiles; each
+// Work items of the persistent step, in queue order: every box's integrate
+// tiles (grouped, see add_tiles), then per box its scan chunks (reduce, then
+// down), its scatter ranges (fluid slots, then walls), its per-cell sort
+// ranges, and its force tiles (grouped); each
 // phase's items of all boxes before the next phase's, so that no item waits
 // on one after it.  need[box][phase] counts them.
 constexpr int kScatterItem = 4096;   // particles per scatter item
 constexpr int kSortItem = 2048;      // cells per sort item
+constexpr int kTilesPerItem = 16;    // at most, integrate or force tiles per item
 
 int build_persistent(dpd_ctx *c) {
   using dpd::PItem;
   const int R = c->R, NP = dpd::kPhases;
+  int ncu = 0;
+  HIP_TRY(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
+  const int per = dpd::persistent_blocks_per_cu(c->ppt, c->grid_f64, c->reflect ? 1 : 0,
+                                                c->sph ? 1 : 0);
+  if (per <= 0) return fail(c, DPD_E_DEVICE, "persistent step: no resident blocks");
+  c->pblocks = per * ncu;
   int rc = build_tiles(c, 256, &c->ptiles, &c->n_ptiles, &c->ptiles_cap, true);
   if (rc) return rc;
   std::vector<Tile> it((size_t)c->n_itiles), ft((size_t)c->n_ptiles);
@@ -384,7 +392,21 @@ int build_persistent(dpd_ctx *c) {
     items.push_back(PItem{phase, box, (int32_t)a, (int32_t)b});
     need[(size_t)box * NP + phase] += 1;
   };
-  for (int t = 0; t < c->n_itiles; ++t) add(dpd::kPhIntegrate, it[t].box, t, 0);
+  // integrate and force items: consecutive tiles of one box, about twice
+  // as many per item as the phase has tiles per resident block, at most
+  // kTilesPerItem (every item ends with a device-scope release, the costly
+  // part, but small boxes need the items to spread over the blocks)
+  auto add_tiles = [&](int phase, const std::vector<Tile> &tl) {
+    const size_t per_item = std::max<size_t>(
+        1, std::min<size_t>(kTilesPerItem, 2 * tl.size() / (size_t)c->pblocks));
+    for (size_t t = 0; t < tl.size();) {
+      size_t e = t + 1;
+      while (e < tl.size() && e - t < per_item && tl[e].box == tl[t].box) ++e;
+      add(phase, tl[t].box, (int64_t)t, (int64_t)e);
+      t = e;
+    }
+  };
+  add_tiles(dpd::kPhIntegrate, it);
   std::vector<int> chunk0((size_t)R);
   int nch_all = 0;
   for (int r = 0; r < R; ++r) {
@@ -409,7 +431,7 @@ int build_persistent(dpd_ctx *c) {
     for (int64_t a = p.co; a < p.co + p.ncell; a += kSortItem)
       add(dpd::kPhSort, r, a, std::min(a + kSortItem, p.co + p.ncell));
   }
-  for (int t = 0; t < c->n_ptiles; ++t) add(dpd::kPhForce, ft[t].box, t, 0);
+  add_tiles(dpd::kPhForce, ft);
   if (c->NF + c->NW + (int64_t)nch_all >= ((int64_t)1 << 31))
     return fail(c, DPD_E_INVAL, "the batch is too large for the persistent step");
 
@@ -473,12 +495,6 @@ int build_persistent(dpd_ctx *c) {
     A.dk = c->dk;
     HIP_TRY(c, hipMemcpy(c->pargs[a], &A, sizeof(A), hipMemcpyHostToDevice));
   }
-  int ncu = 0;
-  HIP_TRY(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
-  const int per = dpd::persistent_blocks_per_cu(c->ppt, c->grid_f64, c->reflect ? 1 : 0,
-                                                c->sph ? 1 : 0);
-  if (per <= 0) return fail(c, DPD_E_DEVICE, "persistent step: no resident blocks");
-  c->pblocks = per * ncu;
   return DPD_OK;
 }
 

@@ -106,7 +106,7 @@ struct Status {
 enum PersistPhase { kPhIntegrate = 0, kPhReduce, kPhDown, kPhScatter, kPhSort, kPhForce, kPhases };
 struct PItem {
   int32_t phase, box;
-  int32_t a, b;   // tile index (integrate, force), chunk index (reduce, down), or range [a, b)
+  int32_t a, b;   // tile range [a, b) (integrate, force), chunk index (reduce, down), or range [a, b)
 };
 
 // ---------------------------------------------------------------------------

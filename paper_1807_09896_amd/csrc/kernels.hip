@@ -1354,12 +1354,16 @@ k_step_persistent(const PArgs *__restrict__ A) {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (t == 0 && !__builtin_amdgcn_readfirstlane(s_ok)) atomicAdd(&A->st->stalled, 1ull);
     switch (I.phase) {
-      case kPhIntegrate: p_integrate<T, PPT, REFLECT>(A, I.a); break;
+      case kPhIntegrate:
+        for (int t = I.a; t < I.b; ++t) p_integrate<T, PPT, REFLECT>(A, t);
+        break;
       case kPhReduce: p_reduce(A, I.box, I.a, I.b, sm.scan.lds); break;
       case kPhDown: p_down(A, I.box, I.a, I.b, sm.scan.tile, sm.scan.lds); break;
       case kPhScatter: p_scatter(A, I.a, I.b); break;
       case kPhSort: p_sort(A, I.a, I.b); break;
-      default: p_force<SPH>(A, I.a, sm.list); break;
+      default:
+        for (int t = I.a; t < I.b; ++t) p_force<SPH>(A, t, sm.list);
+        break;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();

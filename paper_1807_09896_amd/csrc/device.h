@@ -272,6 +272,28 @@ __device__ __forceinline__ uint32_t qshift(float x, float sL) {
 }
 
 // ---------------------------------------------------------------------------
+// Streaming accesses: per-particle records that a step reads or writes once
+// (the integrator's own state, the pair kernel's outputs and its own old
+// velocity and force).  The nontemporal hint lets their lines leave the L2
+// first, so that the neighbour records the pair walk gathers again and again
+// stay there.  Values and ordering are those of plain accesses.
+// ---------------------------------------------------------------------------
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float4 load_stream(const float4 *p) {
+  const f32x4 v = __builtin_nontemporal_load((const f32x4 *)p);
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+
+__device__ __forceinline__ void store_stream(float4 *p, const float4 v) {
+  __builtin_nontemporal_store(f32x4{v.x, v.y, v.z, v.w}, (f32x4 *)p);
+}
+
+__device__ __forceinline__ void store_stream(int32_t *p, int32_t v) {
+  __builtin_nontemporal_store(v, p);
+}
+
+// ---------------------------------------------------------------------------
 // Phase field: trilinear interpolation of the periodic node grid (decision
 // form lerp(a, b, t) = fl(a + fl(t fl(b - a))): four lerps in x, two in y,
 // one in z), and the gradient of the same interpolant.

@@ -683,9 +683,9 @@ __device__ __forceinline__ void integrate_tile(
     p[u] = (int64_t)tile.first + local;
     x[u] = v[u] = f[u] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (a[u]) {
-      x[u] = pos4[p[u]];
-      v[u] = vel4[p[u]];
-      f[u] = frc4[p[u]];
+      x[u] = load_stream(&pos4[p[u]]);
+      v[u] = load_stream(&vel4[p[u]]);
+      f[u] = load_stream(&frc4[p[u]]);
     }
   }
   Moved m[PPT];
@@ -709,10 +709,10 @@ __device__ __forceinline__ void integrate_tile(
   for (int u = 0; u < PPT; ++u) {
     const int k = wave_rank(r[u], b[u]);
     if (a[u]) {
-      pos4[p[u]] = m[u].pos;
-      vt4[p[u]] = m[u].vt;
-      cell_of[p[u]] = m[u].cell;
-      rank_of[p[u]] = k;
+      store_stream(&pos4[p[u]], m[u].pos);
+      store_stream(&vt4[p[u]], m[u].vt);
+      store_stream(&cell_of[p[u]], m[u].cell);
+      store_stream(&rank_of[p[u]], k);
     }
   }
   // event counts: one atomic per wavefront, after the stores (a per-lane
@@ -997,7 +997,7 @@ __device__ __forceinline__ void force_tile(
   }
   flush();
   const float fx = acc.x + P.g[0], fy = acc.y + P.g[1], fz = acc.z + P.g[2];
-  const float4 vo = vel4[i];
+  const float4 vo = load_stream(&vel4[i]);
   float4 vn;
   if (INIT) {
     vn = make_float4(vo.x, vo.y, vo.z, __int_as_float(0));
@@ -1006,15 +1006,15 @@ __device__ __forceinline__ void force_tile(
     if (event) {
       vn = make_float4(vti.x, vti.y, vti.z, __int_as_float(event));
     } else {
-      const float4 fo = frc4[i];
+      const float4 fo = load_stream(&frc4[i]);
       vn = make_float4(vo.x + P.hdt * (fo.x + fx), vo.y + P.hdt * (fo.y + fy),
                        vo.z + P.hdt * (fo.z + fz), __int_as_float(0));
     }
   }
   if (!(isfinite(fx) && isfinite(fy) && isfinite(fz))) atomicAdd(&st->nonfinite, 1ull);
-  pos_out[s] = pi;
-  vel_out[s] = vn;
-  frc_out[s] = make_float4(fx, fy, fz, 0.f);
+  store_stream(&pos_out[s], pi);
+  store_stream(&vel_out[s], vn);
+  store_stream(&frc_out[s], make_float4(fx, fy, fz, 0.f));
 }
 
 // Six wavefronts per SIMD: at most 80 VGPRs, so the walk and the pair pass

@@ -208,7 +208,10 @@ __global__ __launch_bounds__(kThreads) void k_phi_relax(RelaxArgs<T> a) {
                     a.gz * (nz_p[k] - nz_m[k]);
       const T rhs = cur_base[k] - kap * cur_gm[k];
       const bool in = xin && y < a.ny;
-      if (in) zdst[(size_t)y * a.nx + x] = cur_ph[k] + a.dtau * rhs;
+      // the new value is not read again in this launch: the nontemporal
+      // hint lets its line leave the L2 before the planes that neighbouring
+      // tiles still read as their halos
+      if (in) __builtin_nontemporal_store(cur_ph[k] + a.dtau * rhs, &zdst[(size_t)y * a.nx + x]);
       rmax = in ? fmax(rmax, fabs(rhs)) : rmax;
     }
   };

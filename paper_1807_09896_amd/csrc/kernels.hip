@@ -515,30 +515,53 @@ struct Moved {
 // cell, nearness by the FP32 pair-decision r2 (with the neighbour cell's
 // image shift), ties to the smaller gid; zero where there is none.  Walls
 // are at their start-of-step positions: entry NF + w of pos4 and vt4, wall
-// runs wcstart over the global cells (box offset co).
+// runs wcstart over the global cells (box offset co).  The minimum of
+// (r2, gid) does not depend on the visiting order, so the walls are taken
+// row by row (the three cells of a row are one run, two where it wraps in
+// x), four independent loads at a time, with the next row's bounds fetched
+// while the current row is searched: a bouncing lane waits for a few loads
+// per row instead of one per wall and cell.
 __device__ __forceinline__ float4 wall_velocity(const KGeom &G, int co, int64_t NF, float x, float y,
                                              float z, const int32_t *__restrict__ wcstart,
                                              const float4 *__restrict__ pos4,
                                              const float4 *__restrict__ vt4) {
   int cx, cy, cz;
   cell_index(G, x, y, z, cx, cy, cz);
+  const float4 *walls = pos4 + NF;
   float best = INFINITY;
   uint32_t best_gid = 0;
   int best_w = -1;
-  for (int code = 0; code < 27; ++code) {
-    const NCell nc = neighbour_cell(G, cx, cy, cz, code);
-    const float ax = sub_nc(x, nc.sx), ay = sub_nc(y, nc.sy), az = sub_nc(z, nc.sz);
-    const int w1 = wcstart[co + nc.c + 1];
-    for (int w = wcstart[co + nc.c]; w < w1; ++w) {
-      const float4 q = pos4[NF + w];
-      const float r2 = pair_r2(sub_nc(ax, q.x), sub_nc(ay, q.y), sub_nc(az, q.z));
-      const uint32_t g = __float_as_uint(q.w);
-      if (r2 < best || (r2 == best && g < best_gid)) {
-        best = r2;
-        best_gid = g;
-        best_w = w;
+  NeighbourRows rows;
+  rows.init(cx, cy, cz);
+  int t, te;
+  float sx, sy, sz;
+  bool more = rows.next(G, wcstart, co, t, te, sx, sy, sz);
+  while (more) {
+    int t2, te2;
+    float sx2, sy2, sz2;
+    const bool more2 = rows.next(G, wcstart, co, t2, te2, sx2, sy2, sz2);
+    const float ax = sub_nc(x, sx), ay = sub_nc(y, sy), az = sub_nc(z, sz);
+    for (int w = t; w < te; w += 4) {
+      float4 q[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) q[u] = walls[min(w + u, te - 1)];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float r2 = pair_r2(sub_nc(ax, q[u].x), sub_nc(ay, q[u].y), sub_nc(az, q[u].z));
+        const uint32_t g = __float_as_uint(q[u].w);
+        if (w + u < te && (r2 < best || (r2 == best && g < best_gid))) {
+          best = r2;
+          best_gid = g;
+          best_w = w + u;
+        }
       }
     }
+    more = more2;
+    t = t2;
+    te = te2;
+    sx = sx2;
+    sy = sy2;
+    sz = sz2;
   }
   if (best_w < 0) return make_float4(0.f, 0.f, 0.f, 0.f);
   return vt4[NF + best_w];

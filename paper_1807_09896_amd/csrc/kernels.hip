@@ -119,16 +119,52 @@ __global__ void k_copy1(uint8_t *__restrict__ dst, const uint8_t *__restrict__ s
 // ---------------------------------------------------------------------------
 // Counting sort into cells
 // ---------------------------------------------------------------------------
+// Run structure of equal cells across a wavefront (cell < 0: inactive lane).
+struct RunInfo {
+  unsigned long long heads;
+  int len;     // run length, for head lanes
+  bool head;
+};
+
+__device__ __forceinline__ RunInfo wave_runs(int cell) {
+  const int lane = (int)__lane_id();
+  const int prev = __shfl_up(cell, 1, 64);
+  RunInfo r;
+  r.head = lane == 0 || prev != cell;
+  r.heads = __ballot(r.head);
+  const unsigned long long after = lane == 63 ? 0ull : (r.heads >> (lane + 1));
+  r.len = after ? __ffsll((long long)after) : 64 - lane;
+  return r;
+}
+
+__device__ __forceinline__ int wave_rank(const RunInfo &r, int base) {
+  const int lane = (int)__lane_id();
+  const unsigned long long upto = lane == 63 ? r.heads : (r.heads & ((2ull << lane) - 1ull));
+  const int h = 63 - __clzll((long long)upto);
+  return __shfl(base, h, 64) + (lane - h);
+}
+
+// Cell of each of n particles and its rank among the particles of that
+// cell: the lanes of a wavefront that share a cell (consecutive, as the
+// particles arrive cell-sorted from the previous step) take their ranks with
+// one atomic per run of equal cells.  Ranks come in any order; the per-cell
+// sort orders the cells' runs by storage index afterwards.
 __global__ void k_bin(const KGeom G, int64_t cell_off, int64_t n, const float4 *__restrict__ pos4,
                       int32_t *__restrict__ cell_of, int32_t *__restrict__ rank_of,
                       int32_t *__restrict__ count) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  const float4 x = pos4[p];
-  int cx, cy, cz;
-  const int c = (int)cell_off + cell_index(G, x.x, x.y, x.z, cx, cy, cz);
-  cell_of[p] = c;
-  rank_of[p] = atomicAdd(&count[c], 1);
+  int c = -1;
+  if (p < n) {
+    const float4 x = pos4[p];
+    int cx, cy, cz;
+    c = (int)cell_off + cell_index(G, x.x, x.y, x.z, cx, cy, cz);
+    cell_of[p] = c;
+  }
+  const RunInfo r = wave_runs(c);
+  int base = r.len;
+  if (r.head && c >= 0) base = atomicAdd(&count[c], r.len);
+  const int k = wave_rank(r, base);
+  if (p < n) rank_of[p] = k;
 }
 
 __device__ __forceinline__ int block_exclusive_scan(int v, int *lds, int &total) {
@@ -652,31 +688,6 @@ __device__ __forceinline__ Moved integrate_one(const KGeom &G, const KParams &P,
   int cx, cy, cz;
   m.cell = cell_index(G, xs, ys, zs, cx, cy, cz);
   return m;
-}
-
-// Run structure of equal cells across a wavefront (cell < 0: inactive lane).
-struct RunInfo {
-  unsigned long long heads;
-  int len;     // run length, for head lanes
-  bool head;
-};
-
-__device__ __forceinline__ RunInfo wave_runs(int cell) {
-  const int lane = (int)__lane_id();
-  const int prev = __shfl_up(cell, 1, 64);
-  RunInfo r;
-  r.head = lane == 0 || prev != cell;
-  r.heads = __ballot(r.head);
-  const unsigned long long after = lane == 63 ? 0ull : (r.heads >> (lane + 1));
-  r.len = after ? __ffsll((long long)after) : 64 - lane;
-  return r;
-}
-
-__device__ __forceinline__ int wave_rank(const RunInfo &r, int base) {
-  const int lane = (int)__lane_id();
-  const unsigned long long upto = lane == 63 ? r.heads : (r.heads & ((2ull << lane) - 1ull));
-  const int h = 63 - __clzll((long long)upto);
-  return __shfl(base, h, 64) + (lane - h);
 }
 
 // Tile tid of up to PPT x kBlock particles of one box, by one block of

@@ -637,19 +637,12 @@ int wall_pass(dpd_ctx *c, hipStream_t s, int move) {
     const Replica &p = c->rep[r];
     if (p.nw == 0) continue;
     HIP_TRY(c, timed(c, s, K_OTHER, [&] {
-              if (move && p.moving)
-                return dpd::launch_wall_move(s, p.G, p.P.hdt, p.P.dt, p.nw, wp + p.wo, wv + p.wo,
-                                             c->wtmp + p.wo);
-              return dpd::launch_copy(s, c->wtmp + p.wo, wp + p.wo, 16 * (size_t)p.nw);
-            }));
-    HIP_TRY(c, timed(c, s, K_OTHER, [&] {
-              return dpd::launch_bin(s, p.G, p.co, p.nw, c->wtmp + p.wo, c->wcell_tmp + p.wo,
-                                     c->wrank + p.wo, c->wcount);
+              return dpd::launch_wall_move_bin(s, p.G, p.P.hdt, p.P.dt, move && p.moving ? 1 : 0,
+                                               p.co, p.nw, wp + p.wo, wv + p.wo, c->wtmp + p.wo,
+                                               c->wvtmp + p.wo, c->wcell_tmp + p.wo,
+                                               c->wrank + p.wo, c->wcount);
             }));
   }
-  HIP_TRY(c, timed(c, s, K_OTHER, [&] {
-            return dpd::launch_copy(s, c->wvtmp, wv, 16 * (size_t)c->NW);
-          }));
   HIP_TRY(c, timed(c, s, K_SCAN_REDUCE, [&] {
             return dpd::launch_scan_reduce(s, c->NCELL, c->wcount, c->bsum);
           }));
@@ -664,12 +657,10 @@ int wall_pass(dpd_ctx *c, hipStream_t s, int move) {
             return dpd::launch_sort_cells(s, c->NCELL, c->wcstart, c->idx, nullptr, nullptr,
                                           nullptr);
           }));
+  // the sorted walls into both position buffers at once
   HIP_TRY(c, timed(c, s, K_OTHER, [&] {
-            return dpd::launch_permute(s, c->NW, c->idx, c->wtmp, wp, c->wvtmp, wv, nullptr,
-                                       nullptr);
-          }));
-  HIP_TRY(c, timed(c, s, K_OTHER, [&] {
-            return dpd::launch_copy(s, c->pos[b] + c->NF, wp, 16 * (size_t)c->NW);
+            return dpd::launch_permute(s, c->NW, c->idx, c->wtmp, wp, c->wvtmp, wv, c->wtmp,
+                                       c->pos[b] + c->NF);
           }));
   for (int r = 0; r < c->R; ++r) {
     const Replica &p = c->rep[r];

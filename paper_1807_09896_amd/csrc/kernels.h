@@ -142,10 +142,13 @@ hipError_t launch_integrate(hipStream_t s, int ppt, const Box *boxes, const Tile
                             const uint32_t *bits, int use_mask, const void *quad, int grid_f64,
                             Status *st, int64_t NF, const int32_t *wcstart, int reflect);
 
-// Walls of a moving solid advanced by dt v (decision-form drift, zero force)
-// from walls_in/vt_in into walls_out.
-hipError_t launch_wall_move(hipStream_t s, const KGeom &G, float hdt, float dt, int64_t nw,
-                            const float4 *walls_in, const float4 *vt_in, float4 *walls_out);
+// Walls of one box from walls_in/vt_in into walls_out/vt_out, advanced by
+// dt v (decision-form drift, zero force) when move is set, and binned into
+// cells of offset cell_off (cell_of, rank_of, count as launch_bin).
+hipError_t launch_wall_move_bin(hipStream_t s, const KGeom &G, float hdt, float dt, int move,
+                                int64_t cell_off, int64_t nw, const float4 *walls_in,
+                                const float4 *vt_in, float4 *walls_out, float4 *vt_out,
+                                int32_t *cell_of, int32_t *rank_of, int32_t *count);
 
 // Wall positions replaced from gid-ordered float32 rows (device memory).
 hipError_t launch_import_walls(hipStream_t s, int64_t nw, float4 *walls, const float *pos);

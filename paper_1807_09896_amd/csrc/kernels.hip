@@ -144,11 +144,20 @@ __device__ __forceinline__ int wave_rank(const RunInfo &r, int base) {
   return __shfl(base, h, 64) + (lane - h);
 }
 
-// Cell of each of n particles and its rank among the particles of that
-// cell: the lanes of a wavefront that share a cell (consecutive, as the
-// particles arrive cell-sorted from the previous step) take their ranks with
-// one atomic per run of equal cells.  Ranks come in any order; the per-cell
-// sort orders the cells' runs by storage index afterwards.
+// Rank of a lane's particle among the particles of its cell c (c < 0: none,
+// the result unused), called by every lane of the wavefront: the lanes that
+// share a cell (consecutive, as the particles arrive cell-sorted from the
+// previous step) take their ranks with one atomic per run of equal cells.
+// Ranks come in any order; the per-cell sort orders the cells' runs by
+// storage index afterwards.
+__device__ __forceinline__ int rank_in_cell(int c, int32_t *__restrict__ count) {
+  const RunInfo r = wave_runs(c);
+  int base = r.len;
+  if (r.head && c >= 0) base = atomicAdd(&count[c], r.len);
+  return wave_rank(r, base);
+}
+
+// Cell of each of n particles and its rank in that cell.
 __global__ void k_bin(const KGeom G, int64_t cell_off, int64_t n, const float4 *__restrict__ pos4,
                       int32_t *__restrict__ cell_of, int32_t *__restrict__ rank_of,
                       int32_t *__restrict__ count) {
@@ -160,10 +169,7 @@ __global__ void k_bin(const KGeom G, int64_t cell_off, int64_t n, const float4 *
     c = (int)cell_off + cell_index(G, x.x, x.y, x.z, cx, cy, cz);
     cell_of[p] = c;
   }
-  const RunInfo r = wave_runs(c);
-  int base = r.len;
-  if (r.head && c >= 0) base = atomicAdd(&count[c], r.len);
-  const int k = wave_rank(r, base);
+  const int k = rank_in_cell(c, count);
   if (p < n) rank_of[p] = k;
 }
 
@@ -778,18 +784,31 @@ __global__ __launch_bounds__(kBlock) void k_integrate(
                                   bits_base, use_mask, quad_base, st, NF, wcstart);
 }
 
-// Walls of a box whose solid moves translate with it: x += dt v per axis in
-// the decision form of the fluid drift with zero force, then the single-edge
-// wrap.  Reads walls_in, writes the moved copy to walls_out.
-__global__ void k_wall_move(const KGeom G, float hdt, float dt, int64_t nw,
-                            const float4 *__restrict__ walls_in, const float4 *__restrict__ vt_in,
-                            float4 *__restrict__ walls_out) {
+// Walls of one box re-binned: each is advanced by dt v with move (its solid
+// translates: x += dt v per axis in the decision form of the fluid drift
+// with zero force, then the single-edge wrap) or kept, written to walls_out
+// with its velocity to vt_out, and binned (cell and rank in cell, as k_bin).
+__global__ void k_wall_move_bin(const KGeom G, float hdt, float dt, int move, int64_t cell_off,
+                                int64_t nw, const float4 *__restrict__ walls_in,
+                                const float4 *__restrict__ vt_in, float4 *__restrict__ walls_out,
+                                float4 *__restrict__ vt_out, int32_t *__restrict__ cell_of,
+                                int32_t *__restrict__ rank_of, int32_t *__restrict__ count) {
   const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (w >= nw) return;
-  const float4 x = walls_in[w], v = vt_in[w];
-  walls_out[w] = make_float4(drift1(x.x, v.x, 0.f, hdt, dt, G.L[0]),
-                             drift1(x.y, v.y, 0.f, hdt, dt, G.L[1]),
-                             drift1(x.z, v.z, 0.f, hdt, dt, G.L[2]), x.w);
+  int c = -1;
+  if (w < nw) {
+    float4 x = walls_in[w];
+    const float4 v = vt_in[w];
+    if (move)
+      x = make_float4(drift1(x.x, v.x, 0.f, hdt, dt, G.L[0]), drift1(x.y, v.y, 0.f, hdt, dt, G.L[1]),
+                      drift1(x.z, v.z, 0.f, hdt, dt, G.L[2]), x.w);
+    walls_out[w] = x;
+    vt_out[w] = v;
+    int cx, cy, cz;
+    c = (int)cell_off + cell_index(G, x.x, x.y, x.z, cx, cy, cz);
+    cell_of[w] = c;
+  }
+  const int k = rank_in_cell(c, count);
+  if (w < nw) rank_of[w] = k;
 }
 
 // Wall positions from gid-ordered rows (gid in pos4[w].w).
@@ -1488,10 +1507,13 @@ hipError_t launch_sort_cells(hipStream_t s, int64_t ncell, const int32_t *start,
   return hipGetLastError();
 }
 
-hipError_t launch_wall_move(hipStream_t s, const KGeom &G, float hdt, float dt, int64_t nw,
-                            const float4 *walls_in, const float4 *vt_in, float4 *walls_out) {
+hipError_t launch_wall_move_bin(hipStream_t s, const KGeom &G, float hdt, float dt, int move,
+                                int64_t cell_off, int64_t nw, const float4 *walls_in,
+                                const float4 *vt_in, float4 *walls_out, float4 *vt_out,
+                                int32_t *cell_of, int32_t *rank_of, int32_t *count) {
   if (nw <= 0) return hipSuccess;
-  k_wall_move<<<grid_for(nw), kBlock, 0, s>>>(G, hdt, dt, nw, walls_in, vt_in, walls_out);
+  k_wall_move_bin<<<grid_for(nw), kBlock, 0, s>>>(G, hdt, dt, move, cell_off, nw, walls_in, vt_in,
+                                                  walls_out, vt_out, cell_of, rank_of, count);
   return hipGetLastError();
 }
 

@@ -114,7 +114,7 @@ struct dpd_ctx {
           *idx = nullptr, *bsum = nullptr;
   int nscan = 0;
   int32_t *wcstart = nullptr;   // exclusive scan of wall counts per cell (static)
-  int32_t *wcell = nullptr;     // global cell of each cell-sorted wall (static)
+  int32_t *wcell = nullptr;     // global cell of each cell-sorted wall (rebuilt by the wall pass)
   int32_t *idx_all = nullptr;   // merged per-cell runs: walls (NF + w), then fluid
   uint32_t *cq = nullptr;       // coarse position codes of the merged runs
   // moving walls: re-sorted by cell every step (moved copy, velocities,
@@ -653,22 +653,15 @@ int wall_pass(dpd_ctx *c, hipStream_t s, int move) {
   HIP_TRY(c, timed(c, s, K_SCATTER, [&] {
             return dpd::launch_scatter(s, c->NW, c->wcell_tmp, c->wrank, c->wcstart, c->idx);
           }));
+  // per-cell sort, rebuilding wcell (the cell of each sorted wall) on the way
   HIP_TRY(c, timed(c, s, K_SORT, [&] {
-            return dpd::launch_sort_cells(s, c->NCELL, c->wcstart, c->idx, nullptr, nullptr,
-                                          nullptr);
+            return dpd::launch_sort_wall_cells(s, c->NCELL, c->wcstart, c->idx, c->wcell);
           }));
   // the sorted walls into both position buffers at once
   HIP_TRY(c, timed(c, s, K_OTHER, [&] {
             return dpd::launch_permute(s, c->NW, c->idx, c->wtmp, wp, c->wvtmp, wv, c->wtmp,
                                        c->pos[b] + c->NF);
           }));
-  for (int r = 0; r < c->R; ++r) {
-    const Replica &p = c->rep[r];
-    if (p.nw == 0) continue;
-    HIP_TRY(c, timed(c, s, K_OTHER, [&] {
-              return dpd::launch_cells(s, p.G, p.co, p.nw, wp + p.wo, c->wcell + p.wo);
-            }));
-  }
   return DPD_OK;
 }
 

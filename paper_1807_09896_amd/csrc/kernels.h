@@ -50,6 +50,10 @@ hipError_t launch_scatter(hipStream_t s, int64_t n, const int32_t *cell_of,
                           int32_t *idx_all = nullptr, unsigned long long *dk = nullptr);
 hipError_t launch_sort_cells(hipStream_t s, int64_t ncell, const int32_t *start, int32_t *idx,
                              const float4 *key4, const int32_t *fluid_off, int32_t *idx_all);
+// The walls' per-cell sort by storage index, writing also the global cell of
+// every sorted wall position to cell_out.
+hipError_t launch_sort_wall_cells(hipStream_t s, int64_t ncell, const int32_t *start,
+                                  int32_t *idx, int32_t *cell_out);
 // Coarse position codes of the merged runs, cq[t] from pos4[idx_all[t]] for
 // t < n (one word per entry), which the pair kernel's candidate pre-test
 // reads; n = NF + NW, after the scatter and sort.

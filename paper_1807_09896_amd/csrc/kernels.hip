@@ -413,6 +413,18 @@ __global__ void k_sort_cells(int64_t ncell, const int32_t *__restrict__ start,
   sort_cell<BY_GID>(c, start, idx, key4, fluid_off, idx_all);
 }
 
+// The walls' per-cell sort (by storage index, as sort_cell), which also
+// writes the cell of every sorted position: cell_out[i] = c for i in
+// [start[c], start[c + 1]).
+__global__ void k_sort_wall_cells(int64_t ncell, const int32_t *__restrict__ start,
+                                  int32_t *__restrict__ idx, int32_t *__restrict__ cell_out) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  sort_cell<false>(c, start, idx, nullptr, nullptr, nullptr);
+  const int a = start[c], b = start[c + 1];
+  for (int i = a; i < b; ++i) cell_out[i] = (int32_t)c;
+}
+
 // Coarse codes of the merged runs, cq[t] = qcode3(pos4[idx_all[t]]): one
 // thread per entry, so that the index reads and code writes coalesce.
 __global__ void k_quant_runs(int64_t n, const int32_t *__restrict__ idx_all,
@@ -1504,6 +1516,12 @@ hipError_t launch_sort_cells(hipStream_t s, int64_t ncell, const int32_t *start,
   else
     k_sort_cells<false><<<grid_for(ncell), kBlock, 0, s>>>(ncell, start, idx, key4, fluid_off,
                                                          idx_all);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort_wall_cells(hipStream_t s, int64_t ncell, const int32_t *start,
+                                  int32_t *idx, int32_t *cell_out) {
+  k_sort_wall_cells<<<grid_for(ncell), kBlock, 0, s>>>(ncell, start, idx, cell_out);
   return hipGetLastError();
 }
 

@@ -640,7 +640,9 @@ def reap_children():
     psutil.wait_procs(kids, timeout=5)
 
 
-def kernel_source_hash(files=("device.h", "kernels.hip")):
+def kernel_source_hash(files=("device.h", "kernels.hip", "api.hip")):
+    """Hash of the sources that decide a stored traffic record: the step's
+    kernels and the host code that launches them (tile tables and order)."""
     import hashlib
     h = hashlib.sha256()
     for f in files:

@@ -84,6 +84,26 @@ def test_batch_box_equals_box_alone(dpd):
     batch.close()
 
 
+def test_wide_box_tile_order_keeps_bits(dpd):
+    """A box more than 56 cell rows wide in y takes its pair-kernel tiles in
+    y-bands when it is its context's only box, and in plain order inside a
+    batch; the order must not change a bit of the results."""
+    wide = workloads.slab_system(L=(16.0, 64.0, 6.0), grid_dtype=np.float32, seed_fluid=61,
+                                 seed_wall=62)
+    bulk = workloads.bulk_system(L=(5.0, 4.0, 3.0),
+                                 params=workloads.default_params(seed=8, replica=9))
+    say("wide slab", wide.n, "particles")
+    alone = dpd.Simulation(wide)
+    batch = dpd.Simulation([wide, bulk])
+    alone.step(20)
+    batch.step(20)
+    _assert_same(_snap(batch, 0), _snap(alone, 0), "20 steps")
+    assert np.array_equal(sorted_pairs(batch.pairs(0)), sorted_pairs(alone.pairs()))
+    assert alone.counters()["unstable"] == 0
+    alone.close()
+    batch.close()
+
+
 def test_replica_id_enters_random_numbers(dpd):
     s = workloads.tiny_slab_system()
     s0 = workloads.tiny_slab_system()

@@ -286,13 +286,18 @@ int dpd_use_graph(dpd_ctx *ctx, int32_t enable);
  * for the items of the previous phase of box r through per-box arrival
  * counters (each wait bounded; a wait that reaches its bound is reported as
  * DPD_E_DEVICE at the next synchronising call).  Results are bit-identical to
- * the per-phase launches, and it combines with dpd_use_graph.  DPD_E_INVAL
- * for contexts with moving walls or boxes on the LDS-staged brick pair kernel;
- * enable = 0 returns to the per-phase launches. */
+ * the per-phase launches, and it combines with dpd_use_graph.  The
+ * persistent launch integrates at most 2 particles per thread, so a context
+ * at 4 is set to 2 (see dpd_autotune).  DPD_E_INVAL for
+ * contexts with moving walls or boxes on the LDS-staged brick pair kernel;
+ * enable = 0 returns to the per-phase launches and keeps the shapes. */
 int dpd_use_persistent(dpd_ctx *ctx, int32_t enable);
 
-/* Choose the launch shapes of the integrate kernel (particles per thread,
- * 1 or 2) and of the pair-force kernel (work-group size, 128 or 256) by
+/* Choose the launch shapes of the integrate kernel (particles per thread:
+ * P or 1, with P the context's default, 4 for contexts of at least 2^20
+ * fluid particles without moving walls or specular reflection and 2
+ * otherwise, and 2 under dpd_use_persistent) and of the pair-force kernel
+ * (work-group size, 128 or 256; default 256) by
  * timing `steps` steps of each of the four combinations from the current
  * state: one untimed round of all four, then two timed rounds in opposite
  * orders, each combination keeping its faster time (the first trials of a
@@ -303,7 +308,7 @@ int dpd_use_persistent(dpd_ctx *ctx, int32_t enable);
  * choice recorded there for the same device and sizes is used without trials
  * and new choices are appended.  shape_out (host int32[2], may be NULL)
  * receives {particles per thread, work-group size}; ms_out (host double[4],
- * may be NULL) the ms per step of {2/256, 1/256, 2/128, 1/128}, -1 when not
+ * may be NULL) the ms per step of {P/256, 1/256, P/128, 1/128}, -1 when not
  * timed.  Synchronises. */
 int dpd_autotune(dpd_ctx *ctx, int32_t steps, int32_t *shape_out, double *ms_out);
 

@@ -390,7 +390,19 @@ int build_tiles(dpd_ctx *c, int size, Tile **dst, int *n, int *cap, bool without
 
 int build_persistent(dpd_ctx *c);
 
+// The context's wider integrate shape, its default: 4 particles per thread
+// (86 VGPRs, five wavefronts per SIMD, four particles' loads in flight per
+// lane) for contexts of at least 2^20 fluid particles whose boxes all use
+// the plain instance; 2 otherwise.  The instance with moving walls and
+// specular reflection needs 118 VGPRs at 4 (Couette channel: integrate 0.051
+// -> 0.073 ms), and small contexts need the blocks that 2 gives them.
+int wide_ppt(const dpd_ctx *c) { return !c->reflect && c->NF >= ((int64_t)1 << 20) ? 4 : 2; }
+
+// Launch shapes: particles per thread of integrate (1, 2 or 4; at most 2
+// under the persistent step, whose kernel holds every phase at six
+// wavefronts per SIMD) and the pair kernel's work-group size.
 int set_shapes(dpd_ctx *c, int ppt, int fblock) {
+  if (c->persistent && ppt > 2) ppt = 2;
   c->ppt = ppt;
   c->fblock = fblock;
   drop_graphs(c);
@@ -1234,7 +1246,7 @@ int create_impl(int32_t nbox, const dpd_box *boxes, const dpd_particles *parts,
     if (rc) return bail(rc);
   }
   rc = build_bricks(c);
-  if (!rc) rc = set_shapes(c, 2, 256);
+  if (!rc) rc = set_shapes(c, wide_ppt(c), 256);
   if (rc) return bail(rc);
   c->cur = 0;
   c->k = 0;
@@ -1597,7 +1609,7 @@ int dpd_use_persistent(dpd_ctx *c, int32_t enable) {
   if (c->moving) return fail(c, DPD_E_INVAL, "the persistent step does not move walls");
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->persistent = true;
-  int rc = build_persistent(c);
+  int rc = c->ppt > 2 ? set_shapes(c, 2, c->fblock) : build_persistent(c);
   if (rc) {
     c->persistent = false;
     return rc;
@@ -1776,7 +1788,8 @@ int dpd_kernel_times(dpd_ctx *c, int32_t enable, double *out_ms, int64_t *out_la
 int dpd_autotune(dpd_ctx *c, int32_t steps, int32_t *shape_out, double *ms_out) {
   if (!c) return DPD_E_INVAL;
   if (steps < 1) return fail(c, DPD_E_INVAL, "autotune needs at least one step per trial");
-  const int shapes[4][2] = {{2, 256}, {1, 256}, {2, 128}, {1, 128}};
+  const int P = c->persistent ? 2 : wide_ppt(c);
+  const int shapes[4][2] = {{P, 256}, {1, 256}, {P, 128}, {1, 128}};
   const std::string sig = tune_signature(c);
   const char *cache = std::getenv("DPD_TUNE_CACHE");
   int best = -1;

@@ -134,7 +134,7 @@ hipError_t launch_build_quad(hipStream_t s, const KGeom &G, const void *grid, in
                              void *quad);
 
 // Fused drift + predicted velocity + phi test + reflection + binning, over
-// tiles of up to ppt x 256 particles (ppt 1 or 2); quad is the base of the
+// tiles of up to ppt x 256 particles (ppt 1, 2 or 4); quad is the base of the
 // concatenated phase fields in the face layout, bits of the concatenated
 // cube masks.  reflect = 1
 // (some box has moving walls or specular reflection) runs the instance with

@@ -1636,10 +1636,15 @@ hipError_t launch_integrate(hipStream_t s, int ppt, const Box *boxes, const Tile
                                              wcstart)
 #define DPD_INTEGRATE_T(T, K) \
   if (reflect) DPD_INTEGRATE(T, K, true); else DPD_INTEGRATE(T, K, false)
+  if (ppt != 1 && ppt != 2 && ppt != 4) return hipErrorInvalidValue;
   if (grid_f64) {
-    if (ppt == 1) { DPD_INTEGRATE_T(double, 1); } else { DPD_INTEGRATE_T(double, 2); }
+    if (ppt == 1) { DPD_INTEGRATE_T(double, 1); }
+    else if (ppt == 2) { DPD_INTEGRATE_T(double, 2); }
+    else { DPD_INTEGRATE_T(double, 4); }
   } else {
-    if (ppt == 1) { DPD_INTEGRATE_T(float, 1); } else { DPD_INTEGRATE_T(float, 2); }
+    if (ppt == 1) { DPD_INTEGRATE_T(float, 1); }
+    else if (ppt == 2) { DPD_INTEGRATE_T(float, 2); }
+    else { DPD_INTEGRATE_T(float, 4); }
   }
 #undef DPD_INTEGRATE_T
 #undef DPD_INTEGRATE
